@@ -1,0 +1,279 @@
+/*
+ * tk.h -- C-ABI of the symmetric-TensorMap contraction library (gfx950).
+ *
+ * A TensorMap  t : W_1 (x) .. (x) W_N2 -> V_1 (x) .. (x) V_N1  over graded
+ * spaces of an abelian symmetry is stored as one dense column-major matrix
+ * per coupled charge c (the block-diagonal matrix form of the abelian
+ * grouping isomorphism, eq. abeliangrouping).  The library implements
+ *   - tk_tensor_permute : Alg. "Abelian Tensor Permutation" (with the
+ *                         fermionic exchange sign for U(1) x fZ2 / fZ2),
+ *   - tk_tensor_contract: Alg. "Abelian tensor contraction" (permute A,
+ *                         permute B, one GEMM per coupled charge, zero block
+ *                         for an empty K range, permute C fused into the
+ *                         GEMM epilogue),
+ *   - tk_tensor_adjoint : blockwise Hermitian conjugate (section "Adjoint").
+ * All numerical work runs in hand-written HIP kernels on the device; the host
+ * side only plans (block structure, index maps, signs, schedules).
+ *
+ * Conventions
+ * -----------
+ * Legs are 0-based (the paper counts from 1) and numbered codomain first,
+ * then domain: legs 0..N1-1 are V_1..V_N1, legs N1..N1+N2-1 are W_1..W_N2.
+ * A permutation (p, q) takes the p_i-th space of (V_1.., W_1*..) into the
+ * new codomain and the q_j-th space of (V_1*.., W_1..) into the new domain
+ * (Alg. "Tensor Permute"): a leg that crosses between codomain and domain
+ * has its space dualised.
+ *
+ * Spaces.  tk_space lists the sectors of the underlying space and a dual
+ * flag.  `charges` holds nsect * ncomp int32 values, ncomp = 0 for Z1,
+ * 1 for Z2 / FZ2 (parity 0 or 1) and U1 (charge), 2 for U1xFZ2 (charge,
+ * parity).  A leg on a dual space carries the conjugate charge (-q, same
+ * parity) for block keys and charge conservation.  Sectors of one space must
+ * be distinct; degeneracies must be >= 1.
+ *
+ * Storage layout (the "arbitrary but fixed" channel order of the grouping
+ * isomorphism, fixed here): coupled charges that occur on both sides are
+ * stored in ascending (charge, parity) order, each as an R_c x C_c
+ * column-major matrix; rows are the codomain channels (tuples of sector
+ * indices) enumerated with the first leg fastest, columns the domain
+ * channels likewise; inside a channel block the entries follow
+ * eq. linearindex (first index fastest).  tk_tensor_blocks reports every
+ * channel with its offset so callers never need to recompute this.
+ *
+ * Fermions (FZ2, U1xFZ2) follow the graph convention of the section
+ * "Fermions and fusion categories" (twist pushed into the right
+ * evaluation): a TensorMap is read as a tensor in
+ * V_1..V_N1 (x) W*_N2..W*_1 with unchanged coefficients; a permute
+ * multiplies a channel by (-1)^{|x||y|} for every pair of legs whose order
+ * in that reading is exchanged (R^{JJ}_I = -1); a composition multiplies by
+ * (-1)^{|k|} for every contracted leg whose space in the codomain of the
+ * right operand is a dual space.
+ *
+ * Ownership.  All handles are opaque and destroyed by the caller.  A tensor
+ * either owns device memory allocated by the library (device_buf == NULL) or
+ * wraps caller memory (e.g. a torch tensor's data_ptr) that must outlive the
+ * handle and is never freed by the library.  Plans and batches own their
+ * device tables and workspaces, all allocated when they are created, so
+ * their launches allocate nothing and can be captured in a HIP graph.
+ *
+ * Asynchrony.  Device work is enqueued on the hipStream_t passed as
+ * `stream` (NULL = the null stream) and is not synchronised; the caller
+ * orders it.  Host-side planning is thread safe; a plan or batch must not be
+ * executed concurrently with itself.
+ *
+ * Errors.  Every call returns a tk_status; on error the out-parameters are
+ * untouched and tk_last_error() returns a thread-local message.  No C++
+ * exception crosses this interface.
+ */
+#ifndef TK_H
+#define TK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tk_status;
+#define TK_OK 0
+#define TK_ERR_INVALID_ARG 1    /* bad pointer, size, index list or permutation */
+#define TK_ERR_SPACE_MISMATCH 2 /* domain(A~) != codomain(B~), or C's spaces wrong */
+#define TK_ERR_CHARGE 3         /* sector invalid for the symmetry / repeated */
+#define TK_ERR_DTYPE 4          /* dtype or precision combination not allowed */
+#define TK_ERR_UNSUPPORTED 5    /* beyond a documented limit (rank, sectors) */
+#define TK_ERR_OOM 6            /* device or host allocation failed */
+#define TK_ERR_HIP 7            /* a HIP runtime call or kernel launch failed */
+
+typedef enum tk_symmetry {
+  TK_SYM_Z1 = 0,     /* no symmetry: one trivial sector per space */
+  TK_SYM_Z2 = 1,     /* bosonic Z2 */
+  TK_SYM_FZ2 = 2,    /* fermion parity (SVect) */
+  TK_SYM_U1 = 3,     /* U(1) */
+  TK_SYM_U1_FZ2 = 4  /* U(1) x fZ2 (Deligne product) */
+} tk_symmetry;
+
+typedef enum tk_dtype { TK_F64 = 0, TK_F32 = 1 } tk_dtype;
+
+typedef enum tk_precision {
+  TK_PREC_NATIVE = 0, /* fp64 MFMA for fp64 tensors, fp32 MFMA for fp32 tensors */
+  TK_PREC_F32 = 1,    /* operands rounded to fp32, fp32 MFMA, fp32 accumulation */
+  TK_PREC_BF16X3 = 2  /* a = hi + lo (two bf16), hi*hi + hi*lo + lo*hi, fp32 accumulation */
+} tk_precision;
+
+typedef struct tk_space {
+  int32_t nsect;               /* number of sectors, >= 1 */
+  const int32_t* charges;      /* nsect * ncomp values (may be NULL when ncomp == 0) */
+  const int64_t* degeneracies; /* nsect values, each >= 1 */
+  int32_t isdual;              /* 0: V, 1: V* */
+} tk_space;
+
+/* Limits: at most TK_MAX_LEGS legs per side and TK_MAX_RANK in total; at
+ * most 255 sectors per space. */
+#define TK_MAX_LEGS 8
+#define TK_MAX_RANK 8
+
+typedef struct tk_context tk_context;
+typedef struct tk_tensor tk_tensor;
+typedef struct tk_plan tk_plan;
+typedef struct tk_batch tk_batch;
+
+/* ---- context ------------------------------------------------------------
+ * A context binds a HIP device and owns the plan cache used by
+ * tk_tensor_permute / tk_tensor_contract.  tk_context_create makes `device`
+ * current on the calling thread. */
+tk_status tk_context_create(int32_t device, tk_context** out);
+tk_status tk_context_destroy(tk_context* ctx);
+
+/* ---- tensors --------------------------------------------------------------
+ * Creates a TensorMap  dom[0] (x)..(x) dom[ndom-1] -> cod[0] (x)..(x) cod[ncod-1].
+ * ctx == NULL creates a structure-only handle (no data; usable for queries
+ * and planning, not for execution; device_buf must then be NULL).
+ * device_buf == NULL: the library allocates (uninitialised) device memory.
+ * Otherwise device_buf must hold at least nelem * sizeof(dtype) bytes
+ * (buf_bytes) and stay valid while the handle lives. */
+tk_status tk_tensor_create(tk_context* ctx, int32_t sym, int32_t dtype, const tk_space* cod,
+                           int32_t ncod, const tk_space* dom, int32_t ndom, void* device_buf,
+                           uint64_t buf_bytes, tk_tensor** out);
+tk_status tk_tensor_destroy(tk_tensor* t);
+
+/* Number of codomain/domain legs, stored elements, fusion channels and
+ * coupled charges (any out-pointer may be NULL). */
+tk_status tk_tensor_info(const tk_tensor* t, int32_t* sym, int32_t* dtype, int32_t* ncod,
+                         int32_t* ndom, int64_t* nelem, int64_t* nblocks, int64_t* nsectors);
+
+/* Channels first..first+count-1 in storage order (coupled charge ascending,
+ * then domain channel, then codomain channel).  sector_idx receives
+ * count * (ncod + ndom) sector indices (position of each leg's sector in its
+ * space's list), offsets the element offset of the block's first entry,
+ * ld the leading dimension R_c of its coupled-charge matrix.  Any output
+ * pointer may be NULL. */
+tk_status tk_tensor_blocks(const tk_tensor* t, int64_t first, int64_t count, int32_t* sector_idx,
+                           int64_t* offsets, int64_t* ld);
+
+/* Coupled charges first..first+count-1: charges (count * ncomp), rows R_c,
+ * cols C_c and element offset of each matrix. */
+tk_status tk_tensor_sectors(const tk_tensor* t, int64_t first, int64_t count, int32_t* charges,
+                            int64_t* rows, int64_t* cols, int64_t* offsets);
+
+/* Space of leg `leg` (0-based over codomain then domain).  The returned
+ * arrays are owned by the tensor and valid while it lives. */
+tk_status tk_tensor_space(const tk_tensor* t, int32_t leg, tk_space* out);
+
+/* Device pointer and size in bytes of the tensor's storage. */
+tk_status tk_tensor_data(const tk_tensor* t, void** device_ptr, uint64_t* bytes);
+
+/* ---- spaces of results -----------------------------------------------------
+ * Create the (data-holding if ctx != NULL) tensor that tk_tensor_permute,
+ * tk_tensor_contract or tk_tensor_adjoint write, with the spaces the
+ * algorithms assign.  Buffer arguments as for tk_tensor_create. */
+tk_status tk_tensor_create_permuted(tk_context* ctx, const tk_tensor* A, const int32_t* p,
+                                    int32_t np, const int32_t* q, int32_t nq, void* device_buf,
+                                    uint64_t buf_bytes, tk_tensor** out);
+tk_status tk_tensor_create_contracted(tk_context* ctx, const tk_tensor* A, const int32_t* pA,
+                                      int32_t npA, const int32_t* qA, int32_t nqA,
+                                      const tk_tensor* B, const int32_t* pB, int32_t npB,
+                                      const int32_t* qB, int32_t nqB, const int32_t* pAB,
+                                      int32_t npAB, const int32_t* qAB, int32_t nqAB,
+                                      void* device_buf, uint64_t buf_bytes, tk_tensor** out);
+tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* device_buf,
+                                   uint64_t buf_bytes, tk_tensor** out);
+
+/* ---- operations ------------------------------------------------------------
+ * C = permute(A, (p, q)).  C must have the permuted spaces and A's dtype. */
+tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                            const int32_t* q, int32_t nq, tk_tensor* C, void* stream);
+
+/* C = alpha * permute(permute(A,(pA,qA)) o permute(B,(pB,qB)), (pAB,qAB)) + beta * C.
+ * (pA, qA): free legs of A (codomain of A~) and contracted legs (domain of
+ * A~); (pB, qB): contracted legs of B in the same order as qA (codomain of
+ * B~) and free legs (domain of B~); (pAB, qAB) index the legs of
+ * C~ = A~ o B~, numbered pA-legs then qB-legs.  Requires
+ * domain(A~) == codomain(B~) as spaces (sectors, degeneracies, dual flags).
+ * A coupled charge of C~ whose K range is empty yields zeros (times alpha).
+ * beta == 0 never reads C.  A, B and C must not alias. */
+tk_status tk_tensor_contract(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
+                             const int32_t* qA, int32_t nqA, const tk_tensor* B,
+                             const int32_t* pB, int32_t npB, const int32_t* qB, int32_t nqB,
+                             const int32_t* pAB, int32_t npAB, const int32_t* qAB, int32_t nqAB,
+                             double alpha, double beta, int32_t precision, tk_tensor* C,
+                             void* stream);
+
+/* C = A^dagger: codomain and domain exchange, every coupled-charge matrix is
+ * transposed (conjugation is the identity on real data). */
+tk_status tk_tensor_adjoint(tk_context* ctx, const tk_tensor* A, tk_tensor* C, void* stream);
+
+/* ---- plans -----------------------------------------------------------------
+ * A plan fixes everything structural about one contraction (tensors may be
+ * structure-only) and owns its device tables and workspaces.  Executing it
+ * on data-holding tensors with the same structures enqueues: the operand
+ * permutes (one launch), the grouped sector GEMM with the output permute
+ * fused into its epilogue (one persistent launch), and zero blocks for empty
+ * K ranges. */
+tk_status tk_plan_contract(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
+                           const int32_t* qA, int32_t nqA, const tk_tensor* B, const int32_t* pB,
+                           int32_t npB, const int32_t* qB, int32_t nqB, const int32_t* pAB,
+                           int32_t npAB, const int32_t* qAB, int32_t nqAB, int32_t precision,
+                           const tk_tensor* C, tk_plan** out);
+tk_status tk_plan_execute(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C,
+                          double alpha, double beta, void* stream);
+tk_status tk_plan_destroy(tk_plan* plan);
+
+/* Enqueue only some stages of a plan, in the fixed order operand permutes
+ * (TK_STAGE_PERMUTE), grouped GEMM (TK_STAGE_GEMM), zero blocks
+ * (TK_STAGE_ZERO); executing all three equals tk_plan_execute.  Lets a
+ * caller bracket one stage with events (per-kernel timing). */
+#define TK_STAGE_PERMUTE 1
+#define TK_STAGE_GEMM 2
+#define TK_STAGE_ZERO 4
+#define TK_STAGE_ALL 7
+tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C,
+                                 double alpha, double beta, int32_t stages, void* stream);
+
+/* Plan statistics: number of sector GEMMs with K > 0, useful block flops
+ * (sum of 2 M N K), number of zero-filled coupled charges, workspace bytes,
+ * and the GEMM tile shape in use (any pointer may be NULL). */
+tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero,
+                       int64_t* workspace_bytes, int32_t* tile_m, int32_t* tile_n);
+/* (M, N, K) of sector GEMMs first..first+count-1 (3 * count values). */
+tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk);
+
+/* Channel map of a permute: for every channel i of A (storage order) the
+ * channel index of C it lands in and its sign (+1 / -1).  Host only. */
+tk_status tk_permute_map(const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,
+                         int32_t nq, const tk_tensor* C, int64_t* dst_block, int32_t* sign);
+
+/* ---- batches ---------------------------------------------------------------
+ * A batch binds n plans to their data-holding tensors and merges them: all
+ * operand permutes in one launch, every sector GEMM of every plan in one
+ * persistent grouped-GEMM launch (cost-sorted tiles), all zero blocks in one
+ * launch.  tk_batch_launch enqueues that sequence; tk_batch_capture records
+ * it once into a HIP graph which tk_batch_replay then launches. */
+tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tensor* const* A,
+                          const tk_tensor* const* B, tk_tensor* const* C, int32_t n,
+                          double alpha, double beta, tk_batch** out);
+tk_status tk_batch_launch(tk_batch* batch, void* stream);
+tk_status tk_batch_capture(tk_batch* batch, void* stream);
+tk_status tk_batch_replay(tk_batch* batch, void* stream);
+tk_status tk_batch_info(const tk_batch* batch, int64_t* ngemm, int64_t* ntiles, double* flops,
+                        int32_t* tile_m, int32_t* tile_n);
+tk_status tk_batch_destroy(tk_batch* batch);
+
+/* ---- tile shapes ----------------------------------------------------------
+ * GEMM tile shapes the grouped kernel supports: (tile_m, tile_n) pairs.
+ * tk_plan_set_tile / tk_batch_set_tile choose one (re-scheduling the tiles);
+ * the autotuner in the Python package times the candidates and persists the
+ * winner per shape class. */
+tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mn /* 2 * count, may be NULL */);
+tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n);
+tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n);
+
+/* ---- misc ------------------------------------------------------------------ */
+const char* tk_last_error(void);
+const char* tk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TK_H */

@@ -1,0 +1,1670 @@
+// Host side of the symmetric-TensorMap library: graded spaces, block
+// structure of TensorMaps, permute and contraction plans, tile scheduling,
+// plan cache and the C-ABI declared in include/tk.h.  Only planning happens
+// here; every numerical step runs in the kernels of tk_kernels.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <queue>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "tk.h"
+#include "tk_internal.h"
+
+using tk::GemmDesc;
+using tk::GemmTile;
+using tk::LegMap;
+using tk::PairDesc;
+using tk::PermTask;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct TkError {
+  tk_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(tk_status st, const std::string& msg) { throw TkError{st, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(TK_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// symmetries and spaces
+// ---------------------------------------------------------------------------
+struct SymInfo {
+  int ncomp;
+  bool has_q, has_p, fermionic;
+};
+
+SymInfo sym_info(int sym) {
+  switch (sym) {
+    case TK_SYM_Z1: return {0, false, false, false};
+    case TK_SYM_Z2: return {1, false, true, false};
+    case TK_SYM_FZ2: return {1, false, true, true};
+    case TK_SYM_U1: return {1, true, false, false};
+    case TK_SYM_U1_FZ2: return {2, true, true, true};
+    default: fail(TK_ERR_INVALID_ARG, "unknown symmetry " + std::to_string(sym));
+  }
+}
+
+// A graded space: sectors (U(1) charge q, parity p; unused components are 0),
+// degeneracies, dual flag.  The label of sector k on this leg is the sector
+// itself on a normal space and its conjugate (-q, p) on a dual space.
+struct Space {
+  std::vector<int32_t> q, p;
+  std::vector<int64_t> deg;
+  bool dual = false;
+  std::vector<int32_t> raw;  // charges as given (nsect * ncomp), for tk_tensor_space
+
+  int n() const { return static_cast<int>(deg.size()); }
+  int64_t lab_q(int k) const { return dual ? -static_cast<int64_t>(q[k]) : q[k]; }
+  Space flipped() const {
+    Space s = *this;
+    s.dual = !dual;
+    return s;
+  }
+  bool operator==(const Space& o) const { return q == o.q && p == o.p && deg == o.deg && dual == o.dual; }
+  bool operator!=(const Space& o) const { return !(*this == o); }
+};
+
+inline int64_t make_key(int64_t q, int p) { return 2 * q + p; }
+
+Space make_space(int sym, const tk_space& s) {
+  SymInfo si = sym_info(sym);
+  if (s.nsect < 1 || s.nsect > 255) fail(TK_ERR_UNSUPPORTED, "a space needs 1..255 sectors");
+  if (!s.degeneracies) fail(TK_ERR_INVALID_ARG, "null degeneracies");
+  if (si.ncomp > 0 && !s.charges) fail(TK_ERR_INVALID_ARG, "null charges");
+  if (sym == TK_SYM_Z1 && s.nsect != 1) fail(TK_ERR_CHARGE, "Z1 spaces have exactly one sector");
+  Space sp;
+  sp.dual = s.isdual != 0;
+  for (int k = 0; k < s.nsect; ++k) {
+    int32_t q = 0, p = 0;
+    if (sym == TK_SYM_Z2 || sym == TK_SYM_FZ2) p = s.charges[k];
+    if (sym == TK_SYM_U1) q = s.charges[k];
+    if (sym == TK_SYM_U1_FZ2) {
+      q = s.charges[2 * k];
+      p = s.charges[2 * k + 1];
+    }
+    if (si.has_p && (p < 0 || p > 1)) fail(TK_ERR_CHARGE, "parity must be 0 or 1");
+    if (si.has_q && (q < -(1 << 24) || q > (1 << 24))) fail(TK_ERR_CHARGE, "charge out of range");
+    if (s.degeneracies[k] < 1 || s.degeneracies[k] > (int64_t(1) << 31) - 1)
+      fail(TK_ERR_INVALID_ARG, "degeneracies must be in 1 .. 2^31-1");
+    for (int j = 0; j < k; ++j)
+      if (sp.q[j] == q && sp.p[j] == p) fail(TK_ERR_CHARGE, "repeated sector in a space");
+    sp.q.push_back(q);
+    sp.p.push_back(p);
+    sp.deg.push_back(s.degeneracies[k]);
+    for (int c = 0; c < si.ncomp; ++c) sp.raw.push_back(s.charges[si.ncomp * k + c]);
+  }
+  return sp;
+}
+
+// ---------------------------------------------------------------------------
+// block structure
+// ---------------------------------------------------------------------------
+// Channels of one side with one coupled label, in colexicographic order
+// (first leg fastest).  off is the row (column) offset inside t^(c).
+struct Group {
+  std::vector<uint8_t> idx;  // n * nlegs sector indices
+  std::vector<int64_t> size, off;
+  int64_t total = 0;
+  int32_t n() const { return static_cast<int32_t>(size.size()); }
+};
+
+struct Side {
+  int nlegs = 0;
+  std::map<int64_t, Group> groups;
+  mutable std::mutex mu;
+  mutable std::unordered_map<uint64_t, int32_t> lookup;  // packed tuple -> index in its group
+  mutable bool lookup_built = false;
+
+  static uint64_t pack(const uint8_t* t, int n) {
+    uint64_t k = 0;
+    for (int l = 0; l < n; ++l) k |= static_cast<uint64_t>(t[l]) << (8 * l);
+    return k;
+  }
+  int32_t find(const uint8_t* t) const {
+    std::lock_guard<std::mutex> g(mu);
+    if (!lookup_built) {
+      for (const auto& kv : groups) {
+        const Group& gr = kv.second;
+        for (int32_t i = 0; i < gr.n(); ++i) lookup[pack(&gr.idx[size_t(i) * nlegs], nlegs)] = i;
+      }
+      lookup_built = true;
+    }
+    auto it = lookup.find(pack(t, nlegs));
+    return it == lookup.end() ? -1 : it->second;
+  }
+};
+
+struct Structure {
+  int sym = 0;
+  SymInfo si{};
+  std::vector<Space> cod, dom;
+  Side rows, cols;
+  std::vector<int64_t> keys;  // coupled labels present on both sides, ascending
+  std::vector<const Group*> rg, cg;
+  std::vector<int64_t> R, C, soff, bbase;
+  int64_t size = 0, nblocks = 0;
+  std::string sig;
+
+  int N1() const { return static_cast<int>(cod.size()); }
+  int N2() const { return static_cast<int>(dom.size()); }
+  int N() const { return N1() + N2(); }
+  const Space& leg(int l) const { return l < N1() ? cod[l] : dom[l - N1()]; }
+  int sector_of_key(int64_t key) const {
+    auto it = std::lower_bound(keys.begin(), keys.end(), key);
+    return (it != keys.end() && *it == key) ? static_cast<int>(it - keys.begin()) : -1;
+  }
+  int64_t tuple_key(const std::vector<Space>& legs, const uint8_t* t) const {
+    int64_t q = 0;
+    int p = 0;
+    for (size_t l = 0; l < legs.size(); ++l) {
+      q += legs[l].lab_q(t[l]);
+      p ^= legs[l].p[t[l]];
+    }
+    return make_key(q, p);
+  }
+};
+
+void enumerate_side(const std::vector<Space>& legs, const std::vector<int64_t>* keep, Side& out) {
+  const int N = static_cast<int>(legs.size());
+  out.nlegs = N;
+  if (N == 0) {
+    if (!keep || std::binary_search(keep->begin(), keep->end(), make_key(0, 0))) {
+      Group g;
+      g.size = {1};
+      g.off = {0};
+      g.total = 1;
+      out.groups[make_key(0, 0)] = std::move(g);
+    }
+    return;
+  }
+  int64_t qmin = 0, qmax = 0;
+  for (const auto& s : legs) {
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (int k = 0; k < s.n(); ++k) {
+      lo = std::min(lo, s.lab_q(k));
+      hi = std::max(hi, s.lab_q(k));
+    }
+    qmin += lo;
+    qmax += hi;
+  }
+  const int64_t kmin = make_key(qmin, 0), nkeys = make_key(qmax, 1) - kmin + 1;
+  std::vector<Group> flat;
+  std::map<int64_t, Group> sparse;
+  const bool use_flat = nkeys <= (1 << 20);
+  if (use_flat) flat.resize(static_cast<size_t>(nkeys));
+  std::vector<char> keep_flat;
+  if (keep && use_flat) {
+    keep_flat.assign(static_cast<size_t>(nkeys), 0);
+    for (int64_t k : *keep)
+      if (k >= kmin && k < kmin + nkeys) keep_flat[static_cast<size_t>(k - kmin)] = 1;
+  }
+  // odometer over legs 1..N-1, inner loop over leg 0 (first leg fastest)
+  std::vector<int> cur(N, 0);
+  std::vector<uint8_t> tup(N, 0);
+  while (true) {
+    int64_t q = 0, sz = 1;
+    int p = 0;
+    for (int l = 1; l < N; ++l) {
+      q += legs[l].lab_q(cur[l]);
+      p ^= legs[l].p[cur[l]];
+      sz *= legs[l].deg[cur[l]];
+      tup[l] = static_cast<uint8_t>(cur[l]);
+    }
+    const Space& l0 = legs[0];
+    for (int k = 0; k < l0.n(); ++k) {
+      const int64_t key = make_key(q + l0.lab_q(k), p ^ l0.p[k]);
+      Group* g;
+      if (use_flat) {
+        if (keep && !keep_flat[static_cast<size_t>(key - kmin)]) continue;
+        g = &flat[static_cast<size_t>(key - kmin)];
+      } else {
+        if (keep && !std::binary_search(keep->begin(), keep->end(), key)) continue;
+        g = &sparse[key];
+      }
+      tup[0] = static_cast<uint8_t>(k);
+      const int64_t s = sz * l0.deg[k];
+      g->idx.insert(g->idx.end(), tup.begin(), tup.end());
+      g->off.push_back(g->total);
+      g->size.push_back(s);
+      g->total += s;
+    }
+    int l = 1;
+    while (l < N) {
+      if (++cur[l] < legs[l].n()) break;
+      cur[l] = 0;
+      ++l;
+    }
+    if (l >= N) break;
+  }
+  if (use_flat) {
+    for (int64_t i = 0; i < nkeys; ++i)
+      if (!flat[static_cast<size_t>(i)].size.empty()) out.groups[kmin + i] = std::move(flat[static_cast<size_t>(i)]);
+  } else {
+    out.groups = std::move(sparse);
+  }
+}
+
+std::string space_sig(const Space& s) {
+  std::string r = s.dual ? "D" : "N";
+  for (int k = 0; k < s.n(); ++k)
+    r += std::to_string(s.q[k]) + "," + std::to_string(s.p[k]) + ":" + std::to_string(s.deg[k]) + ";";
+  return r;
+}
+
+std::string structure_sig(int sym, const std::vector<Space>& cod, const std::vector<Space>& dom) {
+  std::string r = "S" + std::to_string(sym) + "|";
+  for (const auto& s : cod) r += space_sig(s) + "|";
+  r += "->|";
+  for (const auto& s : dom) r += space_sig(s) + "|";
+  return r;
+}
+
+std::shared_ptr<Structure> build_structure(int sym, const std::vector<Space>& cod, const std::vector<Space>& dom) {
+  if (cod.size() > TK_MAX_LEGS || dom.size() > TK_MAX_LEGS || cod.size() + dom.size() > TK_MAX_RANK)
+    fail(TK_ERR_UNSUPPORTED, "too many legs");
+  auto st = std::make_shared<Structure>();
+  st->sym = sym;
+  st->si = sym_info(sym);
+  st->cod = cod;
+  st->dom = dom;
+  st->sig = structure_sig(sym, cod, dom);
+  // enumerate the smaller side first and keep only its labels on the other
+  auto side_count = [](const std::vector<Space>& v) {
+    double c = 1;
+    for (const auto& s : v) c *= s.n();
+    return c;
+  };
+  std::vector<int64_t> keys;
+  if (side_count(dom) <= side_count(cod)) {
+    enumerate_side(dom, nullptr, st->cols);
+    for (const auto& kv : st->cols.groups) keys.push_back(kv.first);
+    enumerate_side(cod, &keys, st->rows);
+  } else {
+    enumerate_side(cod, nullptr, st->rows);
+    for (const auto& kv : st->rows.groups) keys.push_back(kv.first);
+    enumerate_side(dom, &keys, st->cols);
+  }
+  int64_t off = 0, nb = 0;
+  for (const auto& kv : st->rows.groups) {
+    auto it = st->cols.groups.find(kv.first);
+    if (it == st->cols.groups.end()) continue;
+    st->keys.push_back(kv.first);
+    st->rg.push_back(&kv.second);
+    st->cg.push_back(&it->second);
+    st->R.push_back(kv.second.total);
+    st->C.push_back(it->second.total);
+    st->soff.push_back(off);
+    st->bbase.push_back(nb);
+    off += kv.second.total * it->second.total;
+    nb += static_cast<int64_t>(kv.second.n()) * it->second.n();
+  }
+  st->size = off;
+  st->nblocks = nb;
+  return st;
+}
+
+std::mutex g_struct_mu;
+std::unordered_map<std::string, std::weak_ptr<Structure>> g_struct_cache;
+
+std::shared_ptr<Structure> get_structure(int sym, const std::vector<Space>& cod, const std::vector<Space>& dom) {
+  const std::string sig = structure_sig(sym, cod, dom);
+  {
+    std::lock_guard<std::mutex> g(g_struct_mu);
+    auto it = g_struct_cache.find(sig);
+    if (it != g_struct_cache.end())
+      if (auto sp = it->second.lock()) return sp;
+  }
+  auto st = build_structure(sym, cod, dom);
+  std::lock_guard<std::mutex> g(g_struct_mu);
+  g_struct_cache[sig] = st;
+  return st;
+}
+
+// Space assignment of Alg. "Tensor Permute": V'_i = p_i-th of (V.., W*..),
+// W'_j = q_j-th of (V*.., W..).
+void permute_spaces(const Structure& A, const std::vector<int>& p, const std::vector<int>& q,
+                    std::vector<Space>& cod, std::vector<Space>& dom) {
+  cod.clear();
+  dom.clear();
+  for (int i : p) cod.push_back(i < A.N1() ? A.leg(i) : A.leg(i).flipped());
+  for (int j : q) dom.push_back(j < A.N1() ? A.leg(j).flipped() : A.leg(j));
+}
+
+std::vector<int> to_vec(const int32_t* a, int32_t n, const char* what) {
+  if (n < 0 || (n > 0 && !a)) fail(TK_ERR_INVALID_ARG, std::string("bad index list ") + what);
+  return std::vector<int>(a, a + n);
+}
+
+void check_perm(const std::vector<int>& p, const std::vector<int>& q, int N) {
+  if (static_cast<int>(p.size() + q.size()) != N) fail(TK_ERR_INVALID_ARG, "(p, q) must list every leg once");
+  std::vector<char> seen(N, 0);
+  for (int v : p) {
+    if (v < 0 || v >= N || seen[v]) fail(TK_ERR_INVALID_ARG, "(p, q) is not a permutation of the legs");
+    seen[v] = 1;
+  }
+  for (int v : q) {
+    if (v < 0 || v >= N || seen[v]) fail(TK_ERR_INVALID_ARG, "(p, q) is not a permutation of the legs");
+    seen[v] = 1;
+  }
+  if (p.size() > TK_MAX_LEGS || q.size() > TK_MAX_LEGS) fail(TK_ERR_UNSUPPORTED, "too many legs on one side");
+}
+
+bool is_identity(const std::vector<int>& p, const std::vector<int>& q, int N1) {
+  if (static_cast<int>(p.size()) != N1) return false;
+  for (size_t i = 0; i < p.size(); ++i)
+    if (p[i] != static_cast<int>(i)) return false;
+  for (size_t j = 0; j < q.size(); ++j)
+    if (q[j] != static_cast<int>(N1 + j)) return false;
+  return true;
+}
+
+// Exchanged leg pairs of a permutation: pairs of input legs (x, y) whose
+// order in the bra-ket reading (codomain, then domain reversed) flips.
+std::vector<std::pair<int, int>> exchanged_pairs(int N1, int N2, const std::vector<int>& p, const std::vector<int>& q) {
+  const int N = N1 + N2;
+  std::vector<int> pos_in(N), pos_out(N);
+  for (int l = 0; l < N1; ++l) pos_in[l] = l;
+  for (int j = 0; j < N2; ++j) pos_in[N1 + j] = N - 1 - j;
+  const int n1o = static_cast<int>(p.size());
+  for (int i = 0; i < n1o; ++i) pos_out[p[i]] = i;
+  for (size_t j = 0; j < q.size(); ++j) pos_out[q[j]] = N - 1 - static_cast<int>(j);
+  std::vector<std::pair<int, int>> r;
+  for (int x = 0; x < N; ++x)
+    for (int y = 0; y < N; ++y)
+      if (pos_in[x] < pos_in[y] && pos_out[x] > pos_out[y]) r.emplace_back(x, y);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n) {
+    release();
+    if (n == 0) return;
+    if (hipMalloc(&p, n) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      fail(TK_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
+    }
+    bytes = n;
+  }
+  template <typename T>
+  void upload(const std::vector<T>& v) {
+    alloc(v.size() * sizeof(T));
+    if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  }
+};
+
+// ---------------------------------------------------------------------------
+// permute task lists
+// ---------------------------------------------------------------------------
+struct TaskList {
+  std::vector<PermTask> tasks;
+  std::vector<int32_t> wg_first{0};
+  DevBuf d_tasks, d_wg;
+  int nwg() const { return static_cast<int>(wg_first.size()) - 1; }
+  void upload() {
+    d_tasks.upload(tasks);
+    d_wg.upload(wg_first);
+  }
+};
+
+int32_t checked_i32(int64_t v, const char* what) {
+  if (v > INT32_MAX || v < INT32_MIN) fail(TK_ERR_UNSUPPORTED, std::string(what) + " exceeds 32 bits");
+  return static_cast<int32_t>(v);
+}
+
+// Add one block (dims/strides in output order) as chunked tasks.
+void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int64_t dst, int n, const int64_t* dim,
+                     const int64_t* ss, const int64_t* ds, float sign) {
+  // drop unit dims, merge dims that are contiguous on both sides
+  int64_t D[tk::kMaxDims], S[tk::kMaxDims], T[tk::kMaxDims];
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    if (dim[i] == 1) continue;
+    if (m > 0 && ss[i] == S[m - 1] * D[m - 1] && ds[i] == T[m - 1] * D[m - 1]) {
+      D[m - 1] *= dim[i];
+      continue;
+    }
+    D[m] = dim[i];
+    S[m] = ss[i];
+    T[m] = ds[i];
+    ++m;
+  }
+  if (m == 0) {
+    D[0] = 1;
+    S[0] = 0;
+    T[0] = 0;
+    m = 1;
+  }
+  int64_t total = 1;
+  for (int i = 0; i < m; ++i) total *= D[i];
+  if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
+  PermTask t{};
+  t.src = src;
+  t.dst = dst;
+  t.n = m;
+  t.src_buf = sbuf;
+  t.dst_buf = dbuf;
+  t.sign = sign;
+  for (int i = 0; i < tk::kMaxDims; ++i) {
+    t.dim[i] = i < m ? checked_i32(D[i], "dim") : 1;
+    t.ss[i] = i < m ? checked_i32(S[i], "stride") : 0;
+    t.ds[i] = i < m ? checked_i32(T[i], "stride") : 0;
+  }
+  for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
+    t.start = static_cast<int32_t>(s0);
+    t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
+    tl.tasks.push_back(t);
+  }
+}
+
+// Pack consecutive tasks into workgroups of about kPermChunk elements.
+void pack_workgroups(TaskList& tl) {
+  tl.wg_first.assign(1, 0);
+  int64_t acc = 0;
+  int ntask = 0;
+  for (size_t i = 0; i < tl.tasks.size(); ++i) {
+    const int c = tl.tasks[i].count;
+    if (ntask > 0 && (acc + c > tk::kPermChunk || ntask >= 64)) {
+      tl.wg_first.push_back(static_cast<int32_t>(i));
+      acc = 0;
+      ntask = 0;
+    }
+    acc += c;
+    ++ntask;
+  }
+  if (!tl.tasks.empty()) tl.wg_first.push_back(static_cast<int32_t>(tl.tasks.size()));
+}
+
+// Strides of a block inside its coupled-charge matrix, per leg.
+void block_strides(const Structure& st, const uint8_t* tup, int64_t R, int64_t* dims, int64_t* strides) {
+  int64_t acc = 1;
+  for (int l = 0; l < st.N1(); ++l) {
+    dims[l] = st.leg(l).deg[tup[l]];
+    strides[l] = acc;
+    acc *= dims[l];
+  }
+  acc = R;
+  for (int l = st.N1(); l < st.N(); ++l) {
+    dims[l] = st.leg(l).deg[tup[l]];
+    strides[l] = acc;
+    acc *= dims[l];
+  }
+}
+
+struct BlockLoc {
+  int sector = -1;
+  int32_t row = -1, col = -1;
+  int64_t offset = 0, R = 0;
+};
+
+// Locate the block of `st` with leg sector indices tup (codomain then domain).
+BlockLoc locate(const Structure& st, const uint8_t* tup) {
+  BlockLoc b;
+  const int64_t key = st.tuple_key(st.cod, tup);
+  b.sector = st.sector_of_key(key);
+  if (b.sector < 0) return b;
+  b.row = st.rows.find(tup);
+  b.col = st.cols.find(tup + st.N1());
+  if (b.row < 0 || b.col < 0) {
+    b.sector = -1;
+    return b;
+  }
+  b.R = st.R[b.sector];
+  b.offset = st.soff[b.sector] + st.cg[b.sector]->off[b.col] * b.R + st.rg[b.sector]->off[b.row];
+  return b;
+}
+
+// Iterate the blocks of a structure in storage order.
+template <typename F>
+void for_each_block(const Structure& st, F&& f) {
+  std::vector<uint8_t> tup(st.N());
+  for (size_t s = 0; s < st.keys.size(); ++s) {
+    const Group& rg = *st.rg[s];
+    const Group& cg = *st.cg[s];
+    for (int32_t j = 0; j < cg.n(); ++j) {
+      std::copy(cg.idx.begin() + size_t(j) * st.N2(), cg.idx.begin() + size_t(j + 1) * st.N2(), tup.begin() + st.N1());
+      for (int32_t i = 0; i < rg.n(); ++i) {
+        std::copy(rg.idx.begin() + size_t(i) * st.N1(), rg.idx.begin() + size_t(i + 1) * st.N1(), tup.begin());
+        const int64_t off = st.soff[s] + cg.off[j] * st.R[s] + rg.off[i];
+        f(static_cast<int>(s), i, j, tup.data(), off);
+      }
+    }
+  }
+}
+
+int channel_parity(const Structure& st, const uint8_t* tup, const std::vector<std::pair<int, int>>& pairs) {
+  int s = 0;
+  for (const auto& pr : pairs) s ^= (st.leg(pr.first).p[tup[pr.first]] & st.leg(pr.second).p[tup[pr.second]]);
+  return s;
+}
+
+// Permute plan A -> C (Alg. "Abelian Tensor Permutation"); twist additionally
+// multiplies by (-1)^{|x|} for every codomain leg of C on a dual space.
+void plan_permute_tasks(const Structure& A, const std::vector<int>& p, const std::vector<int>& q, const Structure& C,
+                        int16_t sbuf, int16_t dbuf, bool twist, TaskList& tl, std::vector<int64_t>* map_out = nullptr,
+                        std::vector<int32_t>* sign_out = nullptr) {
+  const bool ferm = A.si.fermionic;
+  const auto pairs = ferm ? exchanged_pairs(A.N1(), A.N2(), p, q) : std::vector<std::pair<int, int>>{};
+  std::vector<int> src(p);
+  src.insert(src.end(), q.begin(), q.end());
+  const int N = A.N();
+  std::vector<uint8_t> otup(N);
+  int64_t idim[TK_MAX_RANK], istr[TK_MAX_RANK], odim[TK_MAX_RANK], ostr[TK_MAX_RANK], oss[TK_MAX_RANK];
+  for_each_block(A, [&](int s, int32_t, int32_t, const uint8_t* tup, int64_t off) {
+    for (int n = 0; n < N; ++n) otup[n] = tup[src[n]];
+    const BlockLoc b = locate(C, otup.data());
+    if (b.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "permute: output tensor lacks a channel of the input");
+    block_strides(A, tup, A.R[s], idim, istr);
+    block_strides(C, otup.data(), b.R, odim, ostr);
+    for (int n = 0; n < N; ++n) oss[n] = istr[src[n]];
+    int par = ferm ? channel_parity(A, tup, pairs) : 0;
+    if (twist && ferm)
+      for (int n = 0; n < C.N1(); ++n)
+        if (C.cod[n].dual) par ^= C.cod[n].p[otup[n]];
+    const float sign = par ? -1.0f : 1.0f;
+    if (map_out) {
+      map_out->push_back(C.bbase[b.sector] + static_cast<int64_t>(b.col) * C.rg[b.sector]->n() + b.row);
+      sign_out->push_back(par ? -1 : 1);
+      return;
+    }
+    add_block_tasks(tl, sbuf, off, dbuf, b.offset, N, odim, oss, ostr, sign);
+  });
+}
+
+// Zero tasks for the whole storage of a sector range [off, off+count).
+void add_zero_range(TaskList& tl, int16_t dbuf, int64_t off, int64_t count) {
+  for (int64_t s0 = 0; s0 < count; s0 += int64_t(1) << 30) {
+    int64_t c = std::min<int64_t>(int64_t(1) << 30, count - s0);
+    int64_t dim = c, ss = 0, ds = 1;
+    add_block_tasks(tl, -1, 0, dbuf, off + s0, 1, &dim, &ss, &ds, 1.0f);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct tk_context {
+  int device = 0;
+  int num_cu = 256;
+  std::mutex mu;
+  std::unordered_map<std::string, std::shared_ptr<tk_plan>> plans;
+  std::unordered_map<std::string, std::shared_ptr<struct PermPlan>> perm_plans;
+};
+
+struct tk_tensor {
+  tk_context* ctx = nullptr;
+  std::shared_ptr<Structure> st;
+  int dtype = TK_F64;
+  void* data = nullptr;
+  uint64_t bytes = 0;
+  bool owns = false;
+  ~tk_tensor() {
+    if (owns && data) (void)hipFree(data);
+  }
+  size_t esize() const { return dtype == TK_F64 ? 8 : 4; }
+};
+
+struct PermPlan {
+  std::shared_ptr<Structure> A, C;
+  TaskList tl;
+};
+
+struct tk_plan {
+  tk_context* ctx = nullptr;
+  std::shared_ptr<Structure> A, B, C, At, Bt, Ct;
+  std::vector<int> pA, qA, pB, qB, pAB, qAB;
+  int precision = 0, dtype = 0;
+  bool permA = false, permB = false, scatter = false, post = false;
+  TaskList pre, zero, postp;
+  std::vector<GemmDesc> descs;
+  std::vector<LegMap> row_map, col_map;
+  std::vector<PairDesc> pairs;
+  DevBuf d_descs, d_rowmap, d_colmap, d_pairs;
+  // tile schedule
+  int tile_m = 128, tile_n = 128;
+  std::vector<GemmTile> tiles;
+  std::vector<int32_t> wg_first;
+  DevBuf d_tiles, d_wg;
+  DevBuf wsA, wsB, wsC;
+  double flops = 0;
+  int64_t nzero = 0;
+};
+
+struct tk_batch {
+  tk_context* ctx = nullptr;
+  int n = 0, dtype = 0, precision = 0;
+  double alpha = 1.0, beta = 0.0;
+  TaskList pre, zero, postp;
+  std::vector<GemmDesc> descs;
+  std::vector<LegMap> row_map, col_map;
+  std::vector<PairDesc> pairs;
+  DevBuf d_descs, d_rowmap, d_colmap, d_pairs, d_tiles, d_wg, d_table;
+  std::vector<std::unique_ptr<DevBuf>> ws;
+  int tile_m = 128, tile_n = 128;
+  std::vector<GemmTile> tiles;
+  std::vector<int32_t> wg_first;
+  double flops = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~tk_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+// LPT schedule of the tiles of a set of GEMMs over at most max_wg workgroups:
+// tiles sorted by cost (K steps) and each given to the least loaded group.
+void schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, std::vector<GemmTile>& tiles_out,
+                    std::vector<int32_t>& wg_first) {
+  struct T {
+    GemmTile t;
+    int64_t cost;
+  };
+  std::vector<T> all;
+  for (size_t g = 0; g < descs.size(); ++g) {
+    const GemmDesc& d = descs[g];
+    const int64_t cost = (d.K + 15) / 16 + 4;
+    for (int m0 = 0; m0 < d.M; m0 += tm)
+      for (int n0 = 0; n0 < d.N; n0 += tn) all.push_back({GemmTile{static_cast<int32_t>(g), m0, n0, 0}, cost});
+  }
+  std::stable_sort(all.begin(), all.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(all.size())));
+  std::vector<std::vector<GemmTile>> per(nwg);
+  using E = std::pair<int64_t, int>;
+  std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
+  for (int w = 0; w < nwg; ++w) heap.push({0, w});
+  for (const auto& t : all) {
+    E e = heap.top();
+    heap.pop();
+    per[e.second].push_back(t.t);
+    heap.push({e.first + t.cost, e.second});
+  }
+  tiles_out.clear();
+  wg_first.assign(1, 0);
+  for (int w = 0; w < nwg; ++w) {
+    tiles_out.insert(tiles_out.end(), per[w].begin(), per[w].end());
+    wg_first.push_back(static_cast<int32_t>(tiles_out.size()));
+  }
+}
+
+void plan_reschedule(tk_plan& P, int tm, int tn) {
+  P.tile_m = tm;
+  P.tile_n = tn;
+  schedule_tiles(P.descs, tm, tn, P.ctx ? P.ctx->num_cu : 256, P.tiles, P.wg_first);
+  if (P.ctx) {
+    P.d_tiles.upload(P.tiles);
+    P.d_wg.upload(P.wg_first);
+  }
+}
+
+void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn) {
+  int64_t mmax = 0, nmax = 0;
+  for (const auto& d : descs) {
+    mmax = std::max<int64_t>(mmax, d.M);
+    nmax = std::max<int64_t>(nmax, d.N);
+  }
+  *tm = mmax > 64 ? 128 : 64;
+  *tn = nmax > 64 ? 128 : 64;
+}
+
+std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A, std::vector<int> pA,
+                                             std::vector<int> qA, const tk_tensor* B, std::vector<int> pB,
+                                             std::vector<int> qB, std::vector<int> pAB, std::vector<int> qAB,
+                                             int precision, const tk_tensor* C) {
+  const Structure& sA = *A->st;
+  const Structure& sB = *B->st;
+  if (sA.sym != sB.sym || sA.sym != C->st->sym) fail(TK_ERR_INVALID_ARG, "symmetry mismatch");
+  if (A->dtype != B->dtype || A->dtype != C->dtype) fail(TK_ERR_DTYPE, "dtype mismatch");
+  check_perm(pA, qA, sA.N());
+  check_perm(pB, qB, sB.N());
+  if (qA.size() != pB.size()) fail(TK_ERR_INVALID_ARG, "qA and pB differ in length");
+  check_perm(pAB, qAB, static_cast<int>(pA.size() + qB.size()));
+  if (precision < TK_PREC_NATIVE || precision > TK_PREC_BF16X3) fail(TK_ERR_INVALID_ARG, "unknown precision");
+  if (!tk::gemm_tile_supported(A->dtype, precision, 128, 128) && !tk::gemm_tile_supported(A->dtype, precision, 64, 64))
+    fail(TK_ERR_DTYPE, "this dtype / precision combination is not available");
+
+  auto P = std::make_unique<tk_plan>();
+  P->ctx = ctx;
+  P->A = A->st;
+  P->B = B->st;
+  P->C = C->st;
+  P->pA = pA;
+  P->qA = qA;
+  P->pB = pB;
+  P->qB = qB;
+  P->pAB = pAB;
+  P->qAB = qAB;
+  P->precision = precision;
+  P->dtype = A->dtype;
+  const int sym = sA.sym;
+
+  std::vector<Space> atc, atd, btc, btd;
+  permute_spaces(sA, pA, qA, atc, atd);
+  permute_spaces(sB, pB, qB, btc, btd);
+  if (atd.size() != btc.size()) fail(TK_ERR_SPACE_MISMATCH, "domain(A~) != codomain(B~)");
+  for (size_t k = 0; k < atd.size(); ++k)
+    if (atd[k] != btc[k]) fail(TK_ERR_SPACE_MISMATCH, "domain(A~) != codomain(B~) at contracted leg " + std::to_string(k));
+  P->At = get_structure(sym, atc, atd);
+  P->Bt = get_structure(sym, btc, btd);
+  P->Ct = get_structure(sym, atc, btd);
+  const Structure& At = *P->At;
+  const Structure& Bt = *P->Bt;
+  const Structure& Ct = *P->Ct;
+  std::vector<Space> cc, cd;
+  permute_spaces(Ct, pAB, qAB, cc, cd);
+  if (cc != C->st->cod || cd != C->st->dom) fail(TK_ERR_SPACE_MISMATCH, "C does not have the contracted spaces");
+  const Structure& sC = *C->st;
+
+  // composition twist: contracted legs on dual spaces (codomain of B~)
+  bool twist = false;
+  if (sA.si.fermionic)
+    for (const auto& s : btc)
+      if (s.dual && std::find(s.p.begin(), s.p.end(), 1) != s.p.end()) twist = true;
+  P->permA = !is_identity(pA, qA, sA.N1());
+  P->permB = !is_identity(pB, qB, sB.N1()) || twist;
+  if (P->permA) plan_permute_tasks(sA, pA, qA, At, tk::kBufA, tk::kBufAt, false, P->pre);
+  if (P->permB) plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, tk::kBufBt, twist, P->pre);
+  pack_workgroups(P->pre);
+
+  const bool idC = is_identity(pAB, qAB, Ct.N1());
+  // fused scatter needs <= 4 legs per side of C~ and 16-bit leg indices
+  bool can_scatter = Ct.N1() <= 4 && Ct.N2() <= 4;
+  for (int l = 0; l < Ct.N() && can_scatter; ++l)
+    for (int64_t d : Ct.leg(l).deg)
+      if (d > 65535) can_scatter = false;
+  P->scatter = !idC && can_scatter;
+  P->post = !idC && !can_scatter;
+
+  const int16_t abuf = P->permA ? tk::kBufAt : tk::kBufA;
+  const int16_t bbuf = P->permB ? tk::kBufBt : tk::kBufB;
+  std::vector<int> src(pAB);
+  src.insert(src.end(), qAB.begin(), qAB.end());
+  std::vector<int> pos(Ct.N());
+  for (int n = 0; n < Ct.N(); ++n) pos[src[n]] = n;
+  const auto outpairs = sA.si.fermionic ? exchanged_pairs(Ct.N1(), Ct.N2(), pAB, qAB) : std::vector<std::pair<int, int>>{};
+
+  std::vector<uint8_t> tup(Ct.N()), otup(Ct.N());
+  int64_t odim[TK_MAX_RANK], ostr[TK_MAX_RANK];
+  for (size_t s = 0; s < Ct.keys.size(); ++s) {
+    const int64_t key = Ct.keys[s];
+    const int sa = At.sector_of_key(key);
+    const int64_t M = Ct.R[s], N = Ct.C[s];
+    const int64_t K = sa >= 0 ? At.C[sa] : 0;
+    const Group& rg = *Ct.rg[s];
+    const Group& cg = *Ct.cg[s];
+    if (K > 0) {
+      const int sb = Bt.sector_of_key(key);
+      if (sb < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: B~ lacks a sector of A~");
+      GemmDesc d{};
+      d.a = At.soff[sa];
+      d.b = Bt.soff[sb];
+      d.M = checked_i32(M, "M");
+      d.N = checked_i32(N, "N");
+      d.K = checked_i32(K, "K");
+      d.lda = d.M;
+      d.ldb = d.K;
+      d.a_buf = abuf;
+      d.b_buf = bbuf;
+      P->flops += 2.0 * double(M) * double(N) * double(K);
+      if (idC) {
+        d.mode = 0;
+        d.c = sC.soff[sC.sector_of_key(key)];
+        d.ldc = d.M;
+        d.c_buf = tk::kBufC;
+      } else if (P->post) {
+        d.mode = 0;
+        d.c = Ct.soff[s];
+        d.ldc = d.M;
+        d.c_buf = tk::kBufCt;
+      } else {
+        d.mode = 1;
+        d.c_buf = tk::kBufC;
+        d.row_map = checked_i32(static_cast<int64_t>(P->row_map.size()), "row map");
+        d.col_map = checked_i32(static_cast<int64_t>(P->col_map.size()), "col map");
+        d.pair_base = checked_i32(static_cast<int64_t>(P->pairs.size()), "pair table");
+        d.ncc = cg.n();
+        // row maps: every row of the sector -> (channel, leg indices)
+        for (int32_t i = 0; i < rg.n(); ++i) {
+          const uint8_t* t = &rg.idx[size_t(i) * Ct.N1()];
+          for (int64_t r = 0; r < rg.size[i]; ++r) {
+            LegMap lm{};
+            lm.chan = i;
+            int64_t rem = r;
+            for (int l = 0; l < Ct.N1(); ++l) {
+              const int64_t dl = Ct.cod[l].deg[t[l]];
+              lm.idx[l] = static_cast<uint16_t>(rem % dl);
+              rem /= dl;
+            }
+            P->row_map.push_back(lm);
+          }
+        }
+        for (int32_t j = 0; j < cg.n(); ++j) {
+          const uint8_t* t = &cg.idx[size_t(j) * Ct.N2()];
+          for (int64_t c = 0; c < cg.size[j]; ++c) {
+            LegMap lm{};
+            lm.chan = j;
+            int64_t rem = c;
+            for (int l = 0; l < Ct.N2(); ++l) {
+              const int64_t dl = Ct.dom[l].deg[t[l]];
+              lm.idx[l] = static_cast<uint16_t>(rem % dl);
+              rem /= dl;
+            }
+            P->col_map.push_back(lm);
+          }
+        }
+        for (int32_t i = 0; i < rg.n(); ++i) {
+          for (int32_t j = 0; j < cg.n(); ++j) {
+            std::copy(rg.idx.begin() + size_t(i) * Ct.N1(), rg.idx.begin() + size_t(i + 1) * Ct.N1(), tup.begin());
+            std::copy(cg.idx.begin() + size_t(j) * Ct.N2(), cg.idx.begin() + size_t(j + 1) * Ct.N2(),
+                      tup.begin() + Ct.N1());
+            for (int n = 0; n < Ct.N(); ++n) otup[n] = tup[src[n]];
+            const BlockLoc b = locate(sC, otup.data());
+            if (b.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
+            block_strides(sC, otup.data(), b.R, odim, ostr);
+            PairDesc pd{};
+            pd.base = b.offset;
+            const int par = sA.si.fermionic ? channel_parity(Ct, tup.data(), outpairs) : 0;
+            pd.sign = par ? -1.0f : 1.0f;
+            for (int l = 0; l < Ct.N1(); ++l) pd.S[l] = checked_i32(ostr[pos[l]], "stride");
+            for (int l = 0; l < Ct.N2(); ++l) pd.S[4 + l] = checked_i32(ostr[pos[Ct.N1() + l]], "stride");
+            P->pairs.push_back(pd);
+          }
+        }
+      }
+      P->descs.push_back(d);
+    } else {
+      // empty K range: the C~ block is zero (eq. abelian_compostion remark)
+      ++P->nzero;
+      if (idC) {
+        const int sc = sC.sector_of_key(key);
+        add_zero_range(P->zero, tk::kBufC, sC.soff[sc], M * N);
+      } else if (P->post) {
+        add_zero_range(P->zero, tk::kBufCt, Ct.soff[s], M * N);
+      } else {
+        for (int32_t j = 0; j < cg.n(); ++j)
+          for (int32_t i = 0; i < rg.n(); ++i) {
+            std::copy(rg.idx.begin() + size_t(i) * Ct.N1(), rg.idx.begin() + size_t(i + 1) * Ct.N1(), tup.begin());
+            std::copy(cg.idx.begin() + size_t(j) * Ct.N2(), cg.idx.begin() + size_t(j + 1) * Ct.N2(),
+                      tup.begin() + Ct.N1());
+            for (int n = 0; n < Ct.N(); ++n) otup[n] = tup[src[n]];
+            const BlockLoc b = locate(sC, otup.data());
+            if (b.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
+            block_strides(sC, otup.data(), b.R, odim, ostr);
+            int64_t zs[TK_MAX_RANK] = {0};
+            add_block_tasks(P->zero, -1, 0, tk::kBufC, b.offset, sC.N(), odim, zs, ostr, 1.0f);
+          }
+      }
+    }
+  }
+  pack_workgroups(P->zero);
+  if (P->post) {
+    plan_permute_tasks(Ct, pAB, qAB, sC, tk::kBufCt, tk::kBufC, false, P->postp);
+    pack_workgroups(P->postp);
+  }
+
+  int tm, tn;
+  choose_default_tile(P->descs, &tm, &tn);
+  P->tile_m = tm;
+  P->tile_n = tn;
+  schedule_tiles(P->descs, tm, tn, ctx ? ctx->num_cu : 256, P->tiles, P->wg_first);
+
+  if (ctx) {
+    const size_t es = A->esize();
+    if (P->permA) P->wsA.alloc(At.size * es);
+    if (P->permB) P->wsB.alloc(Bt.size * es);
+    if (P->post) P->wsC.alloc(Ct.size * es);
+    P->pre.upload();
+    P->zero.upload();
+    P->postp.upload();
+    P->d_descs.upload(P->descs);
+    P->d_rowmap.upload(P->row_map);
+    P->d_colmap.upload(P->col_map);
+    P->d_pairs.upload(P->pairs);
+    P->d_tiles.upload(P->tiles);
+    P->d_wg.upload(P->wg_first);
+  }
+  return P;
+}
+
+tk::Ptrs plan_ptrs(const tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor* C) {
+  tk::Ptrs p{};
+  p.p[tk::kBufA] = A->data;
+  p.p[tk::kBufB] = B->data;
+  p.p[tk::kBufC] = C->data;
+  p.p[tk::kBufAt] = P.wsA.p;
+  p.p[tk::kBufBt] = P.wsB.p;
+  p.p[tk::kBufCt] = P.wsC.p;
+  p.table = nullptr;
+  return p;
+}
+
+void check_exec_tensor(const tk_tensor* t, const std::shared_ptr<Structure>& st, int dtype, const char* what) {
+  if (!t) fail(TK_ERR_INVALID_ARG, std::string("null tensor ") + what);
+  if (!t->data && t->st->size > 0) fail(TK_ERR_INVALID_ARG, std::string("tensor without data: ") + what);
+  if (t->st != st && t->st->sig != st->sig) fail(TK_ERR_SPACE_MISMATCH, std::string("structure differs from the plan: ") + what);
+  if (t->dtype != dtype) fail(TK_ERR_DTYPE, std::string("dtype differs from the plan: ") + what);
+}
+
+void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor* C, double alpha, double beta,
+                  hipStream_t stream, int stages = TK_STAGE_ALL) {
+  if (!P.ctx) fail(TK_ERR_INVALID_ARG, "plan was made without a context");
+  check_exec_tensor(A, P.A, P.dtype, "A");
+  check_exec_tensor(B, P.B, P.dtype, "B");
+  check_exec_tensor(C, P.C, P.dtype, "C");
+  if (C->data && (C->data == A->data || C->data == B->data)) fail(TK_ERR_INVALID_ARG, "C aliases an operand");
+  tk::Ptrs ptrs = plan_ptrs(P, A, B, C);
+  if ((stages & TK_STAGE_PERMUTE) && P.pre.nwg() > 0)
+    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.pre.d_tasks.p),
+                                 static_cast<const int32_t*>(P.pre.d_wg.p), P.pre.nwg(), ptrs, 1.0, 0.0, stream),
+              "permute launch");
+  const double ga = alpha, gb = P.post ? 0.0 : beta;
+  if ((stages & TK_STAGE_GEMM) && !P.descs.empty()) {
+    tk::GemmArgs ga_{};
+    ga_.descs = static_cast<const GemmDesc*>(P.d_descs.p);
+    ga_.tiles = static_cast<const GemmTile*>(P.d_tiles.p);
+    ga_.wg_first = static_cast<const int32_t*>(P.d_wg.p);
+    ga_.row_map = static_cast<const LegMap*>(P.d_rowmap.p);
+    ga_.col_map = static_cast<const LegMap*>(P.d_colmap.p);
+    ga_.pairs = static_cast<const PairDesc*>(P.d_pairs.p);
+    ga_.ptrs = ptrs;
+    ga_.alpha = P.post ? 1.0 : ga;
+    ga_.beta = gb;
+    hip_check(tk::launch_gemm(P.dtype, P.precision, P.tile_m, P.tile_n, ga_, static_cast<int>(P.wg_first.size()) - 1,
+                              stream),
+              "gemm launch");
+  }
+  if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
+    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
+                                 static_cast<const int32_t*>(P.zero.d_wg.p), P.zero.nwg(), ptrs, P.post ? 1.0 : alpha,
+                                 P.post ? 0.0 : beta, stream),
+              "zero launch");
+  if ((stages & TK_STAGE_ZERO) && P.post && P.postp.nwg() > 0)
+    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.postp.d_tasks.p),
+                                 static_cast<const int32_t*>(P.postp.d_wg.p), P.postp.nwg(), ptrs, alpha, beta, stream),
+              "permute launch");
+}
+
+std::string plan_key(const tk_tensor* A, const std::vector<int>& pA, const std::vector<int>& qA, const tk_tensor* B,
+                     const std::vector<int>& pB, const std::vector<int>& qB, const std::vector<int>& pAB,
+                     const std::vector<int>& qAB, int prec, const tk_tensor* C) {
+  auto lst = [](const std::vector<int>& v) {
+    std::string s;
+    for (int x : v) s += std::to_string(x) + ",";
+    return s + "/";
+  };
+  return A->st->sig + "#" + B->st->sig + "#" + C->st->sig + "#" + lst(pA) + lst(qA) + lst(pB) + lst(qB) + lst(pAB) +
+         lst(qAB) + std::to_string(prec) + "/" + std::to_string(A->dtype);
+}
+
+std::vector<Space> make_spaces(int sym, const tk_space* s, int32_t n) {
+  if (n < 0 || n > TK_MAX_LEGS || (n > 0 && !s)) fail(TK_ERR_INVALID_ARG, "bad space list");
+  std::vector<Space> v;
+  for (int i = 0; i < n; ++i) v.push_back(make_space(sym, s[i]));
+  return v;
+}
+
+tk_tensor* new_tensor(tk_context* ctx, std::shared_ptr<Structure> st, int dtype, void* buf, uint64_t bytes) {
+  if (dtype != TK_F64 && dtype != TK_F32) fail(TK_ERR_DTYPE, "dtype must be TK_F64 or TK_F32");
+  auto t = std::make_unique<tk_tensor>();
+  t->ctx = ctx;
+  t->st = std::move(st);
+  t->dtype = dtype;
+  const uint64_t need = static_cast<uint64_t>(t->st->size) * t->esize();
+  if (!ctx) {
+    if (buf) fail(TK_ERR_INVALID_ARG, "a structure-only tensor takes no buffer");
+  } else if (buf) {
+    if (bytes < need) fail(TK_ERR_INVALID_ARG, "buffer smaller than the tensor");
+    t->data = buf;
+    t->bytes = bytes;
+  } else if (need > 0) {
+    hip_check(hipSetDevice(ctx->device), "hipSetDevice");
+    if (hipMalloc(&t->data, need) != hipSuccess) {
+      (void)hipGetLastError();
+      t->data = nullptr;
+      fail(TK_ERR_OOM, "device allocation failed");
+    }
+    t->bytes = need;
+    t->owns = true;
+  }
+  return t.release();
+}
+
+template <typename F>
+tk_status guarded(F&& f) {
+  try {
+    f();
+    return TK_OK;
+  } catch (const TkError& e) {
+    g_err = e.msg;
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return TK_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return TK_ERR_INVALID_ARG;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C-ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tk_last_error(void) { return g_err.c_str(); }
+const char* tk_version(void) { return "tk 0.1 (gfx950)"; }
+
+tk_status tk_context_create(int32_t device, tk_context** out) {
+  return guarded([&] {
+    if (!out) fail(TK_ERR_INVALID_ARG, "null out");
+    int n = 0;
+    hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
+    if (device < 0 || device >= n) fail(TK_ERR_INVALID_ARG, "no such device");
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    auto c = std::make_unique<tk_context>();
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    *out = c.release();
+  });
+}
+
+tk_status tk_context_destroy(tk_context* ctx) {
+  return guarded([&] { delete ctx; });
+}
+
+tk_status tk_tensor_create(tk_context* ctx, int32_t sym, int32_t dtype, const tk_space* cod, int32_t ncod,
+                           const tk_space* dom, int32_t ndom, void* device_buf, uint64_t buf_bytes, tk_tensor** out) {
+  return guarded([&] {
+    if (!out) fail(TK_ERR_INVALID_ARG, "null out");
+    sym_info(sym);
+    auto c = make_spaces(sym, cod, ncod);
+    auto d = make_spaces(sym, dom, ndom);
+    if (c.size() + d.size() > TK_MAX_RANK) fail(TK_ERR_UNSUPPORTED, "rank above TK_MAX_RANK");
+    *out = new_tensor(ctx, get_structure(sym, c, d), dtype, device_buf, buf_bytes);
+  });
+}
+
+tk_status tk_tensor_destroy(tk_tensor* t) {
+  return guarded([&] { delete t; });
+}
+
+tk_status tk_tensor_info(const tk_tensor* t, int32_t* sym, int32_t* dtype, int32_t* ncod, int32_t* ndom,
+                         int64_t* nelem, int64_t* nblocks, int64_t* nsectors) {
+  return guarded([&] {
+    if (!t) fail(TK_ERR_INVALID_ARG, "null tensor");
+    if (sym) *sym = t->st->sym;
+    if (dtype) *dtype = t->dtype;
+    if (ncod) *ncod = t->st->N1();
+    if (ndom) *ndom = t->st->N2();
+    if (nelem) *nelem = t->st->size;
+    if (nblocks) *nblocks = t->st->nblocks;
+    if (nsectors) *nsectors = static_cast<int64_t>(t->st->keys.size());
+  });
+}
+
+tk_status tk_tensor_blocks(const tk_tensor* t, int64_t first, int64_t count, int32_t* sector_idx, int64_t* offsets,
+                           int64_t* ld) {
+  return guarded([&] {
+    if (!t) fail(TK_ERR_INVALID_ARG, "null tensor");
+    const Structure& st = *t->st;
+    if (first < 0 || count < 0 || first + count > st.nblocks) fail(TK_ERR_INVALID_ARG, "block range out of bounds");
+    if (count == 0) return;
+    int s = static_cast<int>(std::upper_bound(st.bbase.begin(), st.bbase.end(), first) - st.bbase.begin()) - 1;
+    for (int64_t b = first; b < first + count; ++b) {
+      while (s + 1 < static_cast<int>(st.bbase.size()) && st.bbase[s + 1] <= b) ++s;
+      const Group& rg = *st.rg[s];
+      const Group& cg = *st.cg[s];
+      const int64_t local = b - st.bbase[s];
+      const int32_t j = static_cast<int32_t>(local / rg.n()), i = static_cast<int32_t>(local % rg.n());
+      const int64_t k = b - first;
+      if (sector_idx) {
+        for (int l = 0; l < st.N1(); ++l) sector_idx[k * st.N() + l] = rg.idx[size_t(i) * st.N1() + l];
+        for (int l = 0; l < st.N2(); ++l) sector_idx[k * st.N() + st.N1() + l] = cg.idx[size_t(j) * st.N2() + l];
+      }
+      if (offsets) offsets[k] = st.soff[s] + cg.off[j] * st.R[s] + rg.off[i];
+      if (ld) ld[k] = st.R[s];
+    }
+  });
+}
+
+tk_status tk_tensor_sectors(const tk_tensor* t, int64_t first, int64_t count, int32_t* charges, int64_t* rows,
+                            int64_t* cols, int64_t* offsets) {
+  return guarded([&] {
+    if (!t) fail(TK_ERR_INVALID_ARG, "null tensor");
+    const Structure& st = *t->st;
+    const int64_t ns = static_cast<int64_t>(st.keys.size());
+    if (first < 0 || count < 0 || first + count > ns) fail(TK_ERR_INVALID_ARG, "sector range out of bounds");
+    for (int64_t k = 0; k < count; ++k) {
+      const int64_t s = first + k, key = st.keys[s];
+      const int64_t p = ((key % 2) + 2) % 2, q = (key - p) / 2;
+      if (charges) {
+        if (st.sym == TK_SYM_Z2 || st.sym == TK_SYM_FZ2) charges[k] = static_cast<int32_t>(p);
+        if (st.sym == TK_SYM_U1) charges[k] = static_cast<int32_t>(q);
+        if (st.sym == TK_SYM_U1_FZ2) {
+          charges[2 * k] = static_cast<int32_t>(q);
+          charges[2 * k + 1] = static_cast<int32_t>(p);
+        }
+      }
+      if (rows) rows[k] = st.R[s];
+      if (cols) cols[k] = st.C[s];
+      if (offsets) offsets[k] = st.soff[s];
+    }
+  });
+}
+
+tk_status tk_tensor_space(const tk_tensor* t, int32_t leg, tk_space* out) {
+  return guarded([&] {
+    if (!t || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (leg < 0 || leg >= t->st->N()) fail(TK_ERR_INVALID_ARG, "leg out of range");
+    const Space& s = t->st->leg(leg);
+    out->nsect = s.n();
+    out->charges = s.raw.empty() ? nullptr : s.raw.data();
+    out->degeneracies = s.deg.data();
+    out->isdual = s.dual ? 1 : 0;
+  });
+}
+
+tk_status tk_tensor_data(const tk_tensor* t, void** device_ptr, uint64_t* bytes) {
+  return guarded([&] {
+    if (!t) fail(TK_ERR_INVALID_ARG, "null tensor");
+    if (device_ptr) *device_ptr = t->data;
+    if (bytes) *bytes = static_cast<uint64_t>(t->st->size) * t->esize();
+  });
+}
+
+tk_status tk_tensor_create_permuted(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                                    const int32_t* q, int32_t nq, void* device_buf, uint64_t buf_bytes,
+                                    tk_tensor** out) {
+  return guarded([&] {
+    if (!A || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto pv = to_vec(p, np, "p");
+    auto qv = to_vec(q, nq, "q");
+    check_perm(pv, qv, A->st->N());
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    *out = new_tensor(ctx, get_structure(A->st->sym, c, d), A->dtype, device_buf, buf_bytes);
+  });
+}
+
+tk_status tk_tensor_create_contracted(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
+                                      const int32_t* qA, int32_t nqA, const tk_tensor* B, const int32_t* pB,
+                                      int32_t npB, const int32_t* qB, int32_t nqB, const int32_t* pAB, int32_t npAB,
+                                      const int32_t* qAB, int32_t nqAB, void* device_buf, uint64_t buf_bytes,
+                                      tk_tensor** out) {
+  return guarded([&] {
+    if (!A || !B || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (A->st->sym != B->st->sym) fail(TK_ERR_INVALID_ARG, "symmetry mismatch");
+    if (A->dtype != B->dtype) fail(TK_ERR_DTYPE, "dtype mismatch");
+    auto pa = to_vec(pA, npA, "pA"), qa = to_vec(qA, nqA, "qA"), pb = to_vec(pB, npB, "pB"), qb = to_vec(qB, nqB, "qB");
+    auto pab = to_vec(pAB, npAB, "pAB"), qab = to_vec(qAB, nqAB, "qAB");
+    check_perm(pa, qa, A->st->N());
+    check_perm(pb, qb, B->st->N());
+    if (qa.size() != pb.size()) fail(TK_ERR_INVALID_ARG, "qA and pB differ in length");
+    check_perm(pab, qab, static_cast<int>(pa.size() + qb.size()));
+    std::vector<Space> atc, atd, btc, btd;
+    permute_spaces(*A->st, pa, qa, atc, atd);
+    permute_spaces(*B->st, pb, qb, btc, btd);
+    for (size_t k = 0; k < atd.size(); ++k)
+      if (atd[k] != btc[k]) fail(TK_ERR_SPACE_MISMATCH, "domain(A~) != codomain(B~)");
+    Structure tmp;
+    tmp.sym = A->st->sym;
+    tmp.cod = atc;
+    tmp.dom = btd;
+    std::vector<Space> c, d;
+    permute_spaces(tmp, pab, qab, c, d);
+    if (c.size() + d.size() > TK_MAX_RANK || c.size() > TK_MAX_LEGS || d.size() > TK_MAX_LEGS)
+      fail(TK_ERR_UNSUPPORTED, "result rank too large");
+    *out = new_tensor(ctx, get_structure(A->st->sym, c, d), A->dtype, device_buf, buf_bytes);
+  });
+}
+
+tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* device_buf, uint64_t buf_bytes,
+                                   tk_tensor** out) {
+  return guarded([&] {
+    if (!A || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    *out = new_tensor(ctx, get_structure(A->st->sym, A->st->dom, A->st->cod), A->dtype, device_buf, buf_bytes);
+  });
+}
+
+tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,
+                            int32_t nq, tk_tensor* C, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !C) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (A->dtype != C->dtype) fail(TK_ERR_DTYPE, "dtype mismatch");
+    if (!A->data && A->st->size) fail(TK_ERR_INVALID_ARG, "A has no data");
+    if (!C->data && C->st->size) fail(TK_ERR_INVALID_ARG, "C has no data");
+    if (A->data && A->data == C->data) fail(TK_ERR_INVALID_ARG, "C aliases A");
+    auto pv = to_vec(p, np, "p");
+    auto qv = to_vec(q, nq, "q");
+    check_perm(pv, qv, A->st->N());
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    if (c != C->st->cod || d != C->st->dom) fail(TK_ERR_SPACE_MISMATCH, "C does not have the permuted spaces");
+    std::string key = "P#" + A->st->sig + "#" + C->st->sig + "#";
+    for (int x : pv) key += std::to_string(x) + ",";
+    key += "/";
+    for (int x : qv) key += std::to_string(x) + ",";
+    std::shared_ptr<PermPlan> pp;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      auto it = ctx->perm_plans.find(key);
+      if (it != ctx->perm_plans.end()) pp = it->second;
+    }
+    if (!pp) {
+      pp = std::make_shared<PermPlan>();
+      pp->A = A->st;
+      pp->C = C->st;
+      plan_permute_tasks(*A->st, pv, qv, *C->st, tk::kBufA, tk::kBufC, false, pp->tl);
+      pack_workgroups(pp->tl);
+      pp->tl.upload();
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->perm_plans[key] = pp;
+    }
+    tk::Ptrs ptrs{};
+    ptrs.p[tk::kBufA] = A->data;
+    ptrs.p[tk::kBufC] = C->data;
+    hip_check(tk::launch_permute(A->dtype, static_cast<const PermTask*>(pp->tl.d_tasks.p),
+                                 static_cast<const int32_t*>(pp->tl.d_wg.p), pp->tl.nwg(), ptrs, 1.0, 0.0,
+                                 static_cast<hipStream_t>(stream)),
+              "permute launch");
+  });
+}
+
+tk_status tk_tensor_adjoint(tk_context* ctx, const tk_tensor* A, tk_tensor* C, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !C) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (A->dtype != C->dtype) fail(TK_ERR_DTYPE, "dtype mismatch");
+    if (C->st->cod != A->st->dom || C->st->dom != A->st->cod) fail(TK_ERR_SPACE_MISMATCH, "C is not shaped as A^dagger");
+    if (A->data && A->data == C->data) fail(TK_ERR_INVALID_ARG, "C aliases A");
+    const std::string key = "ADJ#" + A->st->sig;
+    std::shared_ptr<PermPlan> pp;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      auto it = ctx->perm_plans.find(key);
+      if (it != ctx->perm_plans.end()) pp = it->second;
+    }
+    if (!pp) {
+      pp = std::make_shared<PermPlan>();
+      const Structure& sA = *A->st;
+      const Structure& sC = *C->st;
+      for (size_t s = 0; s < sA.keys.size(); ++s) {
+        const int sc = sC.sector_of_key(sA.keys[s]);
+        if (sc < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: adjoint sector missing");
+        // C^c = (A^c)^T: output (i', j') <- input (j', i')
+        int64_t dims[2] = {sA.C[s], sA.R[s]}, ss[2] = {sA.R[s], 1}, ds[2] = {1, sC.R[sc]};
+        add_block_tasks(pp->tl, tk::kBufA, sA.soff[s], tk::kBufC, sC.soff[sc], 2, dims, ss, ds, 1.0f);
+      }
+      pack_workgroups(pp->tl);
+      pp->tl.upload();
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->perm_plans[key] = pp;
+    }
+    tk::Ptrs ptrs{};
+    ptrs.p[tk::kBufA] = A->data;
+    ptrs.p[tk::kBufC] = C->data;
+    hip_check(tk::launch_permute(A->dtype, static_cast<const PermTask*>(pp->tl.d_tasks.p),
+                                 static_cast<const int32_t*>(pp->tl.d_wg.p), pp->tl.nwg(), ptrs, 1.0, 0.0,
+                                 static_cast<hipStream_t>(stream)),
+              "adjoint launch");
+  });
+}
+
+tk_status tk_plan_contract(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA, const int32_t* qA,
+                           int32_t nqA, const tk_tensor* B, const int32_t* pB, int32_t npB, const int32_t* qB,
+                           int32_t nqB, const int32_t* pAB, int32_t npAB, const int32_t* qAB, int32_t nqAB,
+                           int32_t precision, const tk_tensor* C, tk_plan** out) {
+  return guarded([&] {
+    if (!A || !B || !C || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto P = build_contract_plan(ctx, A, to_vec(pA, npA, "pA"), to_vec(qA, nqA, "qA"), B, to_vec(pB, npB, "pB"),
+                                 to_vec(qB, nqB, "qB"), to_vec(pAB, npAB, "pAB"), to_vec(qAB, nqAB, "qAB"), precision, C);
+    *out = P.release();
+  });
+}
+
+tk_status tk_plan_execute(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C, double alpha,
+                          double beta, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    execute_plan(*plan, A, B, C, alpha, beta, static_cast<hipStream_t>(stream));
+  });
+}
+
+tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C, double alpha,
+                                 double beta, int32_t stages, void* stream) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    if (stages < 0 || stages > TK_STAGE_ALL) fail(TK_ERR_INVALID_ARG, "bad stage mask");
+    execute_plan(*plan, A, B, C, alpha, beta, static_cast<hipStream_t>(stream), stages);
+  });
+}
+
+tk_status tk_plan_destroy(tk_plan* plan) {
+  return guarded([&] { delete plan; });
+}
+
+tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero, int64_t* workspace_bytes,
+                       int32_t* tile_m, int32_t* tile_n) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    if (ngemm) *ngemm = static_cast<int64_t>(plan->descs.size());
+    if (flops) *flops = plan->flops;
+    if (nzero) *nzero = plan->nzero;
+    if (workspace_bytes) {
+      const int64_t es = plan->dtype == TK_F64 ? 8 : 4;
+      *workspace_bytes = (plan->permA ? plan->At->size * es : 0) + (plan->permB ? plan->Bt->size * es : 0) +
+                         (plan->post ? plan->Ct->size * es : 0);
+    }
+    if (tile_m) *tile_m = plan->tile_m;
+    if (tile_n) *tile_n = plan->tile_n;
+  });
+}
+
+tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk) {
+  return guarded([&] {
+    if (!plan || !mnk) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (first < 0 || count < 0 || first + count > static_cast<int64_t>(plan->descs.size()))
+      fail(TK_ERR_INVALID_ARG, "range out of bounds");
+    for (int64_t k = 0; k < count; ++k) {
+      const GemmDesc& d = plan->descs[first + k];
+      mnk[3 * k] = d.M;
+      mnk[3 * k + 1] = d.N;
+      mnk[3 * k + 2] = d.K;
+    }
+  });
+}
+
+tk_status tk_permute_map(const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q, int32_t nq,
+                         const tk_tensor* C, int64_t* dst_block, int32_t* sign) {
+  return guarded([&] {
+    if (!A || !C || !dst_block || !sign) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto pv = to_vec(p, np, "p");
+    auto qv = to_vec(q, nq, "q");
+    check_perm(pv, qv, A->st->N());
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    if (c != C->st->cod || d != C->st->dom) fail(TK_ERR_SPACE_MISMATCH, "C does not have the permuted spaces");
+    TaskList dummy;
+    std::vector<int64_t> m;
+    std::vector<int32_t> sg;
+    plan_permute_tasks(*A->st, pv, qv, *C->st, 0, 0, false, dummy, &m, &sg);
+    std::copy(m.begin(), m.end(), dst_block);
+    std::copy(sg.begin(), sg.end(), sign);
+  });
+}
+
+tk_status tk_tensor_contract(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA, const int32_t* qA,
+                             int32_t nqA, const tk_tensor* B, const int32_t* pB, int32_t npB, const int32_t* qB,
+                             int32_t nqB, const int32_t* pAB, int32_t npAB, const int32_t* qAB, int32_t nqAB,
+                             double alpha, double beta, int32_t precision, tk_tensor* C, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !B || !C) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto pa = to_vec(pA, npA, "pA"), qa = to_vec(qA, nqA, "qA"), pb = to_vec(pB, npB, "pB"), qb = to_vec(qB, nqB, "qB");
+    auto pab = to_vec(pAB, npAB, "pAB"), qab = to_vec(qAB, nqAB, "qAB");
+    const std::string key = plan_key(A, pa, qa, B, pb, qb, pab, qab, precision, C);
+    std::shared_ptr<tk_plan> P;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      auto it = ctx->plans.find(key);
+      if (it != ctx->plans.end()) P = it->second;
+    }
+    if (!P) {
+      P = std::shared_ptr<tk_plan>(build_contract_plan(ctx, A, pa, qa, B, pb, qb, pab, qab, precision, C).release());
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->plans[key] = P;
+    }
+    execute_plan(*P, A, B, C, alpha, beta, static_cast<hipStream_t>(stream));
+  });
+}
+
+tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mn) {
+  return guarded([&] {
+    if (!count) fail(TK_ERR_INVALID_ARG, "null count");
+    *count = tk::num_tile_shapes();
+    if (tile_mn)
+      for (int i = 0; i < *count; ++i) tk::tile_shape(i, &tile_mn[2 * i], &tile_mn[2 * i + 1]);
+  });
+}
+
+tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    if (!tk::gemm_tile_supported(plan->dtype, plan->precision, tile_m, tile_n)) fail(TK_ERR_UNSUPPORTED, "tile shape not available");
+    plan_reschedule(*plan, tile_m, tile_n);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Append the task list `src` of member plan i to `dst`, shifting buffer ids.
+void merge_tasks(TaskList& dst, const TaskList& src, int member) {
+  const int base = static_cast<int>(dst.tasks.size());
+  for (PermTask t : src.tasks) {
+    if (t.src_buf >= 0) t.src_buf = static_cast<int16_t>(t.src_buf + member * tk::kBufsPerPlan);
+    t.dst_buf = static_cast<int16_t>(t.dst_buf + member * tk::kBufsPerPlan);
+    dst.tasks.push_back(t);
+  }
+  for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
+}
+
+void batch_launch_all(tk_batch& b, hipStream_t stream) {
+  tk::Ptrs ptrs{};
+  ptrs.table = static_cast<const uint64_t*>(b.d_table.p);
+  if (b.pre.nwg() > 0)
+    hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.pre.d_tasks.p),
+                                 static_cast<const int32_t*>(b.pre.d_wg.p), b.pre.nwg(), ptrs, 1.0, 0.0, stream),
+              "permute launch");
+  if (!b.descs.empty()) {
+    tk::GemmArgs ga{};
+    ga.descs = static_cast<const GemmDesc*>(b.d_descs.p);
+    ga.tiles = static_cast<const GemmTile*>(b.d_tiles.p);
+    ga.wg_first = static_cast<const int32_t*>(b.d_wg.p);
+    ga.row_map = static_cast<const LegMap*>(b.d_rowmap.p);
+    ga.col_map = static_cast<const LegMap*>(b.d_colmap.p);
+    ga.pairs = static_cast<const PairDesc*>(b.d_pairs.p);
+    ga.ptrs = ptrs;
+    ga.alpha = b.alpha;
+    ga.beta = b.beta;
+    hip_check(tk::launch_gemm(b.dtype, b.precision, b.tile_m, b.tile_n, ga, static_cast<int>(b.wg_first.size()) - 1,
+                              stream),
+              "gemm launch");
+  }
+  if (b.zero.nwg() > 0)
+    hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
+                                 static_cast<const int32_t*>(b.zero.d_wg.p), b.zero.nwg(), ptrs, b.alpha, b.beta,
+                                 stream),
+              "zero launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tensor* const* A, const tk_tensor* const* B,
+                          tk_tensor* const* C, int32_t n, double alpha, double beta, tk_batch** out) {
+  return guarded([&] {
+    if (!ctx || !plans || !A || !B || !C || !out || n < 1) fail(TK_ERR_INVALID_ARG, "bad batch arguments");
+    auto b = std::make_unique<tk_batch>();
+    b->ctx = ctx;
+    b->n = n;
+    b->alpha = alpha;
+    b->beta = beta;
+    b->dtype = plans[0]->dtype;
+    b->precision = plans[0]->precision;
+    std::vector<uint64_t> table;
+    for (int i = 0; i < n; ++i) {
+      tk_plan& P = *plans[i];
+      if (!P.ctx) fail(TK_ERR_INVALID_ARG, "batch member plan made without a context");
+      if (P.dtype != b->dtype || P.precision != b->precision) fail(TK_ERR_DTYPE, "batch members differ in dtype / precision");
+      if (P.post) fail(TK_ERR_UNSUPPORTED, "batch members need a fusable output permute (<= 4 legs per side)");
+      check_exec_tensor(A[i], P.A, P.dtype, "A");
+      check_exec_tensor(B[i], P.B, P.dtype, "B");
+      check_exec_tensor(C[i], P.C, P.dtype, "C");
+      const size_t es = A[i]->esize();
+      auto wa = std::make_unique<DevBuf>(), wb = std::make_unique<DevBuf>();
+      if (P.permA) wa->alloc(P.At->size * es);
+      if (P.permB) wb->alloc(P.Bt->size * es);
+      table.push_back(reinterpret_cast<uint64_t>(A[i]->data));
+      table.push_back(reinterpret_cast<uint64_t>(B[i]->data));
+      table.push_back(reinterpret_cast<uint64_t>(C[i]->data));
+      table.push_back(reinterpret_cast<uint64_t>(wa->p));
+      table.push_back(reinterpret_cast<uint64_t>(wb->p));
+      table.push_back(0);
+      b->ws.push_back(std::move(wa));
+      b->ws.push_back(std::move(wb));
+      merge_tasks(b->pre, P.pre, i);
+      merge_tasks(b->zero, P.zero, i);
+      const int32_t rb = static_cast<int32_t>(b->row_map.size()), cb = static_cast<int32_t>(b->col_map.size());
+      const int32_t pb = static_cast<int32_t>(b->pairs.size());
+      for (GemmDesc d : P.descs) {
+        d.a_buf = static_cast<int16_t>(d.a_buf + i * tk::kBufsPerPlan);
+        d.b_buf = static_cast<int16_t>(d.b_buf + i * tk::kBufsPerPlan);
+        d.c_buf = static_cast<int16_t>(d.c_buf + i * tk::kBufsPerPlan);
+        if (d.mode == 1) {
+          d.row_map += rb;
+          d.col_map += cb;
+          d.pair_base += pb;
+        }
+        b->descs.push_back(d);
+      }
+      b->row_map.insert(b->row_map.end(), P.row_map.begin(), P.row_map.end());
+      b->col_map.insert(b->col_map.end(), P.col_map.begin(), P.col_map.end());
+      b->pairs.insert(b->pairs.end(), P.pairs.begin(), P.pairs.end());
+      b->flops += P.flops;
+    }
+    if (b->descs.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many GEMMs");
+    int tm, tn;
+    choose_default_tile(b->descs, &tm, &tn);
+    b->tile_m = tm;
+    b->tile_n = tn;
+    schedule_tiles(b->descs, tm, tn, ctx->num_cu, b->tiles, b->wg_first);
+    b->pre.upload();
+    b->zero.upload();
+    b->d_descs.upload(b->descs);
+    b->d_rowmap.upload(b->row_map);
+    b->d_colmap.upload(b->col_map);
+    b->d_pairs.upload(b->pairs);
+    b->d_tiles.upload(b->tiles);
+    b->d_wg.upload(b->wg_first);
+    b->d_table.upload(table);
+    *out = b.release();
+  });
+}
+
+tk_status tk_batch_launch(tk_batch* batch, void* stream) {
+  return guarded([&] {
+    if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
+    batch_launch_all(*batch, static_cast<hipStream_t>(stream));
+  });
+}
+
+tk_status tk_batch_capture(tk_batch* batch, void* stream) {
+  return guarded([&] {
+    if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
+    if (!stream) fail(TK_ERR_INVALID_ARG, "graph capture needs a non-null stream");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (batch->exec) {
+      (void)hipGraphExecDestroy(batch->exec);
+      batch->exec = nullptr;
+    }
+    if (batch->graph) {
+      (void)hipGraphDestroy(batch->graph);
+      batch->graph = nullptr;
+    }
+    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      batch_launch_all(*batch, s);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hip_check(hipStreamEndCapture(s, &batch->graph), "hipStreamEndCapture");
+    hip_check(hipGraphInstantiate(&batch->exec, batch->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  });
+}
+
+tk_status tk_batch_replay(tk_batch* batch, void* stream) {
+  return guarded([&] {
+    if (!batch || !batch->exec) fail(TK_ERR_INVALID_ARG, "batch has no captured graph");
+    hip_check(hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+  });
+}
+
+tk_status tk_batch_info(const tk_batch* batch, int64_t* ngemm, int64_t* ntiles, double* flops, int32_t* tile_m,
+                        int32_t* tile_n) {
+  return guarded([&] {
+    if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
+    if (ngemm) *ngemm = static_cast<int64_t>(batch->descs.size());
+    if (ntiles) *ntiles = static_cast<int64_t>(batch->tiles.size());
+    if (flops) *flops = batch->flops;
+    if (tile_m) *tile_m = batch->tile_m;
+    if (tile_n) *tile_n = batch->tile_n;
+  });
+}
+
+tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n) {
+  return guarded([&] {
+    if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
+    if (!tk::gemm_tile_supported(batch->dtype, batch->precision, tile_m, tile_n))
+      fail(TK_ERR_UNSUPPORTED, "tile shape not available");
+    batch->tile_m = tile_m;
+    batch->tile_n = tile_n;
+    schedule_tiles(batch->descs, tile_m, tile_n, batch->ctx->num_cu, batch->tiles, batch->wg_first);
+    batch->d_tiles.upload(batch->tiles);
+    batch->d_wg.upload(batch->wg_first);
+    if (batch->exec) {
+      (void)hipGraphExecDestroy(batch->exec);
+      batch->exec = nullptr;
+    }
+    if (batch->graph) {
+      (void)hipGraphDestroy(batch->graph);
+      batch->graph = nullptr;
+    }
+  });
+}
+
+tk_status tk_batch_destroy(tk_batch* batch) {
+  return guarded([&] { delete batch; });
+}
+
+}  // extern "C"

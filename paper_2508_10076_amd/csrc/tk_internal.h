@@ -1,0 +1,110 @@
+// Internal descriptors shared by the host planner (tk_host.cpp) and the
+// device kernels (tk_kernels.hip).  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace tk {
+
+constexpr int kMaxDims = 8;   // dims of one block task after merging
+constexpr int kPermChunk = 4096;  // elements a permute workgroup handles per visit
+constexpr int kThreads = 256;
+
+// Buffer ids used by task descriptors.  A plan reads/writes at most these
+// six buffers (operands, result, and workspaces for A~, B~ and, when the
+// output permute cannot be fused, C~); a batch offsets them by kBufsPerPlan
+// per member plan.
+enum BufId : int16_t { kBufA = 0, kBufB = 1, kBufC = 2, kBufAt = 3, kBufBt = 4, kBufCt = 5 };
+constexpr int kBufsPerPlan = 6;
+
+// Base pointers: either inline (single plan) or a device table (batch).
+struct Ptrs {
+  void* p[kBufsPerPlan];
+  const uint64_t* table;  // when non-null, buffer id i resolves to table[i]
+};
+
+// One chunk of one block for the permute / zero-fill kernel.  The block is an
+// n-dimensional array in OUTPUT leg order (dim 0 fastest); element with
+// multi-index i sits at src + sum i_d*ss[d] in the source buffer and at
+// dst + sum i_d*ds[d] in the destination.  The chunk covers output-linear
+// indices start .. start+count-1.  src_buf < 0 means "no source": the value
+// is zero (used for coupled charges whose K range is empty).
+struct PermTask {
+  int64_t src;
+  int64_t dst;
+  int32_t n;
+  int32_t count;
+  int32_t start;
+  int16_t src_buf;
+  int16_t dst_buf;
+  float sign;
+  int32_t pad_;
+  int32_t dim[kMaxDims];
+  int32_t ss[kMaxDims];
+  int32_t ds[kMaxDims];
+};
+
+// One sector GEMM  C~^c (M x N) = A~^c (M x K) * B~^c (K x N), all
+// column-major.  mode 0: C~^c is written in place at c (ldc).  mode 1: the
+// epilogue scatters every element to its position in C (fused output
+// permute) through the row/column maps and the channel-pair table.
+struct GemmDesc {
+  int64_t a, b, c;
+  int32_t M, N, K;
+  int32_t lda, ldb, ldc;
+  int16_t a_buf, b_buf, c_buf, mode;
+  int32_t row_map;    // first entry of this sector in the row map
+  int32_t col_map;    // first entry in the column map
+  int32_t pair_base;  // first entry in the pair table
+  int32_t ncc;        // column channels of this sector (pair = rc * ncc + cc)
+  int32_t pad_;
+};
+
+struct GemmTile {
+  int32_t gemm;
+  int32_t m0;
+  int32_t n0;
+  int32_t pad_;
+};
+
+// Row (or column) r of a sector of C~: its channel inside the sector and the
+// index of each of its legs (up to 4 legs per side, 16 bits each).
+struct LegMap {
+  int32_t chan;
+  int32_t pad_;
+  uint16_t idx[4];
+};
+
+// Output placement of the channel pair (row channel, column channel) of C~:
+// element (r, s) goes to base + sum_l row_idx_l * S[l] + sum_l col_idx_l * S[4+l],
+// multiplied by sign.
+struct PairDesc {
+  int64_t base;
+  float sign;
+  int32_t pad_;
+  int32_t S[8];
+};
+
+struct GemmArgs {
+  const GemmDesc* descs;
+  const GemmTile* tiles;     // tiles grouped by workgroup
+  const int32_t* wg_first;   // workgroup w handles tiles wg_first[w] .. wg_first[w+1]-1
+  const LegMap* row_map;
+  const LegMap* col_map;
+  const PairDesc* pairs;
+  Ptrs ptrs;
+  double alpha, beta;
+};
+
+// Launchers (tk_kernels.hip).  dtype: 0 fp64, 1 fp32.  precision: tk_precision.
+hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
+                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
+hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+                       int nwg, hipStream_t stream);
+bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n);
+int num_tile_shapes();
+void tile_shape(int i, int* tm, int* tn);
+
+}  // namespace tk

@@ -1,0 +1,240 @@
+// Device kernels of the symmetric-TensorMap library, written for CDNA4
+// (gfx950, 64-wide wavefronts, MFMA, 160 KiB LDS per CU).
+//
+//  * permute_kernel: Alg. "Abelian Tensor Permutation" executed as a list of
+//    block tasks (one fusion channel, or a chunk of one); also writes the
+//    zero blocks of coupled charges with an empty K range.
+//  * gemm_f64_kernel: persistent grouped GEMM over the coupled charges of a
+//    contraction (eq. abelian_compostion), fp64 MFMA 16x16x4; its epilogue
+//    applies the output permute of Alg. "Abelian tensor contraction" by
+//    scattering every element straight to its place in C.
+#include <hip/hip_runtime.h>
+
+#include "tk_internal.h"
+
+namespace tk {
+
+template <typename T>
+__device__ __forceinline__ T* buf_ptr(const Ptrs& P, int id) {
+  return reinterpret_cast<T*>(P.table ? reinterpret_cast<void*>(P.table[id]) : P.p[id]);
+}
+
+// ---------------------------------------------------------------------------
+// permute / zero-fill
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __restrict__ tasks,
+                                                           const int32_t* __restrict__ wg_first,
+                                                           Ptrs P, double alpha, double beta) {
+  const int t0 = wg_first[blockIdx.x];
+  const int t1 = wg_first[blockIdx.x + 1];
+  for (int t = t0; t < t1; ++t) {
+    const PermTask* tk = tasks + t;
+    const int n = tk->n;
+    const int count = tk->count;
+    const uint32_t start = static_cast<uint32_t>(tk->start);
+    const float sign = tk->sign;
+    int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
+#pragma unroll
+    for (int d = 0; d < kMaxDims; ++d) {
+      dim[d] = tk->dim[d];
+      ss[d] = tk->ss[d];
+      ds[d] = tk->ds[d];
+    }
+    T* dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+    const T* src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
+    for (int e = threadIdx.x; e < count; e += kThreads) {
+      uint32_t lin = start + static_cast<uint32_t>(e);
+      int64_t so = 0, dof = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < n) {
+          const uint32_t ext = static_cast<uint32_t>(dim[d]);
+          const uint32_t q = lin / ext;
+          const uint32_t i = lin - q * ext;
+          lin = q;
+          so += static_cast<int64_t>(i) * ss[d];
+          dof += static_cast<int64_t>(i) * ds[d];
+        }
+      }
+      T v = src ? static_cast<T>(src[so] * static_cast<T>(sign)) : static_cast<T>(0);
+      v = static_cast<T>(alpha) * v;
+      if (beta != 0.0) v += static_cast<T>(beta) * dst[dof];
+      dst[dof] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grouped sector GEMM, fp64 MFMA
+// ---------------------------------------------------------------------------
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// Epilogue store of one accumulated element of C~ (row r, column s of the
+// sector GEMM d): in place (mode 0) or scattered into C (mode 1).
+template <typename TC>
+__device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc& d, TC* Cbase, int r,
+                                           int s, double acc) {
+  if (r >= d.M || s >= d.N) return;
+  int64_t idx;
+  double scale = args.alpha;
+  if (d.mode == 0) {
+    idx = d.c + static_cast<int64_t>(s) * d.ldc + r;
+  } else {
+    const LegMap rm = args.row_map[d.row_map + r];
+    const LegMap cm = args.col_map[d.col_map + s];
+    const PairDesc& pd = args.pairs[d.pair_base + static_cast<int64_t>(rm.chan) * d.ncc + cm.chan];
+    idx = pd.base;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      idx += static_cast<int64_t>(rm.idx[l]) * pd.S[l] + static_cast<int64_t>(cm.idx[l]) * pd.S[4 + l];
+    }
+    scale *= pd.sign;
+  }
+  double v = scale * acc;
+  if (args.beta != 0.0) v += args.beta * static_cast<double>(Cbase[idx]);
+  Cbase[idx] = static_cast<TC>(v);
+}
+
+// Workgroup = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
+// sub-tile made of 16 x 16 MFMA tiles.  K advances in steps of 16 staged
+// through LDS: A as [k][m] (m contiguous, as in HBM), B as [n][k]
+// (k contiguous, as in HBM), so every global load is coalesced along the
+// contiguous axis.  Within one MFMA the k index is lane/16; step j of the 4
+// steps of a stage uses k = 4*(lane/16) + j for both operands.
+template <int BM, int BN>
+__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
+  constexpr int BK = 16;
+  constexpr int APAD = 2, BPAD = 2;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_TPM = kThreads / BM;     // threads sharing one m row
+  constexpr int A_LD = BK / A_TPM;         // A loads per thread per stage
+  constexpr int B_LD = BN / 16;            // B loads per thread per stage
+  static_assert(kThreads % BM == 0 && BK % A_TPM == 0, "tile");
+  __shared__ double As[BK][BM + APAD];
+  __shared__ double Bs[BN][BK + BPAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const int a_m = tid % BM, a_k = tid / BM;
+  const int b_k = tid & 15, b_n = tid >> 4;
+
+  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
+    const GemmTile tile = args.tiles[ti];
+    const GemmDesc d = args.descs[tile.gemm];
+    const double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a;
+    const double* B = buf_ptr<const double>(args.ptrs, d.b_buf) + d.b;
+    double* C = buf_ptr<double>(args.ptrs, d.c_buf);
+
+    d4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+    double ra[A_LD], rb[B_LD];
+    const int am = tile.m0 + a_m;
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const int k = k0 + a_k + A_TPM * i;
+        ra[i] = (am < d.M && k < d.K) ? A[static_cast<int64_t>(k) * d.lda + am] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) {
+        const int n = tile.n0 + b_n + 16 * i;
+        const int k = k0 + b_k;
+        rb[i] = (n < d.N && k < d.K) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
+      }
+    };
+
+    gload(0);
+    for (int k0 = 0; k0 < d.K; k0 += BK) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) As[a_k + A_TPM * i][a_m] = ra[i];
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) Bs[b_n + 16 * i][b_k] = rb[i];
+      __syncthreads();
+      if (k0 + BK < d.K) gload(k0 + BK);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double af[TM], bf[TN];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) af[mi] = As[4 * g + j][wm + 16 * mi + l16];
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[wn + 16 * ni + l16][4 * g + j];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < TN; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+      }
+    }
+
+    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16, row = 4*(lane/16) + v
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + 4 * g + v,
+                             tile.n0 + wn + 16 * ni + l16, acc[mi][ni][v]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
+                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(permute_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+                       ptrs, alpha, beta);
+  else
+    hipLaunchKernelGGL(permute_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+                       ptrs, alpha, beta);
+  return hipGetLastError();
+}
+
+struct TileShape {
+  int m, n;
+};
+static const TileShape kTiles[] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
+
+int num_tile_shapes() { return static_cast<int>(sizeof(kTiles) / sizeof(kTiles[0])); }
+void tile_shape(int i, int* tm, int* tn) {
+  *tm = kTiles[i].m;
+  *tn = kTiles[i].n;
+}
+
+bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n) {
+  if (dtype != 0 || precision != 0) return false;
+  for (const auto& t : kTiles)
+    if (t.m == tile_m && t.n == tile_n) return true;
+  return false;
+}
+
+hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+                       int nwg, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n)) return hipErrorInvalidValue;
+#define TK_GEMM_CASE(BM_, BN_)                                                                   \
+  if (tile_m == BM_ && tile_n == BN_) {                                                          \
+    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_>), dim3(nwg), dim3(kThreads), 0, stream, args); \
+    return hipGetLastError();                                                                    \
+  }
+  TK_GEMM_CASE(128, 128)
+  TK_GEMM_CASE(128, 64)
+  TK_GEMM_CASE(64, 128)
+  TK_GEMM_CASE(64, 64)
+#undef TK_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace tk

@@ -1,0 +1,232 @@
+"""Host-side checks of the C-ABI library (no GPU): exported symbols, block
+structure, permute channel maps and signs, contraction plans and error paths,
+all compared with the oracle (bit-exact: this is integer work)."""
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import blockwise
+from oracle.graded import Structure, permute_spaces
+from paper_2508_10076_amd import synth
+from tests.helpers import ospace, ostruct
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+tk = pytest.importorskip("paper_2508_10076_amd.tk")
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tk.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tk_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 30
+    out = subprocess.run(["nm", "-D", "--defined-only", tk.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    exported = set(ln.split()[-1] for ln in out.splitlines() if " T " in ln)
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_binding_refuses_to_run_without_library(tmp_path):
+    """The product path has no fallback: without libtk.so the import fails."""
+    pkg = tmp_path / "paper_2508_10076_amd"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text("")
+    (pkg / "tk.py").write_text(open(os.path.join(ROOT, "paper_2508_10076_amd", "tk.py")).read())
+    r = subprocess.run([sys.executable, "-c", "import paper_2508_10076_amd.tk"], cwd=tmp_path,
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert r.returncode != 0 and "libtk.so is missing" in r.stdout
+
+
+def lib_tensor(t):
+    return tk.tensor_create(None, t["sym"], t["cod"], t["dom"])
+
+
+def oracle_blocks(st: Structure):
+    idx, off, ld = [], [], []
+    for c, a, b, o, R in st.channels():
+        idx.append(list(a) + list(b))
+        off.append(o)
+        ld.append(R)
+    return np.array(idx, np.int64).reshape(len(off), st.N1 + st.N2), np.array(off), np.array(ld)
+
+
+def random_tdict(rng, sym, n1, n2, **kw):
+    while True:
+        t = dict(sym=sym, cod=[synth.random_space(rng, sym, **kw) for _ in range(n1)],
+                 dom=[synth.random_space(rng, sym, **kw) for _ in range(n2)])
+        if ostruct(t).size:
+            return t
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_block_structure_matches_oracle(sym):
+    rng = np.random.default_rng(17)
+    for _ in range(10):
+        t = random_tdict(rng, sym, int(rng.integers(0, 4)), int(rng.integers(0, 4)))
+        st = ostruct(t)
+        T = lib_tensor(t)
+        assert T.nelem == st.size
+        assert T.nblocks == sum(1 for _ in st.channels())
+        idx, off, ld = T.blocks()
+        oi, oo, ol = oracle_blocks(st)
+        assert np.array_equal(idx, oi) and np.array_equal(off, oo) and np.array_equal(ld, ol)
+        ch, r, c, o = T.sectors()
+        assert [tuple(x) for x in ch] == st.sectors
+        assert list(r) == [st.rows[k].total for k in st.sectors]
+        assert list(c) == [st.cols[k].total for k in st.sectors]
+        assert list(o) == [st.sector_offset[k] for k in st.sectors]
+        for leg in range(len(t["cod"]) + len(t["dom"])):
+            sp = (t["cod"] + t["dom"])[leg]
+            got = T.space(leg)
+            assert (tuple(map(tuple, got[0])), tuple(got[1]), got[2]) == (sp.sectors, sp.degs, sp.dual)
+
+
+def test_workload_structures_match_oracle():
+    cfg = synth.config2()
+    for name, t in cfg["tensors"].items():
+        st = ostruct(t)
+        T = lib_tensor(t)
+        idx, off, ld = T.blocks()
+        oi, oo, ol = oracle_blocks(st)
+        assert np.array_equal(idx, oi) and np.array_equal(off, oo), name
+
+
+@pytest.mark.parametrize("sym", ["U1", "Z2", "FZ2", "U1xFZ2"])
+def test_permute_map_and_signs_match_oracle(sym):
+    rng = np.random.default_rng(23)
+    for _ in range(12):
+        n1, n2 = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        if n1 + n2 == 0:
+            continue
+        t = random_tdict(rng, sym, n1, n2, max_deg=2)
+        st = ostruct(t)
+        perm = [int(x) for x in rng.permutation(n1 + n2)]
+        k = int(rng.integers(0, n1 + n2 + 1))
+        p, q = perm[:k], perm[k:]
+        A = lib_tensor(t)
+        Cn = tk.tensor_create_permuted(None, A, p, q)
+        stC = Structure(sym, *permute_spaces(st.cod, st.dom, p, q))
+        assert Cn.nelem == stC.size
+        dst, sign = tk.permute_map(A, p, q, Cn)
+        cidx = {(tuple(a), tuple(b)): i for i, (_, a, b, _, _) in enumerate(stC.channels())}
+        for i, (c, a, b, o, R) in enumerate(st.channels()):
+            tup = tuple(a) + tuple(b)
+            e = tuple(tup[j] for j in p)
+            f = tuple(tup[j] for j in q)
+            assert dst[i] == cidx[(e, f)]
+            want = -1 if blockwise.koszul_parity(sym, st.cod, st.dom, tup, p, q) else 1
+            assert sign[i] == want
+
+
+def _plan_case(rng, sym):
+    """A random valid contraction (as in the oracle pins)."""
+    while True:
+        tA = random_tdict(rng, sym, int(rng.integers(1, 3)), int(rng.integers(1, 3)), max_deg=3)
+        stA = ostruct(tA)
+        nA = stA.N1 + stA.N2
+        k = int(rng.integers(1, nA + 1))
+        legs = [int(x) for x in rng.permutation(nA)]
+        qA, pA = legs[:k], legs[k:]
+        _, Adom = permute_spaces(stA.cod, stA.dom, pA, qA)
+        free = [synth.random_space(rng, sym, max_deg=3) for _ in range(int(rng.integers(0, 3)))]
+        Bt = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in Adom], dom=free)
+        stBt = ostruct(Bt)
+        if not stBt.size:
+            continue
+        nB = k + len(free)
+        order = [int(x) for x in rng.permutation(nB)]
+        n1B = int(rng.integers(0, nB + 1))
+        stB, _ = blockwise.permute(stBt, {}, order[:n1B], order[n1B:])
+        inv = [0] * nB
+        for n, l in enumerate(order):
+            inv[l] = n
+        pB, qB = inv[:k], inv[k:]
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.cod],
+                  dom=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.dom])
+        if not stB.size:
+            continue
+        nC = len(pA) + len(qB)
+        oc = [int(x) for x in rng.permutation(nC)]
+        n1C = int(rng.integers(0, nC + 1))
+        return tA, pA, qA, tB, pB, qB, oc[:n1C], oc[n1C:]
+
+
+@pytest.mark.parametrize("sym", ["U1", "U1xFZ2"])
+def test_contract_plan_matches_oracle(sym):
+    rng = np.random.default_rng(31)
+    for _ in range(10):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _plan_case(rng, sym)
+        A, B = lib_tensor(tA), lib_tensor(tB)
+        Cn = tk.tensor_create_contracted(None, A, pA, qA, B, pB, qB, pAB, qAB)
+        stA, stB = ostruct(tA), ostruct(tB)
+        stC, _ = blockwise.contract(stA, {}, pA, qA, stB, {}, pB, qB, pAB, qAB)
+        assert Cn.nelem == stC.size
+        P = tk.Plan(None, A, pA, qA, B, pB, qB, pAB, qAB, Cn)
+        info = P.info()
+        assert info["flops"] == blockwise.useful_flops(stA, pA, qA, stB, pB, qB)
+        # sector GEMM shapes
+        sAt = Structure(sym, *permute_spaces(stA.cod, stA.dom, pA, qA))
+        sBt = Structure(sym, *permute_spaces(stB.cod, stB.dom, pB, qB))
+        want = sorted((sAt.rows[c].total, sBt.cols[c].total, sAt.cols[c].total)
+                      for c in sAt.sectors if c in sBt.sectors)
+        assert sorted(map(tuple, P.gemms().tolist())) == want
+        P.close()
+
+
+def test_heff_plan_flops_match_survey_sizes():
+    cfg = synth.config2()
+    t = {k: lib_tensor(v) for k, v in cfg["tensors"].items()}
+    st = {k: ostruct(v) for k, v in cfg["tensors"].items()}
+    total = 0
+    for out, a, b, call in cfg["calls"]:
+        Cn = tk.tensor_create_contracted(None, t[a], call["pA"], call["qA"], t[b], call["pB"], call["qB"],
+                                         call["pAB"], call["qAB"])
+        P = tk.Plan(None, t[a], call["pA"], call["qA"], t[b], call["pB"], call["qB"], call["pAB"], call["qAB"], Cn)
+        f = P.info()["flops"]
+        sC, _ = blockwise.contract(st[a], {}, call["pA"], call["qA"], st[b], {}, call["pB"], call["qB"],
+                                   call["pAB"], call["qAB"])
+        assert f == blockwise.useful_flops(st[a], call["pA"], call["qA"], st[b], call["pB"], call["qB"])
+        t[out], st[out] = Cn, sC
+        total += f
+    assert 4.0e8 < total < 4.8e8
+
+
+def test_error_paths():
+    V = synth.u1_space([-1, 0, 1], [1, 2, 1])
+    P = synth.P_U1
+    A = tk.tensor_create(None, "U1", [V, P], [V])
+    with pytest.raises(tk.TkError) as e:
+        tk.tensor_create_permuted(None, A, [0, 0], [2])
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:     # contracted spaces differ (P vs V)
+        tk.tensor_create_contracted(None, A, [0, 2], [1], A, [0], [1, 2], [0, 1], [2, 3])
+    assert e.value.status == 2
+    with pytest.raises(tk.TkError) as e:     # parity 2 is not a Z2 label
+        tk.tensor_create(None, "Z2", [synth.space([(2,)], [1])], [])
+    assert e.value.status == 3
+    with pytest.raises(tk.TkError) as e:     # repeated sector
+        tk.tensor_create(None, "U1", [synth.u1_space([0, 0], [1, 1])], [])
+    assert e.value.status == 3
+    with pytest.raises(tk.TkError) as e:     # rank above the limit
+        tk.tensor_create(None, "U1", [V] * 5, [V] * 4)
+    assert e.value.status == 5
+    with pytest.raises(tk.TkError) as e:     # unknown dtype
+        tk.tensor_create(None, "U1", [V], [V], dtype=7)
+    assert e.value.status == 4
+    with pytest.raises(tk.TkError) as e:     # plan with mismatched C
+        Cn = tk.tensor_create(None, "U1", [V], [V])
+        tk.Plan(None, A, [0, 1], [2], A, [0], [1, 2], [0, 1], [2, 3], Cn)
+    assert e.value.status == 2
+    with pytest.raises(tk.TkError) as e:     # execution needs a context
+        B = tk.tensor_create(None, "U1", [V, P], [V])
+        Cn = tk.tensor_create_contracted(None, A, [0, 1], [2], B, [0], [1, 2], [0, 1], [2, 3])
+        pl = tk.Plan(None, A, [0, 1], [2], B, [0], [1, 2], [0, 1], [2, 3], Cn)
+        pl.execute(A, B, Cn, stream=0)
+    assert e.value.status == 1

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Integer and index work (block structure, placement, signs) is checked
+bit-exactly: permutes on any data, contractions on small-integer data (exact
+in fp64).  Gaussian fp64 data is held to 1e-12 normwise and entrywise
+relative to |A||B| (an fp64 dot product of length K has error below
+K u (|A||B|)_ij with u = 2^-53, i.e. < 3e-13 for every K used here).
+"""
+import numpy as np
+import pytest
+
+from oracle import blockwise, dense
+from oracle.graded import Structure, permute_spaces
+from paper_2508_10076_amd import synth
+from tests.helpers import ospace, ostruct
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2508_10076_amd import tk  # noqa: E402
+from tests.gpu_util import assert_close, download, fill, upload  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tk.Context(0)
+    yield c
+    torch.cuda.synchronize()
+
+
+def make(ctx, t, vec=None, dtype="f64"):
+    T = tk.tensor_create(ctx, t["sym"], t["cod"], t["dom"], dtype=dtype)
+    if vec is not None:
+        upload(T, vec)
+    return T
+
+
+def random_tdict(rng, sym, n1, n2, **kw):
+    while True:
+        t = dict(sym=sym, cod=[synth.random_space(rng, sym, **kw) for _ in range(n1)],
+                 dom=[synth.random_space(rng, sym, **kw) for _ in range(n2)])
+        if ostruct(t).size:
+            return t
+
+
+def int_vec(rng, n):
+    return rng.integers(-3, 4, size=n).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# permute (Alg. "Abelian Tensor Permutation")
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_permute_bit_exact(ctx, sym):
+    rng = np.random.default_rng(1000 + len(sym))
+    for trial in range(12):
+        n1, n2 = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        if n1 + n2 == 0:
+            continue
+        t = random_tdict(rng, sym, n1, n2, max_deg=4)
+        st = ostruct(t)
+        v = rng.standard_normal(st.size)
+        perm = [int(x) for x in rng.permutation(n1 + n2)]
+        k = int(rng.integers(0, n1 + n2 + 1))
+        p, q = perm[:k], perm[k:]
+        A = make(ctx, t, v)
+        Cg = tk.tensor_create_permuted(ctx, A, p, q)
+        fill(Cg)
+        tk.tensor_permute(ctx, A, p, q, Cg)
+        _, ref = blockwise.permute_storage(st, v, p, q)
+        got = download(Cg)
+        assert np.array_equal(got, ref), (sym, trial, p, q)
+
+
+def test_permute_large_blocks(ctx):
+    """Blocks larger than one workgroup chunk, odd sizes, all strides."""
+    rng = np.random.default_rng(5)
+    V = synth.u1_space([-1, 0, 1], [37, 101, 53])
+    W = synth.u1_space([0, 1], [3, 5])
+    t = dict(sym="U1", cod=[V, W], dom=[V])
+    st = ostruct(t)
+    v = rng.standard_normal(st.size)
+    A = make(ctx, t, v)
+    for p, q in [((2, 0), (1,)), ((1,), (2, 0)), ((0, 2, 1), ()), ((), (1, 0, 2))]:
+        Cg = tk.tensor_create_permuted(ctx, A, p, q)
+        fill(Cg)
+        tk.tensor_permute(ctx, A, p, q, Cg)
+        _, ref = blockwise.permute_storage(st, v, p, q)
+        assert np.array_equal(download(Cg), ref), (p, q)
+
+
+def test_adjoint_bit_exact(ctx):
+    rng = np.random.default_rng(6)
+    for sym in ("U1", "U1xFZ2"):
+        t = random_tdict(rng, sym, 2, 3, max_deg=5)
+        st = ostruct(t)
+        v = rng.standard_normal(st.size)
+        A = make(ctx, t, v)
+        Cg = tk.tensor_adjoint(ctx, A)
+        sta, b = blockwise.adjoint(st, st.to_blocks(v))
+        assert np.array_equal(download(Cg), sta.from_blocks(b))
+
+
+# ---------------------------------------------------------------------------
+# contraction (Alg. "Abelian tensor contraction")
+# ---------------------------------------------------------------------------
+def _contract_case(rng, sym, max_deg=4):
+    from tests.test_abi_host import _plan_case  # same generator as the host tests
+    return _plan_case(rng, sym)
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_contract_random_integer_bit_exact(ctx, sym):
+    rng = np.random.default_rng(2000 + len(sym))
+    for trial in range(10):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _contract_case(rng, sym)
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        fill(Cg)
+        tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, C_=Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB)
+        assert np.array_equal(download(Cg), ref), (sym, trial)
+
+
+def test_contract_fermionic_against_graph_evaluator(ctx):
+    """U(1) x fZ2: the GPU result against the dense graph evaluator (O1)."""
+    rng = np.random.default_rng(77)
+    sym = "U1xFZ2"
+    for trial in range(10):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _contract_case(rng, sym)
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        D, dcod, ddom = dense.contract_dense(sym, stA.to_dense(a), stA.cod, stA.dom, pA, qA,
+                                             stB.to_dense(b), stB.cod, stB.dom, pB, qB, pAB, qAB)
+        stC = Structure(sym, dcod, ddom)
+        assert np.array_equal(stC.to_dense(download(Cg)), D), trial
+
+
+def test_contract_alpha_beta(ctx):
+    rng = np.random.default_rng(8)
+    tA, pA, qA, tB, pB, qB, pAB, qAB = _contract_case(rng, "U1")
+    stA, stB = ostruct(tA), ostruct(tB)
+    a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+    A, B = make(ctx, tA, a), make(ctx, tB, b)
+    Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+    c0 = int_vec(rng, Cg.nelem)
+    upload(Cg, c0)
+    tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
+    _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
+    assert np.array_equal(download(Cg), ref)
+
+
+def test_empty_k_sectors_are_zero(ctx):
+    """A coupled charge present in codomain(A~) and domain(B~) but not in the
+    contracted space gives a zero block (remark after eq. abelian_compostion)."""
+    V = synth.u1_space([-1, 0, 1], [2, 3, 2])
+    K = synth.u1_space([0], [4])
+    tA = dict(sym="U1", cod=[V], dom=[K])
+    tB = dict(sym="U1", cod=[K], dom=[V])
+    rng = np.random.default_rng(9)
+    stA, stB = ostruct(tA), ostruct(tB)
+    a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+    A, B = make(ctx, tA, a), make(ctx, tB, b)
+    for pAB, qAB in [((0,), (1,)), ((1,), (0,))]:     # in place, and scattered
+        Cg = tk.tensor_create_contracted(ctx, A, [0], [1], B, [0], [1], pAB, qAB)
+        fill(Cg)
+        tk.tensor_contract(ctx, A, [0], [1], B, [0], [1], pAB, qAB, C_=Cg)
+        stC, ref = blockwise.contract_storage(stA, a, (0,), (1,), stB, b, (0,), (1,), pAB, qAB)
+        got = download(Cg)
+        assert np.array_equal(got, ref)
+        assert len(stC.sectors) == 3 and (got == 0).sum() >= 2 * 2 * 2
+
+
+def test_config1_gaussian(ctx):
+    cfg = synth.config1()
+    tA, tB = cfg["tensors"]["A"], cfg["tensors"]["B"]
+    stA, stB = ostruct(tA), ostruct(tB)
+    a, b = synth.normal(stA.size, 1, 0), synth.normal(stB.size, 1, 1)
+    A, B = make(ctx, tA, a), make(ctx, tB, b)
+    _, _, _, call = cfg["calls"][0]
+    Cg = tk.tensor_contract(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"], call["qAB"])
+    _, ref = blockwise.contract_storage(stA, a, call["pA"], call["qA"], stB, b, call["pB"], call["qB"],
+                                        call["pAB"], call["qAB"])
+    _, refabs = blockwise.contract_storage(stA, np.abs(a), call["pA"], call["qA"], stB, np.abs(b), call["pB"],
+                                           call["qB"], call["pAB"], call["qAB"])
+    assert_close(download(Cg), ref, refabs)
+
+
+# ---------------------------------------------------------------------------
+# effective Hamiltonian chains
+# ---------------------------------------------------------------------------
+def run_heff_gpu(ctx, cfg, data, precision="native"):
+    T = {k: make(ctx, cfg["tensors"][k], data[k]) for k in cfg["inputs"]}
+    for out, a, b, call in cfg["calls"]:
+        T[out] = tk.tensor_contract(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"], call["pAB"],
+                                    call["qAB"], precision=precision)
+    return T
+
+
+def run_heff_oracle(cfg, data):
+    st = {k: ostruct(cfg["tensors"][k]) for k in cfg["inputs"]}
+    v = dict(data)
+    for out, a, b, call in cfg["calls"]:
+        st[out], v[out] = blockwise.contract_storage(st[a], v[a], call["pA"], call["qA"], st[b], v[b], call["pB"],
+                                                     call["qB"], call["pAB"], call["qAB"])
+    return st, v
+
+
+def heff_data(cfg, cid, ints=False, rng=None):
+    out = {}
+    for i, k in enumerate(cfg["inputs"]):
+        n = ostruct(cfg["tensors"][k]).size
+        out[k] = int_vec(rng, n) if ints else synth.normal(n, cid, i)
+    return out
+
+
+def test_heff_small_integer_bit_exact(ctx):
+    cfg = synth.heff_config(96, 4, 1.6, 90)
+    rng = np.random.default_rng(90)
+    data = heff_data(cfg, 90, ints=True, rng=rng)
+    T = run_heff_gpu(ctx, cfg, data)
+    _, v = run_heff_oracle(cfg, data)
+    for k in ("T1", "T2", "y"):
+        assert np.array_equal(download(T[k]), v[k]), k
+
+
+@pytest.mark.parametrize("cfgfn,cid", [(synth.config2, 2), (synth.config3, 3)])
+def test_heff_full_size_fp64(ctx, cfgfn, cid):
+    cfg = cfgfn()
+    data = heff_data(cfg, cid)
+    T = run_heff_gpu(ctx, cfg, data)
+    _, v = run_heff_oracle(cfg, data)
+    absdata = {k: np.abs(x) for k, x in data.items()}
+    _, vabs = run_heff_oracle(cfg, absdata)
+    for k in ("T1", "T2", "y"):
+        assert_close(download(T[k]), v[k], vabs[k])
+
+
+# ---------------------------------------------------------------------------
+# batches and graphs
+# ---------------------------------------------------------------------------
+def test_batch_graph_replays(ctx):
+    cfg = synth.config4(n=6, dmin=64, dmax=300)
+    call = cfg["call"]
+    rng = np.random.default_rng(44)
+    plans, As, Bs, Cs, refs = [], [], [], [], []
+    for it in cfg["items"]:
+        stA, stB = ostruct(it["A"]), ostruct(it["B"])
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, it["A"], a), make(ctx, it["B"], b)
+        Cg = tk.tensor_create_contracted(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"],
+                                         call["qAB"])
+        plans.append(tk.Plan(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"], call["qAB"], Cg))
+        As.append(A)
+        Bs.append(B)
+        Cs.append(Cg)
+        refs.append(blockwise.contract_storage(stA, a, call["pA"], call["qA"], stB, b, call["pB"], call["qB"],
+                                               call["pAB"], call["qAB"])[1])
+    batch = tk.Batch(ctx, plans, As, Bs, Cs)
+    batch.launch()
+    for Cg, ref in zip(Cs, refs):
+        assert np.array_equal(download(Cg), ref)
+    s = torch.cuda.Stream()
+    batch.capture(s)
+    for rep in range(3):
+        for Cg in Cs:
+            fill(Cg)
+        torch.cuda.synchronize()
+        batch.replay(s)
+        s.synchronize()
+        for Cg, ref in zip(Cs, refs):
+            assert np.array_equal(download(Cg), ref), rep
