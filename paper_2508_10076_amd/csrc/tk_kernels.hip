@@ -175,14 +175,16 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
       }
     }
 
-    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16, row = 4*(lane/16) + v
+    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16 and value v of
+    // the lane is row lane/16 + 4v (rows interleave across the lane groups;
+    // measured with a lane-layout probe on gfx950)
 #pragma unroll
     for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
       for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + 4 * g + v,
+          store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v,
                              tile.n0 + wn + 16 * ni + l16, acc[mi][ni][v]);
   }
 }

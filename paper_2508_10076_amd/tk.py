@@ -37,6 +37,11 @@ class tk_space(C.Structure):
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_2508_10076_amd.build.build()")
+# torch provides device memory and streams; loading it first makes libtk.so
+# bind to the HIP runtime torch already uses (same SONAME), so one process
+# never holds two HIP runtimes.
+import torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 _P = C.c_void_p
