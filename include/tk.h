@@ -230,7 +230,7 @@ tk_status tk_plan_destroy(tk_plan* plan);
 tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C,
                                  double alpha, double beta, int32_t stages, void* stream);
 
-/* Plan statistics: number of sector GEMMs with K > 0, useful block flops
+/* Plan statistics: number of sector GEMMs with K > 0 (MFMA or streamed), useful block flops
  * (sum of 2 M N K), number of zero-filled coupled charges, workspace bytes,
  * and the GEMM tile shape in use (any pointer may be NULL). */
 tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero,

@@ -425,8 +425,9 @@ struct DevBuf {
 // ---------------------------------------------------------------------------
 // permute task lists
 // ---------------------------------------------------------------------------
-struct TaskList {
-  std::vector<PermTask> tasks;
+template <typename TaskT>
+struct TaskListT {
+  std::vector<TaskT> tasks;
   std::vector<int32_t> wg_first{0};
   DevBuf d_tasks, d_wg;
   int nwg() const { return static_cast<int>(wg_first.size()) - 1; }
@@ -435,6 +436,9 @@ struct TaskList {
     d_wg.upload(wg_first);
   }
 };
+
+using TaskList = TaskListT<PermTask>;
+using SmallKList = TaskListT<tk::SmallKTask>;
 
 int32_t checked_i32(int64_t v, const char* what) {
   if (v > INT32_MAX || v < INT32_MIN) fail(TK_ERR_UNSUPPORTED, std::string(what) + " exceeds 32 bits");
@@ -486,8 +490,53 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
   }
 }
 
+// Sector GEMMs with K at most this run as an output-stationary stream.
+constexpr int64_t kSmallK = 8;
+
+// Add one output block of a small-K sector GEMM (dims and strides in output
+// leg order) as chunked tasks, merging dims contiguous in r, s and dst.
+void add_smallk_tasks(SmallKList& tl, const tk::SmallKTask& proto, int n, const int64_t* dim, const int64_t* rs,
+                      const int64_t* cs, const int64_t* ds) {
+  int64_t D[tk::kMaxDims], R[tk::kMaxDims], S[tk::kMaxDims], T[tk::kMaxDims];
+  int m = 0;
+  for (int i = 0; i < n; ++i) {
+    if (dim[i] == 1) continue;
+    if (m > 0 && rs[i] == R[m - 1] * D[m - 1] && cs[i] == S[m - 1] * D[m - 1] && ds[i] == T[m - 1] * D[m - 1]) {
+      D[m - 1] *= dim[i];
+      continue;
+    }
+    D[m] = dim[i];
+    R[m] = rs[i];
+    S[m] = cs[i];
+    T[m] = ds[i];
+    ++m;
+  }
+  if (m == 0) {
+    D[0] = 1;
+    R[0] = S[0] = T[0] = 0;
+    m = 1;
+  }
+  int64_t total = 1;
+  for (int i = 0; i < m; ++i) total *= D[i];
+  if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
+  tk::SmallKTask t = proto;
+  t.n = m;
+  for (int i = 0; i < tk::kMaxDims; ++i) {
+    t.dim[i] = i < m ? checked_i32(D[i], "dim") : 1;
+    t.rs[i] = i < m ? checked_i32(R[i], "stride") : 0;
+    t.cs[i] = i < m ? checked_i32(S[i], "stride") : 0;
+    t.ds[i] = i < m ? checked_i32(T[i], "stride") : 0;
+  }
+  for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
+    t.start = static_cast<int32_t>(s0);
+    t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
+    tl.tasks.push_back(t);
+  }
+}
+
 // Pack consecutive tasks into workgroups of about kPermChunk elements.
-void pack_workgroups(TaskList& tl) {
+template <typename TL>
+void pack_workgroups(TL& tl) {
   tl.wg_first.assign(1, 0);
   int64_t acc = 0;
   int ntask = 0;
@@ -656,6 +705,10 @@ struct tk_plan {
   std::vector<GemmTile> tiles;
   std::vector<int32_t> wg_first;
   DevBuf d_tiles, d_wg;
+  int32_t ngroups = 0, nslots = 0;
+  DevBuf d_partials, d_counters;
+  SmallKList smallk;
+  std::vector<int64_t> mnk;  // (M, N, K) of every sector GEMM with K > 0, MFMA or streamed
   DevBuf wsA, wsB, wsC;
   double flops = 0;
   int64_t nzero = 0;
@@ -666,6 +719,9 @@ struct tk_batch {
   int n = 0, dtype = 0, precision = 0;
   double alpha = 1.0, beta = 0.0;
   TaskList pre, zero, postp;
+  SmallKList smallk;
+  int32_t ngroups = 0, nslots = 0;
+  DevBuf d_partials, d_counters;
   std::vector<GemmDesc> descs;
   std::vector<LegMap> row_map, col_map;
   std::vector<PairDesc> pairs;
@@ -685,49 +741,113 @@ struct tk_batch {
 
 namespace {
 
-// LPT schedule of the tiles of a set of GEMMs over at most max_wg workgroups:
-// tiles sorted by cost (K steps) and each given to the least loaded group.
-void schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, std::vector<GemmTile>& tiles_out,
-                    std::vector<int32_t>& wg_first) {
-  struct T {
+// LPT schedule of the tiles of a set of GEMMs over at most max_wg
+// workgroups: work units sorted by cost (K stages) and each given to the
+// least loaded group.  When the whole-K tiles balance badly (few tiles, long
+// K), tiles are split along K; the schedule with the smaller estimated
+// makespan (including the partial-tile write and reduction of split units)
+// is kept.
+struct Sched {
+  std::vector<GemmTile> tiles;
+  std::vector<int32_t> wg_first;
+  int32_t ngroups = 0, nslots = 0;
+  double makespan = 0;
+};
+
+Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_t split_target) {
+  constexpr int BK = 16;
+  struct U {
     GemmTile t;
     int64_t cost;
   };
-  std::vector<T> all;
+  std::vector<U> units;
+  Sched out;
   for (size_t g = 0; g < descs.size(); ++g) {
     const GemmDesc& d = descs[g];
-    const int64_t cost = (d.K + 15) / 16 + 4;
+    const int64_t stages = (d.K + BK - 1) / BK;
+    int64_t S = 1;
+    if (split_target > 0 && stages > split_target) {
+      S = std::min<int64_t>((stages + split_target - 1) / split_target, 16);
+      S = std::min<int64_t>(S, std::max<int64_t>(1, stages / 4));
+    }
     for (int m0 = 0; m0 < d.M; m0 += tm)
-      for (int n0 = 0; n0 < d.N; n0 += tn) all.push_back({GemmTile{static_cast<int32_t>(g), m0, n0, 0}, cost});
+      for (int n0 = 0; n0 < d.N; n0 += tn) {
+        const int32_t group = S > 1 ? out.ngroups++ : -1;
+        const int32_t slot0 = S > 1 ? out.nslots : -1;
+        if (S > 1) out.nslots += static_cast<int32_t>(S);
+        for (int64_t sp = 0; sp < S; ++sp) {
+          const int64_t s0 = stages * sp / S, s1 = stages * (sp + 1) / S;
+          GemmTile t{};
+          t.gemm = static_cast<int32_t>(g);
+          t.m0 = m0;
+          t.n0 = n0;
+          t.k0 = static_cast<int32_t>(s0 * BK);
+          t.k1 = static_cast<int32_t>(std::min<int64_t>(s1 * BK, d.K));
+          t.nsplit = static_cast<int32_t>(S);
+          t.split = static_cast<int32_t>(sp);
+          t.group = group;
+          t.slot0 = slot0;
+          // cost in stages; prologue/epilogue ~3 stages, a split unit also
+          // writes its partial (~2) and may reduce (~S)
+          const int64_t cost = (s1 - s0) + 3 + (S > 1 ? 2 + S : 0);
+          units.push_back({t, cost});
+        }
+      }
   }
-  std::stable_sort(all.begin(), all.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
-  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(all.size())));
+  std::stable_sort(units.begin(), units.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
+  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(units.size())));
   std::vector<std::vector<GemmTile>> per(nwg);
   using E = std::pair<int64_t, int>;
   std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
   for (int w = 0; w < nwg; ++w) heap.push({0, w});
-  for (const auto& t : all) {
+  int64_t mk = 0;
+  for (const auto& u : units) {
     E e = heap.top();
     heap.pop();
-    per[e.second].push_back(t.t);
-    heap.push({e.first + t.cost, e.second});
+    per[e.second].push_back(u.t);
+    mk = std::max(mk, e.first + u.cost);
+    heap.push({e.first + u.cost, e.second});
   }
-  tiles_out.clear();
-  wg_first.assign(1, 0);
+  out.makespan = static_cast<double>(mk);
+  out.wg_first.assign(1, 0);
   for (int w = 0; w < nwg; ++w) {
-    tiles_out.insert(tiles_out.end(), per[w].begin(), per[w].end());
-    wg_first.push_back(static_cast<int32_t>(tiles_out.size()));
+    out.tiles.insert(out.tiles.end(), per[w].begin(), per[w].end());
+    out.wg_first.push_back(static_cast<int32_t>(out.tiles.size()));
   }
+  return out;
+}
+
+Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg) {
+  Sched best = lpt(descs, tm, tn, max_wg, 0);
+  if (descs.empty()) return best;
+  int64_t total = 0;
+  for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + 15) / 16);
+  for (int per_wg : {3, 4, 6, 8}) {
+    const int64_t target = std::max<int64_t>(8, total / (int64_t(max_wg) * per_wg));
+    Sched s = lpt(descs, tm, tn, max_wg, target);
+    if (s.makespan < 0.97 * best.makespan) best = std::move(s);
+  }
+  return best;
+}
+
+void upload_schedule(DevBuf& d_tiles, DevBuf& d_wg, DevBuf& d_partials, DevBuf& d_counters, const Sched& sc,
+                     int tm, int tn) {
+  d_tiles.upload(sc.tiles);
+  d_wg.upload(sc.wg_first);
+  d_partials.alloc(static_cast<size_t>(sc.nslots) * tm * tn * sizeof(double));
+  d_counters.alloc(static_cast<size_t>(sc.ngroups) * sizeof(int32_t));
+  if (sc.ngroups > 0) hip_check(hipMemset(d_counters.p, 0, d_counters.bytes), "hipMemset");
 }
 
 void plan_reschedule(tk_plan& P, int tm, int tn) {
   P.tile_m = tm;
   P.tile_n = tn;
-  schedule_tiles(P.descs, tm, tn, P.ctx ? P.ctx->num_cu : 256, P.tiles, P.wg_first);
-  if (P.ctx) {
-    P.d_tiles.upload(P.tiles);
-    P.d_wg.upload(P.wg_first);
-  }
+  Sched sc = schedule_tiles(P.descs, tm, tn, P.ctx ? P.ctx->num_cu : 256);
+  P.tiles = sc.tiles;
+  P.wg_first = sc.wg_first;
+  P.ngroups = sc.ngroups;
+  P.nslots = sc.nslots;
+  if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_counters, sc, tm, tn);
 }
 
 void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn) {
@@ -839,6 +959,55 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       d.a_buf = abuf;
       d.b_buf = bbuf;
       P->flops += 2.0 * double(M) * double(N) * double(K);
+      P->mnk.insert(P->mnk.end(), {M, N, K});
+      if (K <= kSmallK) {
+        // output-stationary stream over the output blocks of this sector
+        for (int32_t j = 0; j < cg.n(); ++j)
+          for (int32_t i = 0; i < rg.n(); ++i) {
+            std::copy(rg.idx.begin() + size_t(i) * Ct.N1(), rg.idx.begin() + size_t(i + 1) * Ct.N1(), tup.begin());
+            std::copy(cg.idx.begin() + size_t(j) * Ct.N2(), cg.idx.begin() + size_t(j + 1) * Ct.N2(),
+                      tup.begin() + Ct.N1());
+            int64_t cdim[TK_MAX_RANK], crs[TK_MAX_RANK], ccs[TK_MAX_RANK];
+            int64_t acc = 1;
+            for (int l = 0; l < Ct.N1(); ++l) {
+              cdim[l] = Ct.cod[l].deg[tup[l]];
+              crs[l] = acc;
+              ccs[l] = 0;
+              acc *= cdim[l];
+            }
+            acc = 1;
+            for (int l = Ct.N1(); l < Ct.N(); ++l) {
+              cdim[l] = Ct.leg(l).deg[tup[l]];
+              ccs[l] = acc;
+              crs[l] = 0;
+              acc *= cdim[l];
+            }
+            for (int n = 0; n < Ct.N(); ++n) otup[n] = tup[src[n]];
+            const BlockLoc bl = locate(sC, otup.data());
+            if (bl.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
+            block_strides(sC, otup.data(), bl.R, odim, ostr);
+            const int par = (sA.si.fermionic && !idC) ? channel_parity(Ct, tup.data(), outpairs) : 0;
+            tk::SmallKTask t{};
+            t.a = At.soff[sa] + rg.off[i];
+            t.b = Bt.soff[sb] + cg.off[j] * K;
+            t.dst = bl.offset;
+            t.K = static_cast<int32_t>(K);
+            t.lda = d.M;
+            t.ldb = d.K;
+            t.a_buf = abuf;
+            t.b_buf = bbuf;
+            t.dst_buf = tk::kBufC;
+            t.sign = par ? -1.0f : 1.0f;
+            int64_t dd[TK_MAX_RANK], rr[TK_MAX_RANK], cc2[TK_MAX_RANK];
+            for (int n = 0; n < Ct.N(); ++n) {
+              dd[n] = cdim[src[n]];
+              rr[n] = crs[src[n]];
+              cc2[n] = ccs[src[n]];
+            }
+            add_smallk_tasks(P->smallk, t, Ct.N(), dd, rr, cc2, ostr);
+          }
+        continue;
+      }
       if (idC) {
         d.mode = 0;
         d.c = sC.soff[sC.sector_of_key(key)];
@@ -935,11 +1104,15 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     pack_workgroups(P->postp);
   }
 
+  pack_workgroups(P->smallk);
   int tm, tn;
   choose_default_tile(P->descs, &tm, &tn);
-  P->tile_m = tm;
-  P->tile_n = tn;
-  schedule_tiles(P->descs, tm, tn, ctx ? ctx->num_cu : 256, P->tiles, P->wg_first);
+  {
+    tk_context* keep = P->ctx;
+    P->ctx = nullptr;  // schedule only; uploads follow below
+    plan_reschedule(*P, tm, tn);
+    P->ctx = keep;
+  }
 
   if (ctx) {
     const size_t es = A->esize();
@@ -953,8 +1126,13 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     P->d_rowmap.upload(P->row_map);
     P->d_colmap.upload(P->col_map);
     P->d_pairs.upload(P->pairs);
-    P->d_tiles.upload(P->tiles);
-    P->d_wg.upload(P->wg_first);
+    P->smallk.upload();
+    Sched sc;
+    sc.tiles = P->tiles;
+    sc.wg_first = P->wg_first;
+    sc.ngroups = P->ngroups;
+    sc.nslots = P->nslots;
+    upload_schedule(P->d_tiles, P->d_wg, P->d_partials, P->d_counters, sc, P->tile_m, P->tile_n);
   }
   return P;
 }
@@ -999,6 +1177,8 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
     ga_.row_map = static_cast<const LegMap*>(P.d_rowmap.p);
     ga_.col_map = static_cast<const LegMap*>(P.d_colmap.p);
     ga_.pairs = static_cast<const PairDesc*>(P.d_pairs.p);
+    ga_.partials = static_cast<double*>(P.d_partials.p);
+    ga_.counters = static_cast<int32_t*>(P.d_counters.p);
     ga_.ptrs = ptrs;
     ga_.alpha = P.post ? 1.0 : ga;
     ga_.beta = gb;
@@ -1006,6 +1186,11 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                               stream),
               "gemm launch");
   }
+  if ((stages & TK_STAGE_GEMM) && P.smallk.nwg() > 0)
+    hip_check(tk::launch_smallk(P.dtype, P.precision, static_cast<const tk::SmallKTask*>(P.smallk.d_tasks.p),
+                                static_cast<const int32_t*>(P.smallk.d_wg.p), P.smallk.nwg(), ptrs, alpha, beta,
+                                stream),
+              "small-K launch");
   if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
     hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
                                  static_cast<const int32_t*>(P.zero.d_wg.p), P.zero.nwg(), ptrs, P.post ? 1.0 : alpha,
@@ -1383,7 +1568,7 @@ tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64
                        int32_t* tile_m, int32_t* tile_n) {
   return guarded([&] {
     if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
-    if (ngemm) *ngemm = static_cast<int64_t>(plan->descs.size());
+    if (ngemm) *ngemm = static_cast<int64_t>(plan->mnk.size() / 3);
     if (flops) *flops = plan->flops;
     if (nzero) *nzero = plan->nzero;
     if (workspace_bytes) {
@@ -1399,14 +1584,9 @@ tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64
 tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk) {
   return guarded([&] {
     if (!plan || !mnk) fail(TK_ERR_INVALID_ARG, "null argument");
-    if (first < 0 || count < 0 || first + count > static_cast<int64_t>(plan->descs.size()))
+    if (first < 0 || count < 0 || first + count > static_cast<int64_t>(plan->mnk.size() / 3))
       fail(TK_ERR_INVALID_ARG, "range out of bounds");
-    for (int64_t k = 0; k < count; ++k) {
-      const GemmDesc& d = plan->descs[first + k];
-      mnk[3 * k] = d.M;
-      mnk[3 * k + 1] = d.N;
-      mnk[3 * k + 2] = d.K;
-    }
+    std::copy(plan->mnk.begin() + 3 * first, plan->mnk.begin() + 3 * (first + count), mnk);
   });
 }
 
@@ -1485,6 +1665,28 @@ void merge_tasks(TaskList& dst, const TaskList& src, int member) {
   for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
 }
 
+void merge_smallk(SmallKList& dst, const SmallKList& src, int member) {
+  const int base = static_cast<int>(dst.tasks.size());
+  for (tk::SmallKTask t : src.tasks) {
+    t.a_buf = static_cast<int16_t>(t.a_buf + member * tk::kBufsPerPlan);
+    t.b_buf = static_cast<int16_t>(t.b_buf + member * tk::kBufsPerPlan);
+    t.dst_buf = static_cast<int16_t>(t.dst_buf + member * tk::kBufsPerPlan);
+    dst.tasks.push_back(t);
+  }
+  for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
+}
+
+void batch_schedule(tk_batch& b, int tm, int tn) {
+  b.tile_m = tm;
+  b.tile_n = tn;
+  Sched sc = schedule_tiles(b.descs, tm, tn, b.ctx->num_cu);
+  b.tiles = sc.tiles;
+  b.wg_first = sc.wg_first;
+  b.ngroups = sc.ngroups;
+  b.nslots = sc.nslots;
+  upload_schedule(b.d_tiles, b.d_wg, b.d_partials, b.d_counters, sc, tm, tn);
+}
+
 void batch_launch_all(tk_batch& b, hipStream_t stream) {
   tk::Ptrs ptrs{};
   ptrs.table = static_cast<const uint64_t*>(b.d_table.p);
@@ -1500,6 +1702,8 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
     ga.row_map = static_cast<const LegMap*>(b.d_rowmap.p);
     ga.col_map = static_cast<const LegMap*>(b.d_colmap.p);
     ga.pairs = static_cast<const PairDesc*>(b.d_pairs.p);
+    ga.partials = static_cast<double*>(b.d_partials.p);
+    ga.counters = static_cast<int32_t*>(b.d_counters.p);
     ga.ptrs = ptrs;
     ga.alpha = b.alpha;
     ga.beta = b.beta;
@@ -1507,6 +1711,11 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                               stream),
               "gemm launch");
   }
+  if (b.smallk.nwg() > 0)
+    hip_check(tk::launch_smallk(b.dtype, b.precision, static_cast<const tk::SmallKTask*>(b.smallk.d_tasks.p),
+                                static_cast<const int32_t*>(b.smallk.d_wg.p), b.smallk.nwg(), ptrs, b.alpha, b.beta,
+                                stream),
+              "small-K launch");
   if (b.zero.nwg() > 0)
     hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
                                  static_cast<const int32_t*>(b.zero.d_wg.p), b.zero.nwg(), ptrs, b.alpha, b.beta,
@@ -1552,6 +1761,7 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       b->ws.push_back(std::move(wb));
       merge_tasks(b->pre, P.pre, i);
       merge_tasks(b->zero, P.zero, i);
+      merge_smallk(b->smallk, P.smallk, i);
       const int32_t rb = static_cast<int32_t>(b->row_map.size()), cb = static_cast<int32_t>(b->col_map.size());
       const int32_t pb = static_cast<int32_t>(b->pairs.size());
       for (GemmDesc d : P.descs) {
@@ -1573,17 +1783,14 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     if (b->descs.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many GEMMs");
     int tm, tn;
     choose_default_tile(b->descs, &tm, &tn);
-    b->tile_m = tm;
-    b->tile_n = tn;
-    schedule_tiles(b->descs, tm, tn, ctx->num_cu, b->tiles, b->wg_first);
+    batch_schedule(*b, tm, tn);
     b->pre.upload();
     b->zero.upload();
+    b->smallk.upload();
     b->d_descs.upload(b->descs);
     b->d_rowmap.upload(b->row_map);
     b->d_colmap.upload(b->col_map);
     b->d_pairs.upload(b->pairs);
-    b->d_tiles.upload(b->tiles);
-    b->d_wg.upload(b->wg_first);
     b->d_table.upload(table);
     *out = b.release();
   });
@@ -1647,11 +1854,7 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n) {
     if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
     if (!tk::gemm_tile_supported(batch->dtype, batch->precision, tile_m, tile_n))
       fail(TK_ERR_UNSUPPORTED, "tile shape not available");
-    batch->tile_m = tile_m;
-    batch->tile_n = tile_n;
-    schedule_tiles(batch->descs, tile_m, tile_n, batch->ctx->num_cu, batch->tiles, batch->wg_first);
-    batch->d_tiles.upload(batch->tiles);
-    batch->d_wg.upload(batch->wg_first);
+    batch_schedule(*batch, tile_m, tile_n);
     if (batch->exec) {
       (void)hipGraphExecDestroy(batch->exec);
       batch->exec = nullptr;

@@ -62,11 +62,40 @@ struct GemmDesc {
   int32_t pad_;
 };
 
+// One unit of work of the grouped GEMM: the (m0, n0) tile of sector GEMM
+// `gemm` over the K range [k0, k1).  When nsplit > 1 the K range of the tile
+// is split over nsplit units; each writes its partial tile to slot
+// slot0 + split of the partial buffer and bumps counter `group`; the unit
+// that arrives last sums the nsplit partials in split order (a fixed order,
+// so results do not depend on scheduling), runs the epilogue and resets the
+// counter to zero for the next launch.
 struct GemmTile {
   int32_t gemm;
   int32_t m0;
   int32_t n0;
+  int32_t k0;
+  int32_t k1;
+  int32_t nsplit;
+  int32_t split;
+  int32_t group;  // arrival counter of the split group
+  int32_t slot0;  // first partial slot of the split group
   int32_t pad_;
+};
+
+// Small-K sector GEMM work as output-stationary block tasks: an output block
+// of C (dims/dst strides in C's leg order) whose element i has C~ row
+// r = sum i_d rs[d] and column s = sum i_d cs[d] relative to a and b, and value
+// sign * sum_k A~[a + r + k lda] B~[b + k + s ldb].
+struct SmallKTask {
+  int64_t a, b, dst;
+  int32_t K, lda, ldb, n;
+  int32_t count, start;
+  int16_t a_buf, b_buf, dst_buf, pad_;
+  float sign;
+  int32_t dim[kMaxDims];
+  int32_t rs[kMaxDims];
+  int32_t cs[kMaxDims];
+  int32_t ds[kMaxDims];
 };
 
 // Row (or column) r of a sector of C~: its channel inside the sector and the
@@ -94,6 +123,8 @@ struct GemmArgs {
   const LegMap* row_map;
   const LegMap* col_map;
   const PairDesc* pairs;
+  double* partials;          // split-K partial tiles (tile_m * tile_n each)
+  int32_t* counters;         // split-K arrival counters, zero between launches
   Ptrs ptrs;
   double alpha, beta;
 };
@@ -103,6 +134,8 @@ hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_fi
                           const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
                        int nwg, hipStream_t stream);
+hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
+                        const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n);
 int num_tile_shapes();
 void tile_shape(int i, int* tm, int* tn);

@@ -97,11 +97,13 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
 }
 
 // Workgroup = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
-// sub-tile made of 16 x 16 MFMA tiles.  K advances in steps of 16 staged
-// through LDS: A as [k][m] (m contiguous, as in HBM), B as [n][k]
-// (k contiguous, as in HBM), so every global load is coalesced along the
-// contiguous axis.  Within one MFMA the k index is lane/16; step j of the 4
-// steps of a stage uses k = 4*(lane/16) + j for both operands.
+// sub-tile made of 16 x 16 MFMA tiles.  K advances in stages of 16 staged
+// through a double-buffered LDS tile: A as [k][m] (m contiguous, as in HBM),
+// B as [n][k] (k contiguous, as in HBM), so every global load is coalesced
+// along the contiguous axis.  Stage s+2 is fetched into registers while stage
+// s is multiplied, and written to the free LDS buffer at the start of stage
+// s+1: one barrier per stage.  Within one MFMA the k index is lane/16; step j
+// of the 4 steps of a stage uses k = 4*(lane/16) + j for both operands.
 template <int BM, int BN>
 __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
   constexpr int BK = 16;
@@ -112,8 +114,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
   constexpr int A_LD = BK / A_TPM;         // A loads per thread per stage
   constexpr int B_LD = BN / 16;            // B loads per thread per stage
   static_assert(kThreads % BM == 0 && BK % A_TPM == 0, "tile");
-  __shared__ double As[BK][BM + APAD];
-  __shared__ double Bs[BN][BK + BPAD];
+  __shared__ double As[2][BK][BM + APAD];
+  __shared__ double Bs[2][BN][BK + BPAD];
+  __shared__ int s_last;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -137,42 +140,84 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
 
     double ra[A_LD], rb[B_LD];
     const int am = tile.m0 + a_m;
+    const int kend = tile.k1;
     auto gload = [&](int k0) {
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) {
         const int k = k0 + a_k + A_TPM * i;
-        ra[i] = (am < d.M && k < d.K) ? A[static_cast<int64_t>(k) * d.lda + am] : 0.0;
+        ra[i] = (am < d.M && k < kend) ? A[static_cast<int64_t>(k) * d.lda + am] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < B_LD; ++i) {
         const int n = tile.n0 + b_n + 16 * i;
         const int k = k0 + b_k;
-        rb[i] = (n < d.N && k < d.K) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
+        rb[i] = (n < d.N && k < kend) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
       }
     };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
+#pragma unroll
+      for (int i = 0; i < B_LD; ++i) Bs[buf][b_n + 16 * i][b_k] = rb[i];
+    };
 
-    gload(0);
-    for (int k0 = 0; k0 < d.K; k0 += BK) {
+    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
+    gload(tile.k0);
+    lstore(0);
+    if (nst > 1) gload(tile.k0 + BK);
+    for (int st = 0; st < nst; ++st) {
       __syncthreads();
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) As[a_k + A_TPM * i][a_m] = ra[i];
-#pragma unroll
-      for (int i = 0; i < B_LD; ++i) Bs[b_n + 16 * i][b_k] = rb[i];
-      __syncthreads();
-      if (k0 + BK < d.K) gload(k0 + BK);
+      const int cur = st & 1;
+      if (st + 1 < nst) {
+        lstore(cur ^ 1);
+        if (st + 2 < nst) gload(tile.k0 + (st + 2) * BK);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         double af[TM], bf[TN];
 #pragma unroll
-        for (int mi = 0; mi < TM; ++mi) af[mi] = As[4 * g + j][wm + 16 * mi + l16];
+        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][4 * g + j][wm + 16 * mi + l16];
 #pragma unroll
-        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[wn + 16 * ni + l16][4 * g + j];
+        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][4 * g + j];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
           for (int ni = 0; ni < TN; ++ni)
             acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
       }
+    }
+
+    if (tile.nsplit > 1) {
+      // publish this split's partial tile, then let the last arrival reduce
+      double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) mine[((mi * TN + ni) * 4 + v) * kThreads + tid] = acc[mi][ni][v];
+      __threadfence();
+      __syncthreads();
+      if (tid == 0)
+        s_last = __hip_atomic_fetch_add(args.counters + tile.group, 1, __ATOMIC_ACQ_REL,
+                                        __HIP_MEMORY_SCOPE_AGENT) == tile.nsplit - 1;
+      __syncthreads();
+      if (!s_last) continue;
+      __threadfence();
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double sum = 0.0;
+            for (int j = 0; j < tile.nsplit; ++j) {
+              const double* pj = args.partials + static_cast<int64_t>(tile.slot0 + j) * (BM * BN);
+              sum += (j == tile.split) ? acc[mi][ni][v] : __builtin_nontemporal_load(pj + ((mi * TN + ni) * 4 + v) * kThreads + tid);
+            }
+            acc[mi][ni][v] = sum;
+          }
+      if (tid == 0) __hip_atomic_store(args.counters + tile.group, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 
     // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16 and value v of
@@ -186,6 +231,86 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
         for (int v = 0; v < 4; ++v)
           store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v,
                              tile.n0 + wn + 16 * ni + l16, acc[mi][ni][v]);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small-K sector GEMMs as an output-stationary stream
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_round(float x) {
+  return static_cast<float>(static_cast<__bf16>(x));
+}
+
+// MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
+// each operand, three products, fp32 accumulation (the compensated mode).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __restrict__ tasks,
+                                                          const int32_t* __restrict__ wg_first, Ptrs P,
+                                                          double alpha, double beta) {
+  const int t0 = wg_first[blockIdx.x];
+  const int t1 = wg_first[blockIdx.x + 1];
+  for (int t = t0; t < t1; ++t) {
+    const SmallKTask* tk = tasks + t;
+    const int n = tk->n, count = tk->count, K = tk->K;
+    const int lda = tk->lda, ldb = tk->ldb;
+    const uint32_t start = static_cast<uint32_t>(tk->start);
+    const double scale = alpha * static_cast<double>(tk->sign);
+    int32_t dim[kMaxDims], rs[kMaxDims], cs[kMaxDims], ds[kMaxDims];
+#pragma unroll
+    for (int d = 0; d < kMaxDims; ++d) {
+      dim[d] = tk->dim[d];
+      rs[d] = tk->rs[d];
+      cs[d] = tk->cs[d];
+      ds[d] = tk->ds[d];
+    }
+    const T* A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
+    const T* B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
+    T* D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+    for (int e = threadIdx.x; e < count; e += kThreads) {
+      uint32_t lin = start + static_cast<uint32_t>(e);
+      int64_t r = 0, c = 0, o = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < n) {
+          const uint32_t ext = static_cast<uint32_t>(dim[d]);
+          const uint32_t q = lin / ext;
+          const uint32_t i = lin - q * ext;
+          lin = q;
+          r += static_cast<int64_t>(i) * rs[d];
+          c += static_cast<int64_t>(i) * cs[d];
+          o += static_cast<int64_t>(i) * ds[d];
+        }
+      }
+      const T* ap = A + r;
+      const T* bp = B + c * ldb;
+      double acc;
+      if (MODE == 0) {
+        T s = 0;
+        for (int k = 0; k < K; ++k) s += ap[static_cast<int64_t>(k) * lda] * bp[k];
+        acc = static_cast<double>(s);
+      } else if (MODE == 1) {
+        float s = 0.f;
+        for (int k = 0; k < K; ++k)
+          s = fmaf(static_cast<float>(ap[static_cast<int64_t>(k) * lda]), static_cast<float>(bp[k]), s);
+        acc = s;
+      } else {
+        float s = 0.f;
+        for (int k = 0; k < K; ++k) {
+          const float x = static_cast<float>(ap[static_cast<int64_t>(k) * lda]);
+          const float y = static_cast<float>(bp[k]);
+          const float xh = bf16_round(x), yh = bf16_round(y);
+          const float xl = bf16_round(x - xh), yl = bf16_round(y - yh);
+          s = fmaf(xh, yh, s);
+          s = fmaf(xh, yl, s);
+          s = fmaf(xl, yh, s);
+        }
+        acc = s;
+      }
+      double v = scale * acc;
+      if (beta != 0.0) v += beta * static_cast<double>(D[o]);
+      D[o] = static_cast<T>(v);
+    }
   }
 }
 
@@ -201,6 +326,24 @@ hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_fi
   else
     hipLaunchKernelGGL(permute_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
                        ptrs, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
+                        const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+#define TK_SMALLK(T_, M_)                                                                            \
+  hipLaunchKernelGGL((smallk_kernel<T_, M_>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, ptrs, \
+                     alpha, beta)
+  if (dtype == 0) {
+    if (precision == 0) TK_SMALLK(double, 0);
+    else if (precision == 1) TK_SMALLK(double, 1);
+    else TK_SMALLK(double, 2);
+  } else {
+    if (precision == 2) TK_SMALLK(float, 2);
+    else TK_SMALLK(float, 1);
+  }
+#undef TK_SMALLK
   return hipGetLastError();
 }
 

@@ -277,3 +277,24 @@ def test_batch_graph_replays(ctx):
         s.synchronize()
         for Cg, ref in zip(Cs, refs):
             assert np.array_equal(download(Cg), ref), rep
+
+
+def test_split_k_tall_k_exact_and_repeatable(ctx):
+    """Few tiles with a long K range take the split-K path (partials reduced
+    by the last arriving unit); repeated launches must reset its counters."""
+    V = synth.u1_space([-1, 0, 1], [40, 60, 40])
+    Kb = synth.u1_space([-1, 0, 1], [900, 1200, 900])
+    tA = dict(sym="U1", cod=[V], dom=[Kb])
+    tB = dict(sym="U1", cod=[Kb], dom=[V])
+    rng = np.random.default_rng(12)
+    stA, stB = ostruct(tA), ostruct(tB)
+    a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+    A, B = make(ctx, tA, a), make(ctx, tB, b)
+    _, ref = blockwise.contract_storage(stA, a, (0,), (1,), stB, b, (0,), (1,), (0,), (1,))
+    _, reft = blockwise.contract_storage(stA, a, (0,), (1,), stB, b, (0,), (1,), (1,), (0,))
+    for pAB, qAB, want in [((0,), (1,), ref), ((1,), (0,), reft)]:
+        Cg = tk.tensor_create_contracted(ctx, A, [0], [1], B, [0], [1], pAB, qAB)
+        for rep in range(3):
+            fill(Cg)
+            tk.tensor_contract(ctx, A, [0], [1], B, [0], [1], pAB, qAB, C_=Cg)
+            assert np.array_equal(download(Cg), want), (pAB, rep)
