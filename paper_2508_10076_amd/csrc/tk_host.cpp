@@ -706,7 +706,8 @@ struct tk_plan {
   std::vector<int32_t> wg_first;
   DevBuf d_tiles, d_wg;
   int32_t ngroups = 0, nslots = 0;
-  DevBuf d_partials, d_counters;
+  DevBuf d_partials, d_groups;
+  std::vector<GemmTile> groups;
   SmallKList smallk;
   std::vector<int64_t> mnk;  // (M, N, K) of every sector GEMM with K > 0, MFMA or streamed
   DevBuf wsA, wsB, wsC;
@@ -721,7 +722,8 @@ struct tk_batch {
   TaskList pre, zero, postp;
   SmallKList smallk;
   int32_t ngroups = 0, nslots = 0;
-  DevBuf d_partials, d_counters;
+  DevBuf d_partials, d_groups;
+  std::vector<GemmTile> groups;
   std::vector<GemmDesc> descs;
   std::vector<LegMap> row_map, col_map;
   std::vector<PairDesc> pairs;
@@ -750,6 +752,7 @@ namespace {
 struct Sched {
   std::vector<GemmTile> tiles;
   std::vector<int32_t> wg_first;
+  std::vector<GemmTile> groups;  // one descriptor per split group (its split 0)
   int32_t ngroups = 0, nslots = 0;
   double makespan = 0;
 };
@@ -787,9 +790,10 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_
           t.split = static_cast<int32_t>(sp);
           t.group = group;
           t.slot0 = slot0;
-          // cost in stages; prologue/epilogue ~3 stages, a split unit also
-          // writes its partial (~2) and may reduce (~S)
-          const int64_t cost = (s1 - s0) + 3 + (S > 1 ? 2 + S : 0);
+          if (S > 1 && sp == 0) out.groups.push_back(t);
+          // cost in stages: prologue/epilogue ~3, a split unit writes its
+          // partial tile instead (~2)
+          const int64_t cost = (s1 - s0) + 3;
           units.push_back({t, cost});
         }
       }
@@ -808,7 +812,10 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_
     mk = std::max(mk, e.first + u.cost);
     heap.push({e.first + u.cost, e.second});
   }
-  out.makespan = static_cast<double>(mk);
+  // the reduce kernel reads and writes every partial once: at ~5 TB/s one
+  // 16-deep fp64 stage of MFMA work (4096 cycles at 2.4 GHz) moves ~8.5 MB
+  const double red_bytes = 2.0 * out.nslots * double(tm) * tn * 8.0;
+  out.makespan = static_cast<double>(mk) + (out.nslots ? 2.0 + red_bytes / 8.5e6 : 0.0);
   out.wg_first.assign(1, 0);
   for (int w = 0; w < nwg; ++w) {
     out.tiles.insert(out.tiles.end(), per[w].begin(), per[w].end());
@@ -830,13 +837,12 @@ Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int max
   return best;
 }
 
-void upload_schedule(DevBuf& d_tiles, DevBuf& d_wg, DevBuf& d_partials, DevBuf& d_counters, const Sched& sc,
-                     int tm, int tn) {
+void upload_schedule(DevBuf& d_tiles, DevBuf& d_wg, DevBuf& d_partials, DevBuf& d_groups, const Sched& sc, int tm,
+                     int tn) {
   d_tiles.upload(sc.tiles);
   d_wg.upload(sc.wg_first);
   d_partials.alloc(static_cast<size_t>(sc.nslots) * tm * tn * sizeof(double));
-  d_counters.alloc(static_cast<size_t>(sc.ngroups) * sizeof(int32_t));
-  if (sc.ngroups > 0) hip_check(hipMemset(d_counters.p, 0, d_counters.bytes), "hipMemset");
+  d_groups.upload(sc.groups);
 }
 
 void plan_reschedule(tk_plan& P, int tm, int tn) {
@@ -845,9 +851,10 @@ void plan_reschedule(tk_plan& P, int tm, int tn) {
   Sched sc = schedule_tiles(P.descs, tm, tn, P.ctx ? P.ctx->num_cu : 256);
   P.tiles = sc.tiles;
   P.wg_first = sc.wg_first;
+  P.groups = sc.groups;
   P.ngroups = sc.ngroups;
   P.nslots = sc.nslots;
-  if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_counters, sc, tm, tn);
+  if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
 }
 
 void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn) {
@@ -1130,9 +1137,10 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     Sched sc;
     sc.tiles = P->tiles;
     sc.wg_first = P->wg_first;
+    sc.groups = P->groups;
     sc.ngroups = P->ngroups;
     sc.nslots = P->nslots;
-    upload_schedule(P->d_tiles, P->d_wg, P->d_partials, P->d_counters, sc, P->tile_m, P->tile_n);
+    upload_schedule(P->d_tiles, P->d_wg, P->d_partials, P->d_groups, sc, P->tile_m, P->tile_n);
   }
   return P;
 }
@@ -1178,13 +1186,15 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
     ga_.col_map = static_cast<const LegMap*>(P.d_colmap.p);
     ga_.pairs = static_cast<const PairDesc*>(P.d_pairs.p);
     ga_.partials = static_cast<double*>(P.d_partials.p);
-    ga_.counters = static_cast<int32_t*>(P.d_counters.p);
     ga_.ptrs = ptrs;
     ga_.alpha = P.post ? 1.0 : ga;
     ga_.beta = gb;
     hip_check(tk::launch_gemm(P.dtype, P.precision, P.tile_m, P.tile_n, ga_, static_cast<int>(P.wg_first.size()) - 1,
                               stream),
               "gemm launch");
+    hip_check(tk::launch_splitk_reduce(P.dtype, P.precision, P.tile_m, P.tile_n, ga_,
+                                       static_cast<const GemmTile*>(P.d_groups.p), P.ngroups, stream),
+              "split-K reduce launch");
   }
   if ((stages & TK_STAGE_GEMM) && P.smallk.nwg() > 0)
     hip_check(tk::launch_smallk(P.dtype, P.precision, static_cast<const tk::SmallKTask*>(P.smallk.d_tasks.p),
@@ -1682,9 +1692,10 @@ void batch_schedule(tk_batch& b, int tm, int tn) {
   Sched sc = schedule_tiles(b.descs, tm, tn, b.ctx->num_cu);
   b.tiles = sc.tiles;
   b.wg_first = sc.wg_first;
+  b.groups = sc.groups;
   b.ngroups = sc.ngroups;
   b.nslots = sc.nslots;
-  upload_schedule(b.d_tiles, b.d_wg, b.d_partials, b.d_counters, sc, tm, tn);
+  upload_schedule(b.d_tiles, b.d_wg, b.d_partials, b.d_groups, sc, tm, tn);
 }
 
 void batch_launch_all(tk_batch& b, hipStream_t stream) {
@@ -1703,13 +1714,15 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
     ga.col_map = static_cast<const LegMap*>(b.d_colmap.p);
     ga.pairs = static_cast<const PairDesc*>(b.d_pairs.p);
     ga.partials = static_cast<double*>(b.d_partials.p);
-    ga.counters = static_cast<int32_t*>(b.d_counters.p);
     ga.ptrs = ptrs;
     ga.alpha = b.alpha;
     ga.beta = b.beta;
     hip_check(tk::launch_gemm(b.dtype, b.precision, b.tile_m, b.tile_n, ga, static_cast<int>(b.wg_first.size()) - 1,
                               stream),
               "gemm launch");
+    hip_check(tk::launch_splitk_reduce(b.dtype, b.precision, b.tile_m, b.tile_n, ga,
+                                       static_cast<const GemmTile*>(b.d_groups.p), b.ngroups, stream),
+              "split-K reduce launch");
   }
   if (b.smallk.nwg() > 0)
     hip_check(tk::launch_smallk(b.dtype, b.precision, static_cast<const tk::SmallKTask*>(b.smallk.d_tasks.p),

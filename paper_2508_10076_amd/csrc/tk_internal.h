@@ -65,10 +65,9 @@ struct GemmDesc {
 // One unit of work of the grouped GEMM: the (m0, n0) tile of sector GEMM
 // `gemm` over the K range [k0, k1).  When nsplit > 1 the K range of the tile
 // is split over nsplit units; each writes its partial tile to slot
-// slot0 + split of the partial buffer and bumps counter `group`; the unit
-// that arrives last sums the nsplit partials in split order (a fixed order,
-// so results do not depend on scheduling), runs the epilogue and resets the
-// counter to zero for the next launch.
+// slot0 + split of the partial buffer, and a second kernel sums the nsplit
+// partials of every group in split order (a fixed order, so results do not
+// depend on scheduling) and runs the epilogue.
 struct GemmTile {
   int32_t gemm;
   int32_t m0;
@@ -77,7 +76,7 @@ struct GemmTile {
   int32_t k1;
   int32_t nsplit;
   int32_t split;
-  int32_t group;  // arrival counter of the split group
+  int32_t group;  // index of the split group
   int32_t slot0;  // first partial slot of the split group
   int32_t pad_;
 };
@@ -124,7 +123,6 @@ struct GemmArgs {
   const LegMap* col_map;
   const PairDesc* pairs;
   double* partials;          // split-K partial tiles (tile_m * tile_n each)
-  int32_t* counters;         // split-K arrival counters, zero between launches
   Ptrs ptrs;
   double alpha, beta;
 };
@@ -134,6 +132,8 @@ hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_fi
                           const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
                        int nwg, hipStream_t stream);
+hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+                                const GemmTile* groups, int ngroups, hipStream_t stream);
 hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n);

@@ -96,32 +96,43 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
   Cbase[idx] = static_cast<TC>(v);
 }
 
-// Workgroup = 4 waves in a 2 x 2 grid, each wave owns a (BM/2) x (BN/2)
-// sub-tile made of 16 x 16 MFMA tiles.  K advances in stages of 16 staged
-// through a double-buffered LDS tile: A as [k][m] (m contiguous, as in HBM),
-// B as [n][k] (k contiguous, as in HBM), so every global load is coalesced
-// along the contiguous axis.  Stage s+2 is fetched into registers while stage
-// s is multiplied, and written to the free LDS buffer at the start of stage
-// s+1: one barrier per stage.  Within one MFMA the k index is lane/16; step j
-// of the 4 steps of a stage uses k = 4*(lane/16) + j for both operands.
-template <int BM, int BN>
-__global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
-  constexpr int BK = 16;
-  constexpr int APAD = 2, BPAD = 2;
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_TPM = kThreads / BM;     // threads sharing one m row
-  constexpr int A_LD = BK / A_TPM;         // A loads per thread per stage
-  constexpr int B_LD = BN / 16;            // B loads per thread per stage
-  static_assert(kThreads % BM == 0 && BK % A_TPM == 0, "tile");
-  __shared__ double As[2][BK][BM + APAD];
-  __shared__ double Bs[2][BN][BK + BPAD];
-  __shared__ int s_last;
+// Grouped sector GEMM, fp64 MFMA 16x16x4.  A workgroup of WGM x WGN waves
+// owns a BM x BN tile; each wave a (BM/WGM) x (BN/WGN) sub-tile made of 16 x 16
+// MFMA tiles.  K advances in stages of 16 through a double-buffered LDS tile:
+// A as [k][m] (m contiguous, as in HBM), B as [n][k] (k contiguous, as in
+// HBM), so every global load is coalesced along the contiguous axis.  Stage
+// s+2 is fetched into registers while stage s is multiplied and is written to
+// the free LDS buffer at the start of stage s+1: one barrier per stage.
+// Within one MFMA the k index is lane/16; step j of the 4 steps of a stage
+// uses k = 4*(lane/16) + j for both operands.
+template <int BM, int BN, int WGM, int WGN>
+struct F64Tile {
+  static constexpr int NT = 64 * WGM * WGN;
+  static constexpr int BK = 16, APAD = 2, BPAD = 2;
+  static constexpr int WM = BM / WGM, WN = BN / WGN;
+  static constexpr int TM = WM / 16, TN = WN / 16;
+  static constexpr int A_TPM = NT / BM;  // threads sharing one m row
+  static constexpr int A_LD = BK / A_TPM;
+  static constexpr int B_CPL = NT / 16;  // columns of B covered per load
+  static constexpr int B_LD = BN / B_CPL;
+  static constexpr int NACC = TM * TN * 4;  // accumulator doubles per lane
+  static_assert(NT % BM == 0 && BK % A_TPM == 0 && A_LD >= 1, "A tile");
+  static_assert(BN % B_CPL == 0 && B_LD >= 1, "B tile");
+  static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
+};
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs args) {
+  using TT = F64Tile<BM, BN, WGM, WGN>;
+  constexpr int NT = TT::NT, BK = TT::BK, TM = TT::TM, TN = TT::TN;
+  constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD, B_CPL = TT::B_CPL, B_LD = TT::B_LD;
+  __shared__ double As[2][BK][BM + TT::APAD];
+  __shared__ double Bs[2][BN][BK + TT::BPAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int wm = (wave & 1) * WM, wn = (wave >> 1) * WN;
+  const int wm = (wave % WGM) * TT::WM, wn = (wave / WGM) * TT::WN;
   const int a_m = tid % BM, a_k = tid / BM;
   const int b_k = tid & 15, b_n = tid >> 4;
 
@@ -130,7 +141,6 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
     const GemmDesc d = args.descs[tile.gemm];
     const double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a;
     const double* B = buf_ptr<const double>(args.ptrs, d.b_buf) + d.b;
-    double* C = buf_ptr<double>(args.ptrs, d.c_buf);
 
     d4_t acc[TM][TN];
 #pragma unroll
@@ -140,16 +150,18 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
 
     double ra[A_LD], rb[B_LD];
     const int am = tile.m0 + a_m;
+    const bool a_ok = am < d.M;
+    const double* Arow = A + am;
     const int kend = tile.k1;
     auto gload = [&](int k0) {
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) {
         const int k = k0 + a_k + A_TPM * i;
-        ra[i] = (am < d.M && k < kend) ? A[static_cast<int64_t>(k) * d.lda + am] : 0.0;
+        ra[i] = (a_ok && k < kend) ? Arow[static_cast<int64_t>(k) * d.lda] : 0.0;
       }
 #pragma unroll
       for (int i = 0; i < B_LD; ++i) {
-        const int n = tile.n0 + b_n + 16 * i;
+        const int n = tile.n0 + b_n + B_CPL * i;
         const int k = k0 + b_k;
         rb[i] = (n < d.N && k < kend) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
       }
@@ -158,20 +170,9 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
 #pragma unroll
-      for (int i = 0; i < B_LD; ++i) Bs[buf][b_n + 16 * i][b_k] = rb[i];
+      for (int i = 0; i < B_LD; ++i) Bs[buf][b_n + B_CPL * i][b_k] = rb[i];
     };
-
-    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
-    gload(tile.k0);
-    lstore(0);
-    if (nst > 1) gload(tile.k0 + BK);
-    for (int st = 0; st < nst; ++st) {
-      __syncthreads();
-      const int cur = st & 1;
-      if (st + 1 < nst) {
-        lstore(cur ^ 1);
-        if (st + 2 < nst) gload(tile.k0 + (st + 2) * BK);
-      }
+    auto compute = [&](int cur) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         double af[TM], bf[TN];
@@ -185,54 +186,82 @@ __global__ __launch_bounds__(kThreads) void gemm_f64_kernel(GemmArgs args) {
           for (int ni = 0; ni < TN; ++ni)
             acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
       }
-    }
+    };
 
+    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
+    gload(tile.k0);
+    lstore(0);
+    if (nst > 1) gload(tile.k0 + BK);
+    int st = 0;
+    // steady state: store stage st+1, fetch stage st+2, multiply stage st
+    for (; st + 2 < nst; ++st) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      gload(tile.k0 + (st + 2) * BK);
+      compute(st & 1);
+    }
+    if (st + 1 < nst) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      compute(st & 1);
+      ++st;
+    }
+    __syncthreads();
+    compute(st & 1);
+
+    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16 and value v of
+    // the lane is row lane/16 + 4v (rows interleave across the lane groups;
+    // measured with a lane-layout probe on gfx950)
     if (tile.nsplit > 1) {
-      // publish this split's partial tile, then let the last arrival reduce
+      // partial tile of one K split: stored lane-major for the reduce kernel
       double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) mine[((mi * TN + ni) * 4 + v) * kThreads + tid] = acc[mi][ni][v];
-      __threadfence();
-      __syncthreads();
-      if (tid == 0)
-        s_last = __hip_atomic_fetch_add(args.counters + tile.group, 1, __ATOMIC_ACQ_REL,
-                                        __HIP_MEMORY_SCOPE_AGENT) == tile.nsplit - 1;
-      __syncthreads();
-      if (!s_last) continue;
-      __threadfence();
+          for (int v = 0; v < 4; ++v) mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
+    } else {
+      double* C = buf_ptr<double>(args.ptrs, d.c_buf);
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            double sum = 0.0;
-            for (int j = 0; j < tile.nsplit; ++j) {
-              const double* pj = args.partials + static_cast<int64_t>(tile.slot0 + j) * (BM * BN);
-              sum += (j == tile.split) ? acc[mi][ni][v] : __builtin_nontemporal_load(pj + ((mi * TN + ni) * 4 + v) * kThreads + tid);
-            }
-            acc[mi][ni][v] = sum;
-          }
-      if (tid == 0) __hip_atomic_store(args.counters + tile.group, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int v = 0; v < 4; ++v)
+            store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v, tile.n0 + wn + 16 * ni + l16,
+                               acc[mi][ni][v]);
     }
-
-    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16 and value v of
-    // the lane is row lane/16 + 4v (rows interleave across the lane groups;
-    // measured with a lane-layout probe on gfx950)
-#pragma unroll
-    for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v,
-                             tile.n0 + wn + 16 * ni + l16, acc[mi][ni][v]);
     __syncthreads();
   }
+}
+
+// Sum of the K-split partial tiles of one split group, in split order (a
+// fixed order: the result does not depend on which unit finished first),
+// then the same epilogue as an unsplit tile.  One workgroup per group; each
+// thread owns the same accumulator elements as in gemm_f64_kernel.
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(64 * WGM* WGN) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups) {
+  using TT = F64Tile<BM, BN, WGM, WGN>;
+  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int wm = (wave % WGM) * TT::WM, wn = (wave / WGM) * TT::WN;
+  const GemmTile tile = groups[blockIdx.x];
+  const GemmDesc d = args.descs[tile.gemm];
+  double* C = buf_ptr<double>(args.ptrs, d.c_buf);
+#pragma unroll
+  for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t e = ((mi * TN + ni) * 4 + v) * NT + tid;
+        double sum = 0.0;
+        for (int j = 0; j < tile.nsplit; ++j) sum += args.partials[static_cast<int64_t>(tile.slot0 + j) * (BM * BN) + e];
+        store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v, tile.n0 + wn + 16 * ni + l16, sum);
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -365,20 +394,36 @@ bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n) {
   return false;
 }
 
-hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
-                       int nwg, hipStream_t stream) {
+// wave grid per tile shape: 8 waves for 128-wide tiles, 4 for 64 x 64
+#define TK_F64_SHAPES(X) X(128, 128, 2, 4) X(128, 64, 2, 2) X(64, 128, 2, 4) X(64, 64, 2, 2)
+
+hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args, int nwg,
+                       hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
   if (!gemm_tile_supported(dtype, precision, tile_m, tile_n)) return hipErrorInvalidValue;
-#define TK_GEMM_CASE(BM_, BN_)                                                                   \
-  if (tile_m == BM_ && tile_n == BN_) {                                                          \
-    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_>), dim3(nwg), dim3(kThreads), 0, stream, args); \
-    return hipGetLastError();                                                                    \
+#define TK_GEMM_CASE(BM_, BN_, WM_, WN_)                                                                  \
+  if (tile_m == BM_ && tile_n == BN_) {                                                                   \
+    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_, WM_, WN_>), dim3(nwg), dim3(64 * WM_ * WN_), 0, stream, \
+                       args);                                                                             \
+    return hipGetLastError();                                                                             \
   }
-  TK_GEMM_CASE(128, 128)
-  TK_GEMM_CASE(128, 64)
-  TK_GEMM_CASE(64, 128)
-  TK_GEMM_CASE(64, 64)
+  TK_F64_SHAPES(TK_GEMM_CASE)
 #undef TK_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+                                const GemmTile* groups, int ngroups, hipStream_t stream) {
+  if (ngroups <= 0) return hipSuccess;
+  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n)) return hipErrorInvalidValue;
+#define TK_RED_CASE(BM_, BN_, WM_, WN_)                                                                        \
+  if (tile_m == BM_ && tile_n == BN_) {                                                                        \
+    hipLaunchKernelGGL((splitk_reduce_kernel<BM_, BN_, WM_, WN_>), dim3(ngroups), dim3(64 * WM_ * WN_), 0, \
+                       stream, args, groups);                                                                  \
+    return hipGetLastError();                                                                                  \
+  }
+  TK_F64_SHAPES(TK_RED_CASE)
+#undef TK_RED_CASE
   return hipErrorInvalidValue;
 }
 
