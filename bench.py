@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--precision", default="native", choices=["native", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile configuration")
+    ap.add_argument("--tune-cache", default=None, help="JSON file to read/write tuned tile configurations")
     return ap.parse_args()
 
 
@@ -86,6 +88,21 @@ def main():
     # the MFMA-bound contractions: those whose GEMMs have K well above 16
     mfma_steps = [i for i, (P, *_r) in enumerate(plans) if P.gemms()[:, 2].max() > 64]
     gemm_flops = sum(plans[i][4]["flops"] for i in mfma_steps)
+
+    # tile configuration per contraction, chosen by the autotuner
+    from paper_2508_10076_amd import autotune
+    tuning = {}
+    for i in mfma_steps:
+        P, A, B, Cc, _ = plans[i]
+        if args.no_tune:
+            break
+        best, times = autotune.tune(P, lambda P=P, A=A, B=B, Cc=Cc: P.execute_stages(A, B, Cc, tk.STAGE_GEMM,
+                                                                                       stream=stream),
+                                    P.gemms().tolist(), stream, cache_path=args.tune_cache, force=True,
+                                    tag=("f64", args.precision))
+        tuning[f"step{i + 1}"] = {"tile": list(best), "ms": {"x".join(map(str, c)): round(t, 4)
+                                                             for c, t in times.items()}}
+    torch.cuda.synchronize()
 
     def step(ev=None):
         for i, (P, A, B, Cc, _) in enumerate(plans):
@@ -139,6 +156,8 @@ def main():
                    "precision": args.precision, "block_flops_per_step": flops,
                    "parallelism": "1 GPU"},
         "pct_fp64_mfma_peak": round(100.0 * value / PEAK["f64"], 2),
+        "tiles": {f"step{i + 1}": list(plans[i][0].info()["tile"]) for i in mfma_steps},
+        "tuning": tuning,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK[peak_key], "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK[peak_key], 4), "traffic": None,
                      "kernel": "gemm grouped sector GEMM (steps 1 and 3)",

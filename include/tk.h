@@ -232,9 +232,9 @@ tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_ten
 
 /* Plan statistics: number of sector GEMMs with K > 0 (MFMA or streamed), useful block flops
  * (sum of 2 M N K), number of zero-filled coupled charges, workspace bytes,
- * and the GEMM tile shape in use (any pointer may be NULL). */
+ * and the GEMM tile configuration in use (any pointer may be NULL). */
 tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero,
-                       int64_t* workspace_bytes, int32_t* tile_m, int32_t* tile_n);
+                       int64_t* workspace_bytes, int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);
 /* (M, N, K) of sector GEMMs first..first+count-1 (3 * count values). */
 tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk);
 
@@ -256,17 +256,18 @@ tk_status tk_batch_launch(tk_batch* batch, void* stream);
 tk_status tk_batch_capture(tk_batch* batch, void* stream);
 tk_status tk_batch_replay(tk_batch* batch, void* stream);
 tk_status tk_batch_info(const tk_batch* batch, int64_t* ngemm, int64_t* ntiles, double* flops,
-                        int32_t* tile_m, int32_t* tile_n);
+                        int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);
 tk_status tk_batch_destroy(tk_batch* batch);
 
-/* ---- tile shapes ----------------------------------------------------------
- * GEMM tile shapes the grouped kernel supports: (tile_m, tile_n) pairs.
- * tk_plan_set_tile / tk_batch_set_tile choose one (re-scheduling the tiles);
- * the autotuner in the Python package times the candidates and persists the
- * winner per shape class. */
-tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mn /* 2 * count, may be NULL */);
-tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n);
-tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n);
+/* ---- tile configurations --------------------------------------------------
+ * Tile configurations the grouped GEMM supports: (tile_m, tile_n, tile_k)
+ * triples, tile_k being the K depth staged through LDS per step.
+ * tk_plan_set_tile / tk_batch_set_tile choose one (re-scheduling the tiles,
+ * which drops a captured graph); the autotuner in the Python package times
+ * the candidates and persists the winner per shape class. */
+tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mnk /* 3 * count, may be NULL */);
+tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n, int32_t tile_k);
+tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int32_t tile_k);
 
 /* ---- misc ------------------------------------------------------------------ */
 const char* tk_last_error(void);

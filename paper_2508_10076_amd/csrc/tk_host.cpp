@@ -701,7 +701,7 @@ struct tk_plan {
   std::vector<PairDesc> pairs;
   DevBuf d_descs, d_rowmap, d_colmap, d_pairs;
   // tile schedule
-  int tile_m = 128, tile_n = 128;
+  int tile_m = 128, tile_n = 128, tile_k = 16;
   std::vector<GemmTile> tiles;
   std::vector<int32_t> wg_first;
   DevBuf d_tiles, d_wg;
@@ -729,7 +729,7 @@ struct tk_batch {
   std::vector<PairDesc> pairs;
   DevBuf d_descs, d_rowmap, d_colmap, d_pairs, d_tiles, d_wg, d_table;
   std::vector<std::unique_ptr<DevBuf>> ws;
-  int tile_m = 128, tile_n = 128;
+  int tile_m = 128, tile_n = 128, tile_k = 16;
   std::vector<GemmTile> tiles;
   std::vector<int32_t> wg_first;
   double flops = 0;
@@ -757,8 +757,7 @@ struct Sched {
   double makespan = 0;
 };
 
-Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_t split_target) {
-  constexpr int BK = 16;
+Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg, int64_t split_target) {
   struct U {
     GemmTile t;
     int64_t cost;
@@ -791,9 +790,9 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_
           t.group = group;
           t.slot0 = slot0;
           if (S > 1 && sp == 0) out.groups.push_back(t);
-          // cost in stages: prologue/epilogue ~3, a split unit writes its
-          // partial tile instead (~2)
-          const int64_t cost = (s1 - s0) + 3;
+          // cost in 16-deep stages: prologue/epilogue ~3, a split unit
+          // writes its partial tile instead (~2)
+          const int64_t cost = (s1 - s0) * (BK / 16) + 3;
           units.push_back({t, cost});
         }
       }
@@ -824,14 +823,14 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg, int64_
   return out;
 }
 
-Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int max_wg) {
-  Sched best = lpt(descs, tm, tn, max_wg, 0);
+Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int max_wg) {
+  Sched best = lpt(descs, tm, tn, tk, max_wg, 0);
   if (descs.empty()) return best;
   int64_t total = 0;
-  for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + 15) / 16);
+  for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + tk - 1) / tk);
   for (int per_wg : {3, 4, 6, 8}) {
-    const int64_t target = std::max<int64_t>(8, total / (int64_t(max_wg) * per_wg));
-    Sched s = lpt(descs, tm, tn, max_wg, target);
+    const int64_t target = std::max<int64_t>(4, total / (int64_t(max_wg) * per_wg));
+    Sched s = lpt(descs, tm, tn, tk, max_wg, target);
     if (s.makespan < 0.97 * best.makespan) best = std::move(s);
   }
   return best;
@@ -845,10 +844,11 @@ void upload_schedule(DevBuf& d_tiles, DevBuf& d_wg, DevBuf& d_partials, DevBuf& 
   d_groups.upload(sc.groups);
 }
 
-void plan_reschedule(tk_plan& P, int tm, int tn) {
+void plan_reschedule(tk_plan& P, int tm, int tn, int tk) {
   P.tile_m = tm;
   P.tile_n = tn;
-  Sched sc = schedule_tiles(P.descs, tm, tn, P.ctx ? P.ctx->num_cu : 256);
+  P.tile_k = tk;
+  Sched sc = schedule_tiles(P.descs, tm, tn, tk, P.ctx ? P.ctx->num_cu : 256);
   P.tiles = sc.tiles;
   P.wg_first = sc.wg_first;
   P.groups = sc.groups;
@@ -857,14 +857,16 @@ void plan_reschedule(tk_plan& P, int tm, int tn) {
   if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
 }
 
-void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn) {
-  int64_t mmax = 0, nmax = 0;
+void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn, int* tk) {
+  int64_t mmax = 0, nmax = 0, kmax = 0;
   for (const auto& d : descs) {
     mmax = std::max<int64_t>(mmax, d.M);
     nmax = std::max<int64_t>(nmax, d.N);
+    kmax = std::max<int64_t>(kmax, d.K);
   }
   *tm = mmax > 64 ? 128 : 64;
   *tn = nmax > 64 ? 128 : 64;
+  *tk = kmax >= 256 ? 32 : 16;
 }
 
 std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A, std::vector<int> pA,
@@ -880,7 +882,8 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
   if (qA.size() != pB.size()) fail(TK_ERR_INVALID_ARG, "qA and pB differ in length");
   check_perm(pAB, qAB, static_cast<int>(pA.size() + qB.size()));
   if (precision < TK_PREC_NATIVE || precision > TK_PREC_BF16X3) fail(TK_ERR_INVALID_ARG, "unknown precision");
-  if (!tk::gemm_tile_supported(A->dtype, precision, 128, 128) && !tk::gemm_tile_supported(A->dtype, precision, 64, 64))
+  if (!tk::gemm_tile_supported(A->dtype, precision, 128, 128, 16) &&
+      !tk::gemm_tile_supported(A->dtype, precision, 64, 64, 16))
     fail(TK_ERR_DTYPE, "this dtype / precision combination is not available");
 
   auto P = std::make_unique<tk_plan>();
@@ -1112,12 +1115,12 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
   }
 
   pack_workgroups(P->smallk);
-  int tm, tn;
-  choose_default_tile(P->descs, &tm, &tn);
+  int tm, tn, tkk;
+  choose_default_tile(P->descs, &tm, &tn, &tkk);
   {
     tk_context* keep = P->ctx;
     P->ctx = nullptr;  // schedule only; uploads follow below
-    plan_reschedule(*P, tm, tn);
+    plan_reschedule(*P, tm, tn, tkk);
     P->ctx = keep;
   }
 
@@ -1189,10 +1192,10 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
     ga_.ptrs = ptrs;
     ga_.alpha = P.post ? 1.0 : ga;
     ga_.beta = gb;
-    hip_check(tk::launch_gemm(P.dtype, P.precision, P.tile_m, P.tile_n, ga_, static_cast<int>(P.wg_first.size()) - 1,
-                              stream),
+    hip_check(tk::launch_gemm(P.dtype, P.precision, P.tile_m, P.tile_n, P.tile_k, ga_,
+                              static_cast<int>(P.wg_first.size()) - 1, stream),
               "gemm launch");
-    hip_check(tk::launch_splitk_reduce(P.dtype, P.precision, P.tile_m, P.tile_n, ga_,
+    hip_check(tk::launch_splitk_reduce(P.dtype, P.precision, P.tile_m, P.tile_n, P.tile_k, ga_,
                                        static_cast<const GemmTile*>(P.d_groups.p), P.ngroups, stream),
               "split-K reduce launch");
   }
@@ -1575,7 +1578,7 @@ tk_status tk_plan_destroy(tk_plan* plan) {
 }
 
 tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero, int64_t* workspace_bytes,
-                       int32_t* tile_m, int32_t* tile_n) {
+                       int32_t* tile_m, int32_t* tile_n, int32_t* tile_k) {
   return guarded([&] {
     if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
     if (ngemm) *ngemm = static_cast<int64_t>(plan->mnk.size() / 3);
@@ -1588,6 +1591,7 @@ tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64
     }
     if (tile_m) *tile_m = plan->tile_m;
     if (tile_n) *tile_n = plan->tile_n;
+    if (tile_k) *tile_k = plan->tile_k;
   });
 }
 
@@ -1643,20 +1647,21 @@ tk_status tk_tensor_contract(tk_context* ctx, const tk_tensor* A, const int32_t*
   });
 }
 
-tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mn) {
+tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mnk) {
   return guarded([&] {
     if (!count) fail(TK_ERR_INVALID_ARG, "null count");
     *count = tk::num_tile_shapes();
-    if (tile_mn)
-      for (int i = 0; i < *count; ++i) tk::tile_shape(i, &tile_mn[2 * i], &tile_mn[2 * i + 1]);
+    if (tile_mnk)
+      for (int i = 0; i < *count; ++i) tk::tile_shape(i, &tile_mnk[3 * i], &tile_mnk[3 * i + 1], &tile_mnk[3 * i + 2]);
   });
 }
 
-tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n) {
+tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n, int32_t tile_k) {
   return guarded([&] {
     if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
-    if (!tk::gemm_tile_supported(plan->dtype, plan->precision, tile_m, tile_n)) fail(TK_ERR_UNSUPPORTED, "tile shape not available");
-    plan_reschedule(*plan, tile_m, tile_n);
+    if (!tk::gemm_tile_supported(plan->dtype, plan->precision, tile_m, tile_n, tile_k))
+      fail(TK_ERR_UNSUPPORTED, "tile shape not available");
+    plan_reschedule(*plan, tile_m, tile_n, tile_k);
   });
 }
 
@@ -1686,10 +1691,11 @@ void merge_smallk(SmallKList& dst, const SmallKList& src, int member) {
   for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
 }
 
-void batch_schedule(tk_batch& b, int tm, int tn) {
+void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
   b.tile_m = tm;
   b.tile_n = tn;
-  Sched sc = schedule_tiles(b.descs, tm, tn, b.ctx->num_cu);
+  b.tile_k = tk;
+  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu);
   b.tiles = sc.tiles;
   b.wg_first = sc.wg_first;
   b.groups = sc.groups;
@@ -1717,10 +1723,10 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
     ga.ptrs = ptrs;
     ga.alpha = b.alpha;
     ga.beta = b.beta;
-    hip_check(tk::launch_gemm(b.dtype, b.precision, b.tile_m, b.tile_n, ga, static_cast<int>(b.wg_first.size()) - 1,
-                              stream),
+    hip_check(tk::launch_gemm(b.dtype, b.precision, b.tile_m, b.tile_n, b.tile_k, ga,
+                              static_cast<int>(b.wg_first.size()) - 1, stream),
               "gemm launch");
-    hip_check(tk::launch_splitk_reduce(b.dtype, b.precision, b.tile_m, b.tile_n, ga,
+    hip_check(tk::launch_splitk_reduce(b.dtype, b.precision, b.tile_m, b.tile_n, b.tile_k, ga,
                                        static_cast<const GemmTile*>(b.d_groups.p), b.ngroups, stream),
               "split-K reduce launch");
   }
@@ -1794,9 +1800,9 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       b->flops += P.flops;
     }
     if (b->descs.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many GEMMs");
-    int tm, tn;
-    choose_default_tile(b->descs, &tm, &tn);
-    batch_schedule(*b, tm, tn);
+    int tm, tn, tkk;
+    choose_default_tile(b->descs, &tm, &tn, &tkk);
+    batch_schedule(*b, tm, tn, tkk);
     b->pre.upload();
     b->zero.upload();
     b->smallk.upload();
@@ -1851,7 +1857,7 @@ tk_status tk_batch_replay(tk_batch* batch, void* stream) {
 }
 
 tk_status tk_batch_info(const tk_batch* batch, int64_t* ngemm, int64_t* ntiles, double* flops, int32_t* tile_m,
-                        int32_t* tile_n) {
+                        int32_t* tile_n, int32_t* tile_k) {
   return guarded([&] {
     if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
     if (ngemm) *ngemm = static_cast<int64_t>(batch->descs.size());
@@ -1859,15 +1865,16 @@ tk_status tk_batch_info(const tk_batch* batch, int64_t* ngemm, int64_t* ntiles, 
     if (flops) *flops = batch->flops;
     if (tile_m) *tile_m = batch->tile_m;
     if (tile_n) *tile_n = batch->tile_n;
+    if (tile_k) *tile_k = batch->tile_k;
   });
 }
 
-tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n) {
+tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int32_t tile_k) {
   return guarded([&] {
     if (!batch) fail(TK_ERR_INVALID_ARG, "null batch");
-    if (!tk::gemm_tile_supported(batch->dtype, batch->precision, tile_m, tile_n))
+    if (!tk::gemm_tile_supported(batch->dtype, batch->precision, tile_m, tile_n, tile_k))
       fail(TK_ERR_UNSUPPORTED, "tile shape not available");
-    batch_schedule(*batch, tile_m, tile_n);
+    batch_schedule(*batch, tile_m, tile_n, tile_k);
     if (batch->exec) {
       (void)hipGraphExecDestroy(batch->exec);
       batch->exec = nullptr;

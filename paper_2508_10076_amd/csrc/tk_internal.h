@@ -130,14 +130,14 @@ struct GemmArgs {
 // Launchers (tk_kernels.hip).  dtype: 0 fp64, 1 fp32.  precision: tk_precision.
 hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
                           const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
-hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                        int nwg, hipStream_t stream);
-hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
 hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
-bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n);
+bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k);
 int num_tile_shapes();
-void tile_shape(int i, int* tm, int* tn);
+void tile_shape(int i, int* tm, int* tn, int* tk);
 
 }  // namespace tk

@@ -10,6 +10,8 @@
 //    scattering every element straight to its place in C.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tk_internal.h"
 
 namespace tk {
@@ -103,12 +105,12 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
 // HBM), so every global load is coalesced along the contiguous axis.  Stage
 // s+2 is fetched into registers while stage s is multiplied and is written to
 // the free LDS buffer at the start of stage s+1: one barrier per stage.
-// Within one MFMA the k index is lane/16; step j of the 4 steps of a stage
-// uses k = 4*(lane/16) + j for both operands.
-template <int BM, int BN, int WGM, int WGN>
+// Within one MFMA the k index is lane/16; step j of the BK/4 steps of a
+// stage uses k = (BK/4)*(lane/16) + j for both operands.
+template <int BM, int BN, int WGM, int WGN, int BK_ = 16>
 struct F64Tile {
   static constexpr int NT = 64 * WGM * WGN;
-  static constexpr int BK = 16, APAD = 2, BPAD = 2;
+  static constexpr int BK = BK_, APAD = 2, BPAD = 2;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
   static constexpr int TM = WM / 16, TN = WN / 16;
   static constexpr int A_TPM = NT / BM;  // threads sharing one m row
@@ -118,12 +120,13 @@ struct F64Tile {
   static constexpr int NACC = TM * TN * 4;  // accumulator doubles per lane
   static_assert(NT % BM == 0 && BK % A_TPM == 0 && A_LD >= 1, "A tile");
   static_assert(BN % B_CPL == 0 && B_LD >= 1, "B tile");
+  static_assert(BK % 16 == 0, "stage depth");
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
 };
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, int BK_>
 __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs args) {
-  using TT = F64Tile<BM, BN, WGM, WGN>;
+  using TT = F64Tile<BM, BN, WGM, WGN, BK_>;
   constexpr int NT = TT::NT, BK = TT::BK, TM = TT::TM, TN = TT::TN;
   constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD, B_CPL = TT::B_CPL, B_LD = TT::B_LD;
   __shared__ double As[2][BK][BM + TT::APAD];
@@ -134,7 +137,9 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
   const int g = lane >> 4, l16 = lane & 15;
   const int wm = (wave % WGM) * TT::WM, wn = (wave / WGM) * TT::WN;
   const int a_m = tid % BM, a_k = tid / BM;
-  const int b_k = tid & 15, b_n = tid >> 4;
+  const int b_k = tid % BK, b_n = tid / BK;
+  constexpr int B_NPL = NT / BK;  // columns of B covered per load
+  constexpr int B_LDK = BN / B_NPL;
 
   for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
     const GemmTile tile = args.tiles[ti];
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
 
-    double ra[A_LD], rb[B_LD];
+    double ra[A_LD], rb[B_LDK];
     const int am = tile.m0 + a_m;
     const bool a_ok = am < d.M;
     const double* Arow = A + am;
@@ -160,8 +165,8 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
         ra[i] = (a_ok && k < kend) ? Arow[static_cast<int64_t>(k) * d.lda] : 0.0;
       }
 #pragma unroll
-      for (int i = 0; i < B_LD; ++i) {
-        const int n = tile.n0 + b_n + B_CPL * i;
+      for (int i = 0; i < B_LDK; ++i) {
+        const int n = tile.n0 + b_n + B_NPL * i;
         const int k = k0 + b_k;
         rb[i] = (n < d.N && k < kend) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
       }
@@ -170,16 +175,16 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 #pragma unroll
       for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
 #pragma unroll
-      for (int i = 0; i < B_LD; ++i) Bs[buf][b_n + B_CPL * i][b_k] = rb[i];
+      for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[i];
     };
     auto compute = [&](int cur) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < BK / 4; ++j) {
         double af[TM], bf[TN];
 #pragma unroll
-        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][4 * g + j][wm + 16 * mi + l16];
+        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
 #pragma unroll
-        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][4 * g + j];
+        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][(BK / 4) * g + j];
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -220,7 +225,9 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 #pragma unroll
         for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
+          for (int v = 0; v < 4; ++v)
+            if (tile.m0 + wm + 16 * mi + g + 4 * v < d.M && tile.n0 + wn + 16 * ni + l16 < d.N)
+              mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
     } else {
       double* C = buf_ptr<double>(args.ptrs, d.c_buf);
 #pragma unroll
@@ -236,32 +243,33 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
   }
 }
 
-// Sum of the K-split partial tiles of one split group, in split order (a
+// Sum of the K-split partial tiles of the split groups, in split order (a
 // fixed order: the result does not depend on which unit finished first),
-// then the same epilogue as an unsplit tile.  One workgroup per group; each
-// thread owns the same accumulator elements as in gemm_f64_kernel.
+// then the same epilogue as an unsplit tile.  A flat stream over (group,
+// element) pairs: element e of a partial tile is the accumulator value the
+// GEMM thread e % NT held as its value number e / NT.
 template <int BM, int BN, int WGM, int WGN>
-__global__ __launch_bounds__(64 * WGM* WGN) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups) {
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
-  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, l16 = lane & 15;
-  const int wm = (wave % WGM) * TT::WM, wn = (wave / WGM) * TT::WN;
-  const GemmTile tile = groups[blockIdx.x];
-  const GemmDesc d = args.descs[tile.gemm];
-  double* C = buf_ptr<double>(args.ptrs, d.c_buf);
-#pragma unroll
-  for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t e = ((mi * TN + ni) * 4 + v) * NT + tid;
-        double sum = 0.0;
-        for (int j = 0; j < tile.nsplit; ++j) sum += args.partials[static_cast<int64_t>(tile.slot0 + j) * (BM * BN) + e];
-        store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v, tile.n0 + wn + 16 * ni + l16, sum);
-      }
+  constexpr int NT = TT::NT, TN = TT::TN;
+  for (int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; x < total;
+       x += static_cast<int64_t>(gridDim.x) * 256) {
+    const int grp = static_cast<int>(x / (BM * BN));
+    const int e = static_cast<int>(x % (BM * BN));
+    const int tid = e % NT, val = e / NT;
+    const int v = val & 3, t = val >> 2;
+    const int mi = t / TN, ni = t % TN;
+    const int lane = tid & 63, wave = tid >> 6;
+    const GemmTile tile = groups[grp];
+    const GemmDesc d = args.descs[tile.gemm];
+    const int r = tile.m0 + (wave % WGM) * TT::WM + 16 * mi + (lane >> 4) + 4 * v;
+    const int c = tile.n0 + (wave / WGM) * TT::WN + 16 * ni + (lane & 15);
+    if (r >= d.M || c >= d.N) continue;
+    double sum = 0.0;
+    const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
+    for (int j = 0; j < tile.nsplit; ++j) sum += p[static_cast<int64_t>(j) * (BM * BN)];
+    store_elem<double>(args, d, buf_ptr<double>(args.ptrs, d.c_buf), r, c, sum);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -376,50 +384,60 @@ hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, cons
   return hipGetLastError();
 }
 
+// Tile configurations of the fp64 grouped GEMM: (tile_m, tile_n, stage
+// depth) and the wave grid that covers the tile.
+#define TK_F64_SHAPES(X)                                                                              \
+  X(128, 128, 16, 2, 4) X(128, 128, 32, 2, 4) X(128, 64, 16, 2, 2) X(128, 64, 32, 2, 2)              \
+  X(64, 128, 16, 2, 4) X(64, 128, 32, 2, 4) X(64, 64, 16, 2, 2) X(64, 64, 32, 2, 2)
+
 struct TileShape {
-  int m, n;
+  int m, n, k;
 };
-static const TileShape kTiles[] = {{128, 128}, {128, 64}, {64, 128}, {64, 64}};
+static const TileShape kTiles[] = {
+#define TK_SHAPE_ENTRY(BM_, BN_, BK_, WM_, WN_) {BM_, BN_, BK_},
+    TK_F64_SHAPES(TK_SHAPE_ENTRY)
+#undef TK_SHAPE_ENTRY
+};
 
 int num_tile_shapes() { return static_cast<int>(sizeof(kTiles) / sizeof(kTiles[0])); }
-void tile_shape(int i, int* tm, int* tn) {
+void tile_shape(int i, int* tm, int* tn, int* tk) {
   *tm = kTiles[i].m;
   *tn = kTiles[i].n;
+  *tk = kTiles[i].k;
 }
 
-bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n) {
+bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k) {
   if (dtype != 0 || precision != 0) return false;
   for (const auto& t : kTiles)
-    if (t.m == tile_m && t.n == tile_n) return true;
+    if (t.m == tile_m && t.n == tile_n && t.k == tile_k) return true;
   return false;
 }
 
-// wave grid per tile shape: 8 waves for 128-wide tiles, 4 for 64 x 64
-#define TK_F64_SHAPES(X) X(128, 128, 2, 4) X(128, 64, 2, 2) X(64, 128, 2, 4) X(64, 64, 2, 2)
-
-hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args, int nwg,
+hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args, int nwg,
                        hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
-  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n)) return hipErrorInvalidValue;
-#define TK_GEMM_CASE(BM_, BN_, WM_, WN_)                                                                  \
-  if (tile_m == BM_ && tile_n == BN_) {                                                                   \
-    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_, WM_, WN_>), dim3(nwg), dim3(64 * WM_ * WN_), 0, stream, \
-                       args);                                                                             \
-    return hipGetLastError();                                                                             \
+  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
+#define TK_GEMM_CASE(BM_, BN_, BK_, WM_, WN_)                                                              \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                   \
+    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_, WM_, WN_, BK_>), dim3(nwg), dim3(64 * WM_ * WN_), 0, stream, \
+                       args);                                                                              \
+    return hipGetLastError();                                                                              \
   }
   TK_F64_SHAPES(TK_GEMM_CASE)
 #undef TK_GEMM_CASE
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, const GemmArgs& args,
+hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream) {
   if (ngroups <= 0) return hipSuccess;
-  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n)) return hipErrorInvalidValue;
-#define TK_RED_CASE(BM_, BN_, WM_, WN_)                                                                        \
-  if (tile_m == BM_ && tile_n == BN_) {                                                                        \
-    hipLaunchKernelGGL((splitk_reduce_kernel<BM_, BN_, WM_, WN_>), dim3(ngroups), dim3(64 * WM_ * WN_), 0, \
-                       stream, args, groups);                                                                  \
+  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
+  const int64_t total = static_cast<int64_t>(ngroups) * tile_m * tile_n;
+  const unsigned nblk = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 65536));
+#define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                                   \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                       \
+    hipLaunchKernelGGL((splitk_reduce_kernel<BM_, BN_, WM_, WN_>), dim3(nblk), dim3(256), 0, stream, args, groups, \
+                       total);                                                                                 \
     return hipGetLastError();                                                                                  \
   }
   TK_F64_SHAPES(TK_RED_CASE)

@@ -71,7 +71,7 @@ _SIGS = {
     "tk_plan_execute": [_P, _P, _P, _P, C.c_double, C.c_double, _P],
     "tk_plan_destroy": [_P],
     "tk_plan_execute_stages": [_P, _P, _P, _P, C.c_double, C.c_double, C.c_int32, _P],
-    "tk_plan_info": [_P, _I64P, C.POINTER(C.c_double), _I64P, _I64P, _I32P, _I32P],
+    "tk_plan_info": [_P, _I64P, C.POINTER(C.c_double), _I64P, _I64P, _I32P, _I32P, _I32P],
     "tk_plan_gemms": [_P, C.c_int64, C.c_int64, _I64P],
     "tk_permute_map": [_P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I64P, _I32P],
     "tk_batch_create": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, C.c_double,
@@ -79,11 +79,11 @@ _SIGS = {
     "tk_batch_launch": [_P, _P],
     "tk_batch_capture": [_P, _P],
     "tk_batch_replay": [_P, _P],
-    "tk_batch_info": [_P, _I64P, _I64P, C.POINTER(C.c_double), _I32P, _I32P],
+    "tk_batch_info": [_P, _I64P, _I64P, C.POINTER(C.c_double), _I32P, _I32P, _I32P],
     "tk_batch_destroy": [_P],
     "tk_tile_shapes": [_I32P, _I32P],
-    "tk_plan_set_tile": [_P, C.c_int32, C.c_int32],
-    "tk_batch_set_tile": [_P, C.c_int32, C.c_int32],
+    "tk_plan_set_tile": [_P, C.c_int32, C.c_int32, C.c_int32],
+    "tk_batch_set_tile": [_P, C.c_int32, C.c_int32, C.c_int32],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
@@ -372,11 +372,11 @@ class Plan:
     def info(self):
         ng, nz, ws = C.c_int64(), C.c_int64(), C.c_int64()
         fl = C.c_double()
-        tm, tn = C.c_int32(), C.c_int32()
+        tm, tn, tkk = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib.tk_plan_info(self.h, C.byref(ng), C.byref(fl), C.byref(nz), C.byref(ws), C.byref(tm),
-                                C.byref(tn)))
+                                C.byref(tn), C.byref(tkk)))
         return dict(ngemm=ng.value, flops=fl.value, nzero=nz.value, workspace_bytes=ws.value,
-                    tile=(tm.value, tn.value))
+                    tile=(tm.value, tn.value, tkk.value))
 
     def gemms(self):
         n = self.info()["ngemm"]
@@ -385,8 +385,8 @@ class Plan:
             _check(lib.tk_plan_gemms(self.h, 0, n, out.ctypes.data_as(_I64P)))
         return out
 
-    def set_tile(self, tm, tn):
-        _check(lib.tk_plan_set_tile(self.h, int(tm), int(tn)))
+    def set_tile(self, tm, tn, tk_):
+        _check(lib.tk_plan_set_tile(self.h, int(tm), int(tn), int(tk_)))
 
     def close(self):
         if self.h:
@@ -419,15 +419,16 @@ class Batch:
     def replay(self, stream=None):
         _check(lib.tk_batch_replay(self.h, _stream(stream)))
 
-    def set_tile(self, tm, tn):
-        _check(lib.tk_batch_set_tile(self.h, int(tm), int(tn)))
+    def set_tile(self, tm, tn, tk_):
+        _check(lib.tk_batch_set_tile(self.h, int(tm), int(tn), int(tk_)))
 
     def info(self):
         ng, nt = C.c_int64(), C.c_int64()
         fl = C.c_double()
-        tm, tn = C.c_int32(), C.c_int32()
-        _check(lib.tk_batch_info(self.h, C.byref(ng), C.byref(nt), C.byref(fl), C.byref(tm), C.byref(tn)))
-        return dict(ngemm=ng.value, ntiles=nt.value, flops=fl.value, tile=(tm.value, tn.value))
+        tm, tn, tkk = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib.tk_batch_info(self.h, C.byref(ng), C.byref(nt), C.byref(fl), C.byref(tm), C.byref(tn),
+                                 C.byref(tkk)))
+        return dict(ngemm=ng.value, ntiles=nt.value, flops=fl.value, tile=(tm.value, tn.value, tkk.value))
 
     def close(self):
         if self.h:
@@ -444,9 +445,9 @@ class Batch:
 def tile_shapes():
     n = C.c_int32()
     _check(lib.tk_tile_shapes(C.byref(n), None))
-    arr = (C.c_int32 * (2 * n.value))()
+    arr = (C.c_int32 * (3 * n.value))()
     _check(lib.tk_tile_shapes(C.byref(n), arr))
-    return [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
+    return [(arr[3 * i], arr[3 * i + 1], arr[3 * i + 2]) for i in range(n.value)]
 
 
 def version():
