@@ -757,6 +757,32 @@ struct Sched {
   double makespan = 0;
 };
 
+// Relative MFMA time of a tile whose valid extent is (mrem, nrem) rows and
+// columns: waves of the GEMM kernel whose sub-tile is empty skip their MFMAs,
+// and the tile takes as long as its busiest SIMD (waves w and w + NW/2 share
+// one; the placement mirrors wave_origin in the kernel).
+double tile_activity(int tm, int tn, int64_t mrem, int64_t nrem) {
+  const int wgm = 2, wgn = (tm == 128 && tn == 128) || (tm == 64 && tn == 128) ? 4 : 2;
+  const int nw = wgm * wgn, wmsz = tm / wgm, wnsz = tn / wgn;
+  auto origin = [&](int w, int* wm, int* wn) {
+    const int half = nw / 2, r = w / half, c = w % half;
+    *wm = r * wmsz;
+    *wn = ((c + r * (half / 2)) % half) * wnsz;
+  };
+  int busiest = 0;
+  for (int simd = 0; simd < 4; ++simd) {
+    int act = 0;
+    for (int w = simd; w < nw; w += 4) {
+      int wm, wn;
+      origin(w, &wm, &wn);
+      act += (wm < mrem && wn < nrem) ? 1 : 0;
+    }
+    busiest = std::max(busiest, act);
+  }
+  const int per_simd = (nw + 3) / 4;
+  return double(busiest) / per_simd;
+}
+
 Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg, int64_t split_target) {
   struct U {
     GemmTile t;
@@ -790,9 +816,10 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
           t.group = group;
           t.slot0 = slot0;
           if (S > 1 && sp == 0) out.groups.push_back(t);
-          // cost in 16-deep stages: prologue/epilogue ~3, a split unit
-          // writes its partial tile instead (~2)
-          const int64_t cost = (s1 - s0) * (BK / 16) + 3;
+          // cost in quarter 16-deep stages: MFMA work scaled by the tile's
+          // activity, plus prologue/epilogue (~3 stages)
+          const double act = tile_activity(tm, tn, d.M - m0, d.N - n0);
+          const int64_t cost = static_cast<int64_t>(4.0 * (s1 - s0) * (BK / 16) * act) + 12;
           units.push_back({t, cost});
         }
       }
@@ -814,7 +841,7 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
   // the reduce kernel reads and writes every partial once: at ~5 TB/s one
   // 16-deep fp64 stage of MFMA work (4096 cycles at 2.4 GHz) moves ~8.5 MB
   const double red_bytes = 2.0 * out.nslots * double(tm) * tn * 8.0;
-  out.makespan = static_cast<double>(mk) + (out.nslots ? 2.0 + red_bytes / 8.5e6 : 0.0);
+  out.makespan = static_cast<double>(mk) / 4.0 + (out.nslots ? 2.0 + red_bytes / 8.5e6 : 0.0);
   out.wg_first.assign(1, 0);
   for (int w = 0; w < nwg; ++w) {
     out.tiles.insert(out.tiles.end(), per[w].begin(), per[w].end());
@@ -828,7 +855,7 @@ Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk,
   if (descs.empty()) return best;
   int64_t total = 0;
   for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + tk - 1) / tk);
-  for (int per_wg : {3, 4, 6, 8}) {
+  for (int per_wg : {2, 3, 4, 6, 8}) {
     const int64_t target = std::max<int64_t>(4, total / (int64_t(max_wg) * per_wg));
     Sched s = lpt(descs, tm, tn, tk, max_wg, target);
     if (s.makespan < 0.97 * best.makespan) best = std::move(s);

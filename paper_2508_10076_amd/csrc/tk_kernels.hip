@@ -24,6 +24,11 @@ __device__ __forceinline__ T* buf_ptr(const Ptrs& P, int id) {
 // ---------------------------------------------------------------------------
 // permute / zero-fill
 // ---------------------------------------------------------------------------
+// Each thread handles up to kBatch elements of a task at a time: all their
+// offsets and loads are issued before any store, so many loads are in flight
+// per thread (the kernel is bound by HBM bandwidth and latency, not ALU).
+constexpr int kBatch = 8;
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __restrict__ tasks,
                                                            const int32_t* __restrict__ wg_first,
@@ -35,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
     const int n = tk->n;
     const int count = tk->count;
     const uint32_t start = static_cast<uint32_t>(tk->start);
-    const float sign = tk->sign;
+    const T sign = static_cast<T>(tk->sign);
     int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
 #pragma unroll
     for (int d = 0; d < kMaxDims; ++d) {
@@ -43,26 +48,50 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
       ss[d] = tk->ss[d];
       ds[d] = tk->ds[d];
     }
-    T* dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-    const T* src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
-    for (int e = threadIdx.x; e < count; e += kThreads) {
-      uint32_t lin = start + static_cast<uint32_t>(e);
-      int64_t so = 0, dof = 0;
+    T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+    const T* __restrict__ src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
+    for (int e0 = 0; e0 < count; e0 += kThreads * kBatch) {
+      int64_t so[kBatch], dof[kBatch];
+      T v[kBatch];
 #pragma unroll
-      for (int d = 0; d < kMaxDims; ++d) {
-        if (d < n) {
-          const uint32_t ext = static_cast<uint32_t>(dim[d]);
-          const uint32_t q = lin / ext;
-          const uint32_t i = lin - q * ext;
-          lin = q;
-          so += static_cast<int64_t>(i) * ss[d];
-          dof += static_cast<int64_t>(i) * ds[d];
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + u * kThreads + threadIdx.x;
+        uint32_t lin = start + static_cast<uint32_t>(e);
+        int64_t a = 0, b = 0;
+#pragma unroll
+        for (int d = 0; d < kMaxDims; ++d) {
+          if (d < n) {
+            const uint32_t ext = static_cast<uint32_t>(dim[d]);
+            const uint32_t q = lin / ext;
+            const uint32_t i = lin - q * ext;
+            lin = q;
+            a += static_cast<int64_t>(i) * ss[d];
+            b += static_cast<int64_t>(i) * ds[d];
+          }
         }
+        so[u] = a;
+        dof[u] = b;
       }
-      T v = src ? static_cast<T>(src[so] * static_cast<T>(sign)) : static_cast<T>(0);
-      v = static_cast<T>(alpha) * v;
-      if (beta != 0.0) v += static_cast<T>(beta) * dst[dof];
-      dst[dof] = v;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + u * kThreads + threadIdx.x;
+        v[u] = (src && e < count) ? src[so[u]] * sign : static_cast<T>(0);
+      }
+      if (beta != 0.0) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int e = e0 + u * kThreads + threadIdx.x;
+          if (e < count) v[u] = static_cast<T>(alpha) * v[u] + static_cast<T>(beta) * dst[dof[u]];
+        }
+      } else if (alpha != 1.0) {
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v[u] = static_cast<T>(alpha) * v[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + u * kThreads + threadIdx.x;
+        if (e < count) dst[dof[u]] = v[u];
+      }
     }
   }
 }
@@ -107,8 +136,9 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
 // the free LDS buffer at the start of stage s+1: one barrier per stage.
 // Within one MFMA the k index is lane/16; step j of the BK/4 steps of a
 // stage uses k = (BK/4)*(lane/16) + j for both operands.
-template <int BM, int BN, int WGM, int WGN, int BK_ = 16>
+template <int BM, int BN, int WGM_, int WGN_, int BK_ = 16>
 struct F64Tile {
+  static constexpr int WGM = WGM_, WGN = WGN_;
   static constexpr int NT = 64 * WGM * WGN;
   static constexpr int BK = BK_, APAD = 2, BPAD = 2;
   static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -124,6 +154,26 @@ struct F64Tile {
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
 };
 
+// Origin of wave w's sub-tile.  Waves w and w + NW/2 share a SIMD (waves of
+// a workgroup are spread round robin over the 4 SIMDs of a CU); the first
+// half of the waves covers the top row band, the second half the bottom row
+// band with the column bands rotated by half, so that when the bottom rows
+// or the right columns of an edge tile are empty every SIMD keeps one busy
+// wave and the tile takes about half the time.
+template <class TT>
+__device__ __forceinline__ void wave_origin(int w, int* wm, int* wn) {
+  constexpr int NW = TT::NT / 64;
+  if (TT::WGM == 2 && NW >= 4) {
+    const int half = NW / 2;
+    const int r = w / half, c = w % half;
+    *wm = r * TT::WM;
+    *wn = ((c + r * (half / 2)) % half) * TT::WN;
+  } else {
+    *wm = (w % TT::WGM) * TT::WM;
+    *wn = (w / TT::WGM) * TT::WN;
+  }
+}
+
 template <int BM, int BN, int WGM, int WGN, int BK_>
 __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs args) {
   using TT = F64Tile<BM, BN, WGM, WGN, BK_>;
@@ -135,7 +185,8 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int wm = (wave % WGM) * TT::WM, wn = (wave / WGM) * TT::WN;
+  int wm, wn;
+  wave_origin<TT>(wave, &wm, &wn);
   const int a_m = tid % BM, a_k = tid / BM;
   const int b_k = tid % BK, b_n = tid / BK;
   constexpr int B_NPL = NT / BK;  // columns of B covered per load
@@ -177,7 +228,11 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 #pragma unroll
       for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[i];
     };
+    // a wave whose whole sub-tile lies past M or N skips its MFMAs (uniform
+    // per wave); see wave_origin for why that shortens edge tiles
+    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
     auto compute = [&](int cur) {
+      if (!active) return;
 #pragma unroll
       for (int j = 0; j < BK / 4; ++j) {
         double af[TM], bf[TN];
@@ -262,8 +317,10 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const int lane = tid & 63, wave = tid >> 6;
     const GemmTile tile = groups[grp];
     const GemmDesc d = args.descs[tile.gemm];
-    const int r = tile.m0 + (wave % WGM) * TT::WM + 16 * mi + (lane >> 4) + 4 * v;
-    const int c = tile.n0 + (wave / WGM) * TT::WN + 16 * ni + (lane & 15);
+    int wm, wn;
+    wave_origin<TT>(wave, &wm, &wn);
+    const int r = tile.m0 + wm + 16 * mi + (lane >> 4) + 4 * v;
+    const int c = tile.n0 + wn + 16 * ni + (lane & 15);
     if (r >= d.M || c >= d.N) continue;
     double sum = 0.0;
     const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
@@ -281,6 +338,35 @@ __device__ __forceinline__ float bf16_round(float x) {
 
 // MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
 // each operand, three products, fp32 accumulation (the compensated mode).
+template <typename T, int MODE>
+__device__ __forceinline__ double smallk_dot(const T* __restrict__ ap, const T* __restrict__ bp, int K, int lda) {
+  if (MODE == 0) {
+    T s = 0;
+    for (int k = 0; k < K; ++k) s += ap[static_cast<int64_t>(k) * lda] * bp[k];
+    return static_cast<double>(s);
+  } else if (MODE == 1) {
+    float s = 0.f;
+    for (int k = 0; k < K; ++k)
+      s = fmaf(static_cast<float>(ap[static_cast<int64_t>(k) * lda]), static_cast<float>(bp[k]), s);
+    return s;
+  } else {
+    float s = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float x = static_cast<float>(ap[static_cast<int64_t>(k) * lda]);
+      const float y = static_cast<float>(bp[k]);
+      const float xh = bf16_round(x), yh = bf16_round(y);
+      const float xl = bf16_round(x - xh), yl = bf16_round(y - yh);
+      s = fmaf(xh, yh, s);
+      s = fmaf(xh, yl, s);
+      s = fmaf(xl, yh, s);
+    }
+    return s;
+  }
+}
+
+// MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
+// each operand, three products, fp32 accumulation (the compensated mode).
+// Elements are processed kBatch at a time per thread (loads before stores).
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __restrict__ tasks,
                                                           const int32_t* __restrict__ wg_first, Ptrs P,
@@ -301,52 +387,45 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
       cs[d] = tk->cs[d];
       ds[d] = tk->ds[d];
     }
-    const T* A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
-    const T* B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
-    T* D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-    for (int e = threadIdx.x; e < count; e += kThreads) {
-      uint32_t lin = start + static_cast<uint32_t>(e);
-      int64_t r = 0, c = 0, o = 0;
+    const T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
+    const T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
+    T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+    constexpr int U = kBatch / 2;
+    for (int e0 = 0; e0 < count; e0 += kThreads * U) {
+      int64_t r[U], c[U], o[U];
+      double acc[U];
 #pragma unroll
-      for (int d = 0; d < kMaxDims; ++d) {
-        if (d < n) {
-          const uint32_t ext = static_cast<uint32_t>(dim[d]);
-          const uint32_t q = lin / ext;
-          const uint32_t i = lin - q * ext;
-          lin = q;
-          r += static_cast<int64_t>(i) * rs[d];
-          c += static_cast<int64_t>(i) * cs[d];
-          o += static_cast<int64_t>(i) * ds[d];
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kThreads + threadIdx.x;
+        uint32_t lin = start + static_cast<uint32_t>(min(e, count - 1));
+        int64_t rr = 0, cc = 0, oo = 0;
+#pragma unroll
+        for (int d = 0; d < kMaxDims; ++d) {
+          if (d < n) {
+            const uint32_t ext = static_cast<uint32_t>(dim[d]);
+            const uint32_t q = lin / ext;
+            const uint32_t i = lin - q * ext;
+            lin = q;
+            rr += static_cast<int64_t>(i) * rs[d];
+            cc += static_cast<int64_t>(i) * cs[d];
+            oo += static_cast<int64_t>(i) * ds[d];
+          }
+        }
+        r[u] = rr;
+        c[u] = cc;
+        o[u] = oo;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] = smallk_dot<T, MODE>(A + r[u], B + c[u] * ldb, K, lda);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * kThreads + threadIdx.x;
+        if (e < count) {
+          double v = scale * acc[u];
+          if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
+          D[o[u]] = static_cast<T>(v);
         }
       }
-      const T* ap = A + r;
-      const T* bp = B + c * ldb;
-      double acc;
-      if (MODE == 0) {
-        T s = 0;
-        for (int k = 0; k < K; ++k) s += ap[static_cast<int64_t>(k) * lda] * bp[k];
-        acc = static_cast<double>(s);
-      } else if (MODE == 1) {
-        float s = 0.f;
-        for (int k = 0; k < K; ++k)
-          s = fmaf(static_cast<float>(ap[static_cast<int64_t>(k) * lda]), static_cast<float>(bp[k]), s);
-        acc = s;
-      } else {
-        float s = 0.f;
-        for (int k = 0; k < K; ++k) {
-          const float x = static_cast<float>(ap[static_cast<int64_t>(k) * lda]);
-          const float y = static_cast<float>(bp[k]);
-          const float xh = bf16_round(x), yh = bf16_round(y);
-          const float xl = bf16_round(x - xh), yl = bf16_round(y - yh);
-          s = fmaf(xh, yh, s);
-          s = fmaf(xh, yl, s);
-          s = fmaf(xl, yh, s);
-        }
-        acc = s;
-      }
-      double v = scale * acc;
-      if (beta != 0.0) v += beta * static_cast<double>(D[o]);
-      D[o] = static_cast<T>(v);
     }
   }
 }
