@@ -706,6 +706,7 @@ struct tk_plan {
   std::vector<int32_t> wg_first;
   DevBuf d_tiles, d_wg;
   int32_t ngroups = 0, nslots = 0;
+  double makespan = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
   SmallKList smallk;
@@ -881,6 +882,7 @@ void plan_reschedule(tk_plan& P, int tm, int tn, int tk) {
   P.groups = sc.groups;
   P.ngroups = sc.ngroups;
   P.nslots = sc.nslots;
+  P.makespan = sc.makespan;
   if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
 }
 
@@ -1619,6 +1621,20 @@ tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64
     if (tile_m) *tile_m = plan->tile_m;
     if (tile_n) *tile_n = plan->tile_n;
     if (tile_k) *tile_k = plan->tile_k;
+  });
+}
+
+tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
+  return guarded([&] {
+    if (!plan || !c) fail(TK_ERR_INVALID_ARG, "null argument");
+    const tk_plan& P = *plan;
+    const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
+                           static_cast<int64_t>(P.zero.tasks.size()), P.zero.nwg(),
+                           static_cast<int64_t>(P.smallk.tasks.size()), P.smallk.nwg(),
+                           static_cast<int64_t>(P.descs.size()), static_cast<int64_t>(P.tiles.size()),
+                           static_cast<int64_t>(P.wg_first.size()) - 1, P.ngroups, P.nslots,
+                           static_cast<int64_t>(P.makespan + 0.5)};
+    std::copy(v, v + 12, c);
   });
 }
 

@@ -29,71 +29,84 @@ __device__ __forceinline__ T* buf_ptr(const Ptrs& P, int id) {
 // per thread (the kernel is bound by HBM bandwidth and latency, not ALU).
 constexpr int kBatch = 8;
 
+// One task, processed by `nthr` threads starting at thread `t0` of the
+// workgroup (the whole workgroup for a large task, one wave for small ones).
+template <typename T>
+__device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, const Ptrs& P, double alpha,
+                                             double beta, int lt, int nthr) {
+  const int n = tk->n;
+  const int count = tk->count;
+  const uint32_t start = static_cast<uint32_t>(tk->start);
+  const T sign = static_cast<T>(tk->sign);
+  int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
+#pragma unroll
+  for (int d = 0; d < kMaxDims; ++d) {
+    dim[d] = tk->dim[d];
+    ss[d] = tk->ss[d];
+    ds[d] = tk->ds[d];
+  }
+  T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  const T* __restrict__ src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
+  for (int e0 = 0; e0 < count; e0 += nthr * kBatch) {
+    int64_t so[kBatch], dof[kBatch];
+    T v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * nthr + lt;
+      uint32_t lin = start + static_cast<uint32_t>(e);
+      int64_t a = 0, b = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < n) {
+          const uint32_t ext = static_cast<uint32_t>(dim[d]);
+          const uint32_t q = lin / ext;
+          const uint32_t i = lin - q * ext;
+          lin = q;
+          a += static_cast<int64_t>(i) * ss[d];
+          b += static_cast<int64_t>(i) * ds[d];
+        }
+      }
+      so[u] = a;
+      dof[u] = b;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * nthr + lt;
+      v[u] = (src && e < count) ? src[so[u]] * sign : static_cast<T>(0);
+    }
+    if (beta != 0.0) {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + u * nthr + lt;
+        if (e < count) v[u] = static_cast<T>(alpha) * v[u] + static_cast<T>(beta) * dst[dof[u]];
+      }
+    } else if (alpha != 1.0) {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = static_cast<T>(alpha) * v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * nthr + lt;
+      if (e < count) dst[dof[u]] = v[u];
+    }
+  }
+}
+
+// A workgroup holding one task spreads it over all its threads; one holding
+// several small tasks gives each wave its own tasks, so their loads are in
+// flight together instead of one task after another.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __restrict__ tasks,
                                                            const int32_t* __restrict__ wg_first,
                                                            Ptrs P, double alpha, double beta) {
   const int t0 = wg_first[blockIdx.x];
   const int t1 = wg_first[blockIdx.x + 1];
-  for (int t = t0; t < t1; ++t) {
-    const PermTask* tk = tasks + t;
-    const int n = tk->n;
-    const int count = tk->count;
-    const uint32_t start = static_cast<uint32_t>(tk->start);
-    const T sign = static_cast<T>(tk->sign);
-    int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
-#pragma unroll
-    for (int d = 0; d < kMaxDims; ++d) {
-      dim[d] = tk->dim[d];
-      ss[d] = tk->ss[d];
-      ds[d] = tk->ds[d];
-    }
-    T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-    const T* __restrict__ src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
-    for (int e0 = 0; e0 < count; e0 += kThreads * kBatch) {
-      int64_t so[kBatch], dof[kBatch];
-      T v[kBatch];
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int e = e0 + u * kThreads + threadIdx.x;
-        uint32_t lin = start + static_cast<uint32_t>(e);
-        int64_t a = 0, b = 0;
-#pragma unroll
-        for (int d = 0; d < kMaxDims; ++d) {
-          if (d < n) {
-            const uint32_t ext = static_cast<uint32_t>(dim[d]);
-            const uint32_t q = lin / ext;
-            const uint32_t i = lin - q * ext;
-            lin = q;
-            a += static_cast<int64_t>(i) * ss[d];
-            b += static_cast<int64_t>(i) * ds[d];
-          }
-        }
-        so[u] = a;
-        dof[u] = b;
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int e = e0 + u * kThreads + threadIdx.x;
-        v[u] = (src && e < count) ? src[so[u]] * sign : static_cast<T>(0);
-      }
-      if (beta != 0.0) {
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) {
-          const int e = e0 + u * kThreads + threadIdx.x;
-          if (e < count) v[u] = static_cast<T>(alpha) * v[u] + static_cast<T>(beta) * dst[dof[u]];
-        }
-      } else if (alpha != 1.0) {
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u) v[u] = static_cast<T>(alpha) * v[u];
-      }
-#pragma unroll
-      for (int u = 0; u < kBatch; ++u) {
-        const int e = e0 + u * kThreads + threadIdx.x;
-        if (e < count) dst[dof[u]] = v[u];
-      }
-    }
+  if (t1 - t0 == 1) {
+    permute_task<T>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
+    return;
   }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T>(tasks + t, P, alpha, beta, lane, 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,70 +377,78 @@ __device__ __forceinline__ double smallk_dot(const T* __restrict__ ap, const T* 
   }
 }
 
+template <typename T, int MODE>
+__device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, const Ptrs& P, double alpha,
+                                            double beta, int lt, int nthr) {
+  const int n = tk->n, count = tk->count, K = tk->K;
+  const int lda = tk->lda, ldb = tk->ldb;
+  const uint32_t start = static_cast<uint32_t>(tk->start);
+  const double scale = alpha * static_cast<double>(tk->sign);
+  int32_t dim[kMaxDims], rs[kMaxDims], cs[kMaxDims], ds[kMaxDims];
+#pragma unroll
+  for (int d = 0; d < kMaxDims; ++d) {
+    dim[d] = tk->dim[d];
+    rs[d] = tk->rs[d];
+    cs[d] = tk->cs[d];
+    ds[d] = tk->ds[d];
+  }
+  const T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
+  const T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
+  T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  constexpr int U = kBatch / 2;
+  for (int e0 = 0; e0 < count; e0 += nthr * U) {
+    int64_t r[U], c[U], o[U];
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr + lt;
+      uint32_t lin = start + static_cast<uint32_t>(min(e, count - 1));
+      int64_t rr = 0, cc = 0, oo = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < n) {
+          const uint32_t ext = static_cast<uint32_t>(dim[d]);
+          const uint32_t q = lin / ext;
+          const uint32_t i = lin - q * ext;
+          lin = q;
+          rr += static_cast<int64_t>(i) * rs[d];
+          cc += static_cast<int64_t>(i) * cs[d];
+          oo += static_cast<int64_t>(i) * ds[d];
+        }
+      }
+      r[u] = rr;
+      c[u] = cc;
+      o[u] = oo;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = smallk_dot<T, MODE>(A + r[u], B + c[u] * ldb, K, lda);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * nthr + lt;
+      if (e < count) {
+        double v = scale * acc[u];
+        if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
+        D[o[u]] = static_cast<T>(v);
+      }
+    }
+  }
+}
+
 // MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
 // each operand, three products, fp32 accumulation (the compensated mode).
-// Elements are processed kBatch at a time per thread (loads before stores).
+// Work distribution as in permute_kernel.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __restrict__ tasks,
                                                           const int32_t* __restrict__ wg_first, Ptrs P,
                                                           double alpha, double beta) {
   const int t0 = wg_first[blockIdx.x];
   const int t1 = wg_first[blockIdx.x + 1];
-  for (int t = t0; t < t1; ++t) {
-    const SmallKTask* tk = tasks + t;
-    const int n = tk->n, count = tk->count, K = tk->K;
-    const int lda = tk->lda, ldb = tk->ldb;
-    const uint32_t start = static_cast<uint32_t>(tk->start);
-    const double scale = alpha * static_cast<double>(tk->sign);
-    int32_t dim[kMaxDims], rs[kMaxDims], cs[kMaxDims], ds[kMaxDims];
-#pragma unroll
-    for (int d = 0; d < kMaxDims; ++d) {
-      dim[d] = tk->dim[d];
-      rs[d] = tk->rs[d];
-      cs[d] = tk->cs[d];
-      ds[d] = tk->ds[d];
-    }
-    const T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
-    const T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
-    T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-    constexpr int U = kBatch / 2;
-    for (int e0 = 0; e0 < count; e0 += kThreads * U) {
-      int64_t r[U], c[U], o[U];
-      double acc[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kThreads + threadIdx.x;
-        uint32_t lin = start + static_cast<uint32_t>(min(e, count - 1));
-        int64_t rr = 0, cc = 0, oo = 0;
-#pragma unroll
-        for (int d = 0; d < kMaxDims; ++d) {
-          if (d < n) {
-            const uint32_t ext = static_cast<uint32_t>(dim[d]);
-            const uint32_t q = lin / ext;
-            const uint32_t i = lin - q * ext;
-            lin = q;
-            rr += static_cast<int64_t>(i) * rs[d];
-            cc += static_cast<int64_t>(i) * cs[d];
-            oo += static_cast<int64_t>(i) * ds[d];
-          }
-        }
-        r[u] = rr;
-        c[u] = cc;
-        o[u] = oo;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) acc[u] = smallk_dot<T, MODE>(A + r[u], B + c[u] * ldb, K, lda);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = e0 + u * kThreads + threadIdx.x;
-        if (e < count) {
-          double v = scale * acc[u];
-          if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
-          D[o[u]] = static_cast<T>(v);
-        }
-      }
-    }
+  if (t1 - t0 == 1) {
+    smallk_task<T, MODE>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
+    return;
   }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) smallk_task<T, MODE>(tasks + t, P, alpha, beta, lane, 64);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,6 +73,7 @@ _SIGS = {
     "tk_plan_execute_stages": [_P, _P, _P, _P, C.c_double, C.c_double, C.c_int32, _P],
     "tk_plan_info": [_P, _I64P, C.POINTER(C.c_double), _I64P, _I64P, _I32P, _I32P, _I32P],
     "tk_plan_gemms": [_P, C.c_int64, C.c_int64, _I64P],
+    "tk_plan_counts": [_P, _I64P],
     "tk_permute_map": [_P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I64P, _I32P],
     "tk_batch_create": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, C.c_double,
                         C.c_double, C.POINTER(_P)],
@@ -377,6 +378,13 @@ class Plan:
                                 C.byref(tn), C.byref(tkk)))
         return dict(ngemm=ng.value, flops=fl.value, nzero=nz.value, workspace_bytes=ws.value,
                     tile=(tm.value, tn.value, tkk.value))
+
+    def counts(self):
+        out = np.zeros(12, np.int64)
+        _check(lib.tk_plan_counts(self.h, out.ctypes.data_as(_I64P)))
+        keys = ("pre_tasks", "pre_wgs", "zero_tasks", "zero_wgs", "smallk_tasks", "smallk_wgs", "gemm_descs",
+                "tiles", "gemm_wgs", "split_groups", "split_slots", "makespan_stages")
+        return dict(zip(keys, out.tolist()))
 
     def gemms(self):
         n = self.info()["ngemm"]
