@@ -9,7 +9,7 @@
 namespace tk {
 
 constexpr int kMaxDims = 8;   // dims of one block task after merging
-constexpr int kPermChunk = 2048;  // elements of one block task (a workgroup visit)
+constexpr int kPermChunk = 4096;  // elements of one block task (a workgroup visit)
 constexpr int kThreads = 256;
 
 // Buffer ids used by task descriptors.  A plan reads/writes at most these

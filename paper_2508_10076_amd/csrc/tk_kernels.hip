@@ -16,9 +16,14 @@
 
 namespace tk {
 
+// Device memory pointers in the global address space: pointers read from
+// the buffer table would otherwise be generic (flat) pointers, whose loads
+// count against the LDS wait counter and serialise with LDS traffic.
+#define TK_GLOBAL __attribute__((address_space(1)))
+
 template <typename T>
-__device__ __forceinline__ T* buf_ptr(const Ptrs& P, int id) {
-  return reinterpret_cast<T*>(P.table ? reinterpret_cast<void*>(P.table[id]) : P.p[id]);
+__device__ __forceinline__ TK_GLOBAL T* buf_ptr(const Ptrs& P, int id) {
+  return (TK_GLOBAL T*)(P.table ? reinterpret_cast<void*>(P.table[id]) : P.p[id]);
 }
 
 // ---------------------------------------------------------------------------
@@ -45,14 +50,17 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
     ss[d] = tk->ss[d];
     ds[d] = tk->ds[d];
   }
-  T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  const T* __restrict__ src = tk->src_buf >= 0 ? buf_ptr<const T>(P, tk->src_buf) + tk->src : nullptr;
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  const bool has_src = tk->src_buf >= 0;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, has_src ? tk->src_buf : tk->dst_buf) + tk->src;
   for (int e0 = 0; e0 < count; e0 += nthr * kBatch) {
     int64_t so[kBatch], dof[kBatch];
     T v[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
-      const int e = e0 + u * nthr + lt;
+      // out-of-range lanes repeat the last element (loads stay in bounds and
+      // unconditional; their stores are skipped)
+      const int e = min(e0 + u * nthr + lt, count - 1);
       uint32_t lin = start + static_cast<uint32_t>(e);
       int64_t a = 0, b = 0;
 #pragma unroll
@@ -69,10 +77,12 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
       so[u] = a;
       dof[u] = b;
     }
+    if (has_src) {
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int e = e0 + u * nthr + lt;
-      v[u] = (src && e < count) ? src[so[u]] * sign : static_cast<T>(0);
+      for (int u = 0; u < kBatch; ++u) v[u] = src[so[u]] * sign;
+    } else {
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) v[u] = static_cast<T>(0);
     }
     if (beta != 0.0) {
 #pragma unroll
@@ -117,7 +127,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 // Epilogue store of one accumulated element of C~ (row r, column s of the
 // sector GEMM d): in place (mode 0) or scattered into C (mode 1).
 template <typename TC>
-__device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc& d, TC* Cbase, int r,
+__device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL TC* Cbase, int r,
                                            int s, double acc) {
   if (r >= d.M || s >= d.N) return;
   int64_t idx;
@@ -208,8 +218,8 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
   for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
     const GemmTile tile = args.tiles[ti];
     const GemmDesc d = args.descs[tile.gemm];
-    const double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a;
-    const double* B = buf_ptr<const double>(args.ptrs, d.b_buf) + d.b;
+    const TK_GLOBAL double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a;
+    const TK_GLOBAL double* B = buf_ptr<const double>(args.ptrs, d.b_buf) + d.b;
 
     d4_t acc[TM][TN];
 #pragma unroll
@@ -220,7 +230,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
     double ra[A_LD], rb[B_LDK];
     const int am = tile.m0 + a_m;
     const bool a_ok = am < d.M;
-    const double* Arow = A + am;
+    const TK_GLOBAL double* Arow = A + am;
     const int kend = tile.k1;
     auto gload = [&](int k0) {
 #pragma unroll
@@ -297,7 +307,7 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
             if (tile.m0 + wm + 16 * mi + g + 4 * v < d.M && tile.n0 + wn + 16 * ni + l16 < d.N)
               mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
     } else {
-      double* C = buf_ptr<double>(args.ptrs, d.c_buf);
+      TK_GLOBAL double* C = buf_ptr<double>(args.ptrs, d.c_buf);
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -352,7 +362,8 @@ __device__ __forceinline__ float bf16_round(float x) {
 // MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
 // each operand, three products, fp32 accumulation (the compensated mode).
 template <typename T, int MODE>
-__device__ __forceinline__ double smallk_dot(const T* __restrict__ ap, const T* __restrict__ bp, int K, int lda) {
+__device__ __forceinline__ double smallk_dot(const TK_GLOBAL T* __restrict__ ap, const TK_GLOBAL T* __restrict__ bp,
+                                             int K, int lda) {
   if (MODE == 0) {
     T s = 0;
     for (int k = 0; k < K; ++k) s += ap[static_cast<int64_t>(k) * lda] * bp[k];
@@ -392,9 +403,9 @@ __device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, c
     cs[d] = tk->cs[d];
     ds[d] = tk->ds[d];
   }
-  const T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
-  const T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
-  T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
+  const TK_GLOBAL T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
+  TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
   constexpr int U = kBatch / 2;
   for (int e0 = 0; e0 < count; e0 += nthr * U) {
     int64_t r[U], c[U], o[U];
