@@ -709,7 +709,7 @@ struct tk_plan {
   double makespan = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
-  SmallKList smallk;
+  SmallKList smallk[9];  // indexed by K
   std::vector<int64_t> mnk;  // (M, N, K) of every sector GEMM with K > 0, MFMA or streamed
   DevBuf wsA, wsB, wsC;
   double flops = 0;
@@ -721,7 +721,7 @@ struct tk_batch {
   int n = 0, dtype = 0, precision = 0;
   double alpha = 1.0, beta = 0.0;
   TaskList pre, zero, postp;
-  SmallKList smallk;
+  SmallKList smallk[9];
   int32_t ngroups = 0, nslots = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
@@ -1043,7 +1043,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
               rr[n] = crs[src[n]];
               cc2[n] = ccs[src[n]];
             }
-            add_smallk_tasks(P->smallk, t, Ct.N(), dd, rr, cc2, ostr);
+            add_smallk_tasks(P->smallk[K], t, Ct.N(), dd, rr, cc2, ostr);
           }
         continue;
       }
@@ -1143,7 +1143,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     pack_workgroups(P->postp);
   }
 
-  pack_workgroups(P->smallk);
+  for (auto& l : P->smallk) pack_workgroups(l);
   int tm, tn, tkk;
   choose_default_tile(P->descs, &tm, &tn, &tkk);
   {
@@ -1165,7 +1165,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     P->d_rowmap.upload(P->row_map);
     P->d_colmap.upload(P->col_map);
     P->d_pairs.upload(P->pairs);
-    P->smallk.upload();
+    for (auto& l : P->smallk) l.upload();
     Sched sc;
     sc.tiles = P->tiles;
     sc.wg_first = P->wg_first;
@@ -1228,11 +1228,13 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                        static_cast<const GemmTile*>(P.d_groups.p), P.ngroups, stream),
               "split-K reduce launch");
   }
-  if ((stages & TK_STAGE_GEMM) && P.smallk.nwg() > 0)
-    hip_check(tk::launch_smallk(P.dtype, P.precision, static_cast<const tk::SmallKTask*>(P.smallk.d_tasks.p),
-                                static_cast<const int32_t*>(P.smallk.d_wg.p), P.smallk.nwg(), ptrs, alpha, beta,
-                                stream),
-              "small-K launch");
+  if (stages & TK_STAGE_GEMM)
+    for (int K = 1; K <= kSmallK; ++K)
+      if (P.smallk[K].nwg() > 0)
+        hip_check(tk::launch_smallk(P.dtype, P.precision, K, static_cast<const tk::SmallKTask*>(P.smallk[K].d_tasks.p),
+                                    static_cast<const int32_t*>(P.smallk[K].d_wg.p), P.smallk[K].nwg(), ptrs, alpha,
+                                    beta, stream),
+                  "small-K launch");
   if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
     hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
                                  static_cast<const int32_t*>(P.zero.d_wg.p), P.zero.nwg(), ptrs, P.post ? 1.0 : alpha,
@@ -1628,9 +1630,13 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
   return guarded([&] {
     if (!plan || !c) fail(TK_ERR_INVALID_ARG, "null argument");
     const tk_plan& P = *plan;
+    int64_t skt = 0, skw = 0;
+    for (const auto& l : P.smallk) {
+      skt += static_cast<int64_t>(l.tasks.size());
+      skw += l.nwg();
+    }
     const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
-                           static_cast<int64_t>(P.zero.tasks.size()), P.zero.nwg(),
-                           static_cast<int64_t>(P.smallk.tasks.size()), P.smallk.nwg(),
+                           static_cast<int64_t>(P.zero.tasks.size()), P.zero.nwg(), skt, skw,
                            static_cast<int64_t>(P.descs.size()), static_cast<int64_t>(P.tiles.size()),
                            static_cast<int64_t>(P.wg_first.size()) - 1, P.ngroups, P.nslots,
                            static_cast<int64_t>(P.makespan + 0.5)};
@@ -1773,11 +1779,12 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                        static_cast<const GemmTile*>(b.d_groups.p), b.ngroups, stream),
               "split-K reduce launch");
   }
-  if (b.smallk.nwg() > 0)
-    hip_check(tk::launch_smallk(b.dtype, b.precision, static_cast<const tk::SmallKTask*>(b.smallk.d_tasks.p),
-                                static_cast<const int32_t*>(b.smallk.d_wg.p), b.smallk.nwg(), ptrs, b.alpha, b.beta,
-                                stream),
-              "small-K launch");
+  for (int K = 1; K <= kSmallK; ++K)
+    if (b.smallk[K].nwg() > 0)
+      hip_check(tk::launch_smallk(b.dtype, b.precision, K, static_cast<const tk::SmallKTask*>(b.smallk[K].d_tasks.p),
+                                  static_cast<const int32_t*>(b.smallk[K].d_wg.p), b.smallk[K].nwg(), ptrs, b.alpha,
+                                  b.beta, stream),
+                "small-K launch");
   if (b.zero.nwg() > 0)
     hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
                                  static_cast<const int32_t*>(b.zero.d_wg.p), b.zero.nwg(), ptrs, b.alpha, b.beta,
@@ -1823,7 +1830,7 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       b->ws.push_back(std::move(wb));
       merge_tasks(b->pre, P.pre, i);
       merge_tasks(b->zero, P.zero, i);
-      merge_smallk(b->smallk, P.smallk, i);
+      for (int K = 1; K <= kSmallK; ++K) merge_smallk(b->smallk[K], P.smallk[K], i);
       const int32_t rb = static_cast<int32_t>(b->row_map.size()), cb = static_cast<int32_t>(b->col_map.size());
       const int32_t pb = static_cast<int32_t>(b->pairs.size());
       for (GemmDesc d : P.descs) {
@@ -1848,7 +1855,7 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     batch_schedule(*b, tm, tn, tkk);
     b->pre.upload();
     b->zero.upload();
-    b->smallk.upload();
+    for (auto& l : b->smallk) l.upload();
     b->d_descs.upload(b->descs);
     b->d_rowmap.upload(b->row_map);
     b->d_colmap.upload(b->col_map);

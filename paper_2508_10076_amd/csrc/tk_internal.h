@@ -134,8 +134,9 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
                        int nwg, hipStream_t stream);
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
-hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
-                        const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
+// Small-K sector GEMM tasks that all share the same K (1..8).
+hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
+                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k);
 int num_tile_shapes();
 void tile_shape(int i, int* tm, int* tn, int* tk);

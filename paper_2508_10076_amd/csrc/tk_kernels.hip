@@ -361,23 +361,24 @@ __device__ __forceinline__ float bf16_round(float x) {
 
 // MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
 // each operand, three products, fp32 accumulation (the compensated mode).
-template <typename T, int MODE>
-__device__ __forceinline__ double smallk_dot(const TK_GLOBAL T* __restrict__ ap, const TK_GLOBAL T* __restrict__ bp,
-                                             int K, int lda) {
+// sum_k a_k b_k over KK terms in the arithmetic of MODE (see smallk_kernel)
+template <int MODE, int KK>
+__device__ __forceinline__ double smallk_dot(const double* a, const double* b) {
   if (MODE == 0) {
-    T s = 0;
-    for (int k = 0; k < K; ++k) s += ap[static_cast<int64_t>(k) * lda] * bp[k];
-    return static_cast<double>(s);
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) s = fma(a[k], b[k], s);
+    return s;
   } else if (MODE == 1) {
     float s = 0.f;
-    for (int k = 0; k < K; ++k)
-      s = fmaf(static_cast<float>(ap[static_cast<int64_t>(k) * lda]), static_cast<float>(bp[k]), s);
+#pragma unroll
+    for (int k = 0; k < KK; ++k) s = fmaf(static_cast<float>(a[k]), static_cast<float>(b[k]), s);
     return s;
   } else {
     float s = 0.f;
-    for (int k = 0; k < K; ++k) {
-      const float x = static_cast<float>(ap[static_cast<int64_t>(k) * lda]);
-      const float y = static_cast<float>(bp[k]);
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      const float x = static_cast<float>(a[k]), y = static_cast<float>(b[k]);
       const float xh = bf16_round(x), yh = bf16_round(y);
       const float xl = bf16_round(x - xh), yl = bf16_round(y - yh);
       s = fmaf(xh, yh, s);
@@ -388,10 +389,10 @@ __device__ __forceinline__ double smallk_dot(const TK_GLOBAL T* __restrict__ ap,
   }
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int KK>
 __device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, const Ptrs& P, double alpha,
                                             double beta, int lt, int nthr) {
-  const int n = tk->n, count = tk->count, K = tk->K;
+  const int n = tk->n, count = tk->count;
   const int lda = tk->lda, ldb = tk->ldb;
   const uint32_t start = static_cast<uint32_t>(tk->start);
   const double scale = alpha * static_cast<double>(tk->sign);
@@ -406,14 +407,13 @@ __device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, c
   const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
   const TK_GLOBAL T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
   TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  constexpr int U = kBatch / 2;
+  constexpr int U = KK <= 2 ? 8 : 4;
   for (int e0 = 0; e0 < count; e0 += nthr * U) {
     int64_t r[U], c[U], o[U];
-    double acc[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * nthr + lt;
-      uint32_t lin = start + static_cast<uint32_t>(min(e, count - 1));
+      const int e = min(e0 + u * nthr + lt, count - 1);
+      uint32_t lin = start + static_cast<uint32_t>(e);
       int64_t rr = 0, cc = 0, oo = 0;
 #pragma unroll
       for (int d = 0; d < kMaxDims; ++d) {
@@ -428,38 +428,43 @@ __device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, c
         }
       }
       r[u] = rr;
-      c[u] = cc;
+      c[u] = cc * ldb;
       o[u] = oo;
     }
+    double av[U][KK], bv[U][KK];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = smallk_dot<T, MODE>(A + r[u], B + c[u] * ldb, K, lda);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        av[u][k] = static_cast<double>(A[r[u] + static_cast<int64_t>(k) * lda]);
+        bv[u][k] = static_cast<double>(B[c[u] + k]);
+      }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = e0 + u * nthr + lt;
-      if (e < count) {
-        double v = scale * acc[u];
-        if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
-        D[o[u]] = static_cast<T>(v);
-      }
+      double v = scale * smallk_dot<MODE, KK>(av[u], bv[u]);
+      if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
+      if (e < count) D[o[u]] = static_cast<T>(v);
     }
   }
 }
 
-// MODE 0: arithmetic in the storage type; 1: fp32; 2: two-term bf16 split of
-// each operand, three products, fp32 accumulation (the compensated mode).
-// Work distribution as in permute_kernel.
-template <typename T, int MODE>
+// Small-K sector GEMMs with K = KK fixed at compile time.  MODE 0: fp64
+// arithmetic (fp64 tensors); 1: fp32 (fp32 tensors, or the fp32 mode);
+// 2: two-term bf16 split of each operand, three products, fp32 accumulation
+// (the compensated mode).  Work distribution as in permute_kernel.
+template <typename T, int MODE, int KK>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __restrict__ tasks,
                                                           const int32_t* __restrict__ wg_first, Ptrs P,
                                                           double alpha, double beta) {
   const int t0 = wg_first[blockIdx.x];
   const int t1 = wg_first[blockIdx.x + 1];
   if (t1 - t0 == 1) {
-    smallk_task<T, MODE>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
+    smallk_task<T, MODE, KK>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = t0 + wave; t < t1; t += kThreads / 64) smallk_task<T, MODE>(tasks + t, P, alpha, beta, lane, 64);
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) smallk_task<T, MODE, KK>(tasks + t, P, alpha, beta, lane, 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,21 +482,33 @@ hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_fi
   return hipGetLastError();
 }
 
-hipError_t launch_smallk(int dtype, int precision, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
-                        const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
-  if (nwg <= 0) return hipSuccess;
-#define TK_SMALLK(T_, M_)                                                                            \
-  hipLaunchKernelGGL((smallk_kernel<T_, M_>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, ptrs, \
-                     alpha, beta)
-  if (dtype == 0) {
-    if (precision == 0) TK_SMALLK(double, 0);
-    else if (precision == 1) TK_SMALLK(double, 1);
-    else TK_SMALLK(double, 2);
-  } else {
-    if (precision == 2) TK_SMALLK(float, 2);
-    else TK_SMALLK(float, 1);
+template <typename T, int MODE>
+static void launch_smallk_k(int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg, const Ptrs& ptrs,
+                            double alpha, double beta, hipStream_t stream) {
+  switch (K) {
+#define TK_SK(KK_)                                                                                            \
+  case KK_:                                                                                                   \
+    hipLaunchKernelGGL((smallk_kernel<T, MODE, KK_>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, \
+                       ptrs, alpha, beta);                                                                    \
+    break;
+    TK_SK(1) TK_SK(2) TK_SK(3) TK_SK(4) TK_SK(5) TK_SK(6) TK_SK(7) TK_SK(8)
+#undef TK_SK
+    default: break;
   }
-#undef TK_SMALLK
+}
+
+hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
+                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (K < 1 || K > 8) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    if (precision == 0) launch_smallk_k<double, 0>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+    else if (precision == 1) launch_smallk_k<double, 1>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+    else launch_smallk_k<double, 2>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+  } else {
+    if (precision == 2) launch_smallk_k<float, 2>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+    else launch_smallk_k<float, 1>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+  }
   return hipGetLastError();
 }
 
