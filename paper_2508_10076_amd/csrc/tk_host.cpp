@@ -886,7 +886,7 @@ void plan_reschedule(tk_plan& P, int tm, int tn, int tk) {
   if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
 }
 
-void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn, int* tk) {
+void choose_default_tile(const std::vector<GemmDesc>& descs, int precision, int* tm, int* tn, int* tk) {
   int64_t mmax = 0, nmax = 0, kmax = 0;
   for (const auto& d : descs) {
     mmax = std::max<int64_t>(mmax, d.M);
@@ -895,7 +895,7 @@ void choose_default_tile(const std::vector<GemmDesc>& descs, int* tm, int* tn, i
   }
   *tm = mmax > 64 ? 128 : 64;
   *tn = nmax > 64 ? 128 : 64;
-  *tk = kmax >= 256 ? 32 : 16;
+  *tk = (kmax >= 256 || precision == TK_PREC_BF16X3) ? 32 : 16;
 }
 
 std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A, std::vector<int> pA,
@@ -911,8 +911,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
   if (qA.size() != pB.size()) fail(TK_ERR_INVALID_ARG, "qA and pB differ in length");
   check_perm(pAB, qAB, static_cast<int>(pA.size() + qB.size()));
   if (precision < TK_PREC_NATIVE || precision > TK_PREC_BF16X3) fail(TK_ERR_INVALID_ARG, "unknown precision");
-  if (!tk::gemm_tile_supported(A->dtype, precision, 128, 128, 16) &&
-      !tk::gemm_tile_supported(A->dtype, precision, 64, 64, 16))
+  if (!tk::gemm_tile_supported(A->dtype, precision, 128, 128, 32))
     fail(TK_ERR_DTYPE, "this dtype / precision combination is not available");
 
   auto P = std::make_unique<tk_plan>();
@@ -1145,7 +1144,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
 
   for (auto& l : P->smallk) pack_workgroups(l);
   int tm, tn, tkk;
-  choose_default_tile(P->descs, &tm, &tn, &tkk);
+  choose_default_tile(P->descs, precision, &tm, &tn, &tkk);
   {
     tk_context* keep = P->ctx;
     P->ctx = nullptr;  // schedule only; uploads follow below
@@ -1851,7 +1850,7 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     }
     if (b->descs.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many GEMMs");
     int tm, tn, tkk;
-    choose_default_tile(b->descs, &tm, &tn, &tkk);
+    choose_default_tile(b->descs, b->precision, &tm, &tn, &tkk);
     batch_schedule(*b, tm, tn, tkk);
     b->pre.upload();
     b->zero.upload();

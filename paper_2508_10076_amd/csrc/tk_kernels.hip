@@ -177,6 +177,39 @@ struct F64Tile {
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
 };
 
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// Epilogue of a tile accumulated in fp32 (fp32 16x16 MFMA layout: value v
+// of lane l is row 4*(l/16) + v).  Split tiles store their partial sums
+// (fp64, lane-major) for the reduce kernel; others go straight to C.
+template <class TT, typename TS>
+__device__ __forceinline__ void gemm_epilogue_f32(const GemmArgs& args, const GemmDesc& d, const GemmTile& tile,
+                                                  const f4_t (&acc)[TT::TM][TT::TN], int tid, int wm, int wn, int g,
+                                                  int l16) {
+  constexpr int TM = TT::TM, TN = TT::TN, NT = TT::NT;
+  if (tile.nsplit > 1) {
+    double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (TT::WM * TT::WGM * TT::WN * TT::WGN);
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (tile.m0 + wm + 16 * mi + 4 * g + v < d.M && tile.n0 + wn + 16 * ni + l16 < d.N)
+            mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
+  } else {
+    TK_GLOBAL TS* C = buf_ptr<TS>(args.ptrs, d.c_buf);
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          store_elem<TS>(args, d, C, tile.m0 + wm + 16 * mi + 4 * g + v, tile.n0 + wn + 16 * ni + l16,
+                         acc[mi][ni][v]);
+  }
+}
+
 // Origin of wave w's sub-tile.  Waves w and w + NW/2 share a SIMD (waves of
 // a workgroup are spread round robin over the 4 SIMDs of a CU); the first
 // half of the waves covers the top row band, the second half the bottom row
@@ -326,7 +359,8 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 // then the same epilogue as an unsplit tile.  A flat stream over (group,
 // element) pairs: element e of a partial tile is the accumulator value the
 // GEMM thread e % NT held as its value number e / NT.
-template <int BM, int BN, int WGM, int WGN>
+// LAYOUT 0: fp64 MFMA rows (lane/16 + 4v); 1: fp32 / bf16 MFMA rows (4*(lane/16) + v).
+template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
   constexpr int NT = TT::NT, TN = TT::TN;
@@ -342,13 +376,261 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const GemmDesc d = args.descs[tile.gemm];
     int wm, wn;
     wave_origin<TT>(wave, &wm, &wn);
-    const int r = tile.m0 + wm + 16 * mi + (lane >> 4) + 4 * v;
+    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
     const int c = tile.n0 + wn + 16 * ni + (lane & 15);
     if (r >= d.M || c >= d.N) continue;
     double sum = 0.0;
     const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
     for (int j = 0; j < tile.nsplit; ++j) sum += p[static_cast<int64_t>(j) * (BM * BN)];
-    store_elem<double>(args, d, buf_ptr<double>(args.ptrs, d.c_buf), r, c, sum);
+    store_elem<TS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), r, c, sum);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// grouped sector GEMM in reduced precision
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+// fp32 MFMA 16x16x4: operands rounded to fp32 as they enter LDS (A as [k][m],
+// B as [n][k], as in the fp64 kernel), fp32 accumulation.  Output layout of
+// the fp32 16x16 MFMA: value v of lane l is row 4*(l/16) + v, column l%16.
+template <typename TS, int BM, int BN, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f32_kernel(GemmArgs args) {
+  using TT = F64Tile<BM, BN, WGM, WGN, BK>;
+  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
+  constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD;
+  __shared__ float As[2][BK][BM + 4];
+  __shared__ float Bs[2][BN][BK + 4];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  int wm, wn;
+  wave_origin<TT>(wave, &wm, &wn);
+  const int a_m = tid % BM, a_k = tid / BM;
+  const int b_k = tid % BK, b_n = tid / BK;
+  constexpr int B_NPL = NT / BK;
+  constexpr int B_LDK = BN / B_NPL;
+
+  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
+    const GemmTile tile = args.tiles[ti];
+    const GemmDesc d = args.descs[tile.gemm];
+    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a;
+    const TK_GLOBAL TS* B = buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b;
+    f4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    float ra[A_LD], rb[B_LDK];
+    const int am = tile.m0 + a_m;
+    const bool a_ok = am < d.M;
+    const TK_GLOBAL TS* Arow = A + am;
+    const int kend = tile.k1;
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) {
+        const int k = k0 + a_k + A_TPM * i;
+        ra[i] = (a_ok && k < kend) ? static_cast<float>(Arow[static_cast<int64_t>(k) * d.lda]) : 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < B_LDK; ++i) {
+        const int n = tile.n0 + b_n + B_NPL * i;
+        const int k = k0 + b_k;
+        rb[i] = (n < d.N && k < kend) ? static_cast<float>(B[static_cast<int64_t>(n) * d.ldb + k]) : 0.f;
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
+#pragma unroll
+      for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[i];
+    };
+    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
+    auto compute = [&](int cur) {
+      if (!active) return;
+#pragma unroll
+      for (int j = 0; j < BK / 4; ++j) {
+        float af[TM], bf[TN];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][(BK / 4) * g + j];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < TN; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+      }
+    };
+    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
+    gload(tile.k0);
+    lstore(0);
+    if (nst > 1) gload(tile.k0 + BK);
+    int st = 0;
+    for (; st + 2 < nst; ++st) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      gload(tile.k0 + (st + 2) * BK);
+      compute(st & 1);
+    }
+    if (st + 1 < nst) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      compute(st & 1);
+      ++st;
+    }
+    __syncthreads();
+    compute(st & 1);
+    gemm_epilogue_f32<TT, TS>(args, d, tile, acc, tid, wm, wn, g, l16);
+    __syncthreads();
+  }
+}
+
+// Compensated split-BF16x3: every operand value a (rounded to fp32) is split
+// into hi = bf16(a) and lo = bf16(a - hi) as it enters LDS; each 16x16x32
+// block of the product is hi*hi + hi*lo + lo*hi on the bf16 MFMA with fp32
+// accumulation (the lo*lo term is dropped).  LDS holds A as [m][k] and B as
+// [n][k] (k contiguous) so a lane fetches its 8 consecutive k values of an
+// MFMA operand with one 16-byte read; lane group g = l/16 owns k = 8g..8g+7.
+template <typename TS, int BM, int BN, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_bf16x3_kernel(GemmArgs args) {
+  using TT = F64Tile<BM, BN, WGM, WGN, BK>;
+  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
+  constexpr int KP = BK + 8;  // padded row of bf16 values
+  constexpr int A_ITEMS = BM * BK / 8, B_ITEMS = BN * BK / 8;  // 8-value groups per stage
+  constexpr int A_PT = (A_ITEMS + NT - 1) / NT, B_PT = (B_ITEMS + NT - 1) / NT;
+  static_assert(BK % 32 == 0, "bf16 stage depth");
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  int wm, wn;
+  wave_origin<TT>(wave, &wm, &wn);
+
+  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
+    const GemmTile tile = args.tiles[ti];
+    const GemmDesc d = args.descs[tile.gemm];
+    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a;
+    const TK_GLOBAL TS* B = buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b;
+    f4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+    const int kend = tile.k1;
+    float ra[A_PT][8], rb[B_PT][8];
+    // A item x: m = x % BM, k group = x / BM (consecutive threads, consecutive m)
+    // B item x: k group = x % (BK/8), n = x / (BK/8) (a column's k groups adjacent)
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int p = 0; p < A_PT; ++p) {
+        const int x = tid + p * NT;
+        const int m = x % BM, kg = x / BM;
+        const int gm = tile.m0 + m;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 8 * kg + q;
+          ra[p][q] = (x < A_ITEMS && gm < d.M && k < kend) ? static_cast<float>(A[static_cast<int64_t>(k) * d.lda + gm])
+                                                           : 0.f;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < B_PT; ++p) {
+        const int x = tid + p * NT;
+        const int kg = x % (BK / 8), n = x / (BK / 8);
+        const int gn = tile.n0 + n;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + 8 * kg + q;
+          rb[p][q] = (x < B_ITEMS && gn < d.N && k < kend) ? static_cast<float>(B[static_cast<int64_t>(gn) * d.ldb + k])
+                                                           : 0.f;
+        }
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int p = 0; p < A_PT; ++p) {
+        const int x = tid + p * NT;
+        if (x < A_ITEMS) {
+          const int m = x % BM, kg = x / BM;
+          bf8_t h, l;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            h[q] = static_cast<__bf16>(ra[p][q]);
+            l[q] = static_cast<__bf16>(ra[p][q] - static_cast<float>(h[q]));
+          }
+          *reinterpret_cast<bf8_t*>(&Ah[buf][m][8 * kg]) = h;
+          *reinterpret_cast<bf8_t*>(&Al[buf][m][8 * kg]) = l;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < B_PT; ++p) {
+        const int x = tid + p * NT;
+        if (x < B_ITEMS) {
+          const int kg = x % (BK / 8), n = x / (BK / 8);
+          bf8_t h, l;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            h[q] = static_cast<__bf16>(rb[p][q]);
+            l[q] = static_cast<__bf16>(rb[p][q] - static_cast<float>(h[q]));
+          }
+          *reinterpret_cast<bf8_t*>(&Bh[buf][n][8 * kg]) = h;
+          *reinterpret_cast<bf8_t*>(&Bl[buf][n][8 * kg]) = l;
+        }
+      }
+    };
+    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
+    auto compute = [&](int cur) {
+      if (!active) return;
+#pragma unroll
+      for (int kb = 0; kb < BK / 32; ++kb) {
+        bf8_t ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) {
+          ah[mi] = *reinterpret_cast<const bf8_t*>(&Ah[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
+          al[mi] = *reinterpret_cast<const bf8_t*>(&Al[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
+        }
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni) {
+          bh[ni] = *reinterpret_cast<const bf8_t*>(&Bh[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
+          bl[ni] = *reinterpret_cast<const bf8_t*>(&Bl[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
+        }
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < TN; ++ni) {
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+          }
+      }
+    };
+    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
+    gload(tile.k0);
+    lstore(0);
+    if (nst > 1) gload(tile.k0 + BK);
+    int st = 0;
+    for (; st + 2 < nst; ++st) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      gload(tile.k0 + (st + 2) * BK);
+      compute(st & 1);
+    }
+    if (st + 1 < nst) {
+      __syncthreads();
+      lstore((st + 1) & 1);
+      compute(st & 1);
+      ++st;
+    }
+    __syncthreads();
+    compute(st & 1);
+    gemm_epilogue_f32<TT, TS>(args, d, tile, acc, tid, wm, wn, g, l16);
+    __syncthreads();
   }
 }
 
@@ -512,9 +794,9 @@ hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* task
   return hipGetLastError();
 }
 
-// Tile configurations of the fp64 grouped GEMM: (tile_m, tile_n, stage
-// depth) and the wave grid that covers the tile.
-#define TK_F64_SHAPES(X)                                                                              \
+// Tile configurations of the grouped GEMM: (tile_m, tile_n, stage depth) and
+// the wave grid that covers the tile.  The bf16 kernel needs a depth of 32.
+#define TK_GEMM_SHAPES(X)                                                                             \
   X(128, 128, 16, 2, 4) X(128, 128, 32, 2, 4) X(128, 64, 16, 2, 2) X(128, 64, 32, 2, 2)              \
   X(64, 128, 16, 2, 4) X(64, 128, 32, 2, 4) X(64, 64, 16, 2, 2) X(64, 64, 32, 2, 2)
 
@@ -523,7 +805,7 @@ struct TileShape {
 };
 static const TileShape kTiles[] = {
 #define TK_SHAPE_ENTRY(BM_, BN_, BK_, WM_, WN_) {BM_, BN_, BK_},
-    TK_F64_SHAPES(TK_SHAPE_ENTRY)
+    TK_GEMM_SHAPES(TK_SHAPE_ENTRY)
 #undef TK_SHAPE_ENTRY
 };
 
@@ -534,24 +816,48 @@ void tile_shape(int i, int* tm, int* tn, int* tk) {
   *tk = kTiles[i].k;
 }
 
+// compute kind: 0 fp64 MFMA, 1 fp32 MFMA, 2 split-bf16x3
+static int compute_kind(int dtype, int precision) {
+  if (precision == 2) return 2;
+  if (dtype == 1 || precision == 1) return 1;
+  return 0;
+}
+
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k) {
-  if (dtype != 0 || precision != 0) return false;
+  if (dtype < 0 || dtype > 1 || precision < 0 || precision > 2) return false;
+  if (compute_kind(dtype, precision) == 2 && tile_k % 32 != 0) return false;
   for (const auto& t : kTiles)
     if (t.m == tile_m && t.n == tile_n && t.k == tile_k) return true;
   return false;
+}
+
+template <typename TS, int BM, int BN, int WM, int WN, int BK>
+static void launch_gemm_kind(int kind, const GemmArgs& args, int nwg, hipStream_t stream) {
+  const dim3 grid(nwg), block(64 * WM * WN);
+  if (kind == 0) {
+    if constexpr (sizeof(TS) == 8) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+  } else if (kind == 1) {
+    hipLaunchKernelGGL((gemm_f32_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+  } else {
+    if constexpr (BK % 32 == 0)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+  }
 }
 
 hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args, int nwg,
                        hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
   if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
-#define TK_GEMM_CASE(BM_, BN_, BK_, WM_, WN_)                                                              \
-  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                   \
-    hipLaunchKernelGGL((gemm_f64_kernel<BM_, BN_, WM_, WN_, BK_>), dim3(nwg), dim3(64 * WM_ * WN_), 0, stream, \
-                       args);                                                                              \
-    return hipGetLastError();                                                                              \
+  const int kind = compute_kind(dtype, precision);
+#define TK_GEMM_CASE(BM_, BN_, BK_, WM_, WN_)                                           \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                \
+    if (dtype == 0)                                                                     \
+      launch_gemm_kind<double, BM_, BN_, WM_, WN_, BK_>(kind, args, nwg, stream);       \
+    else                                                                                \
+      launch_gemm_kind<float, BM_, BN_, WM_, WN_, BK_>(kind, args, nwg, stream);        \
+    return hipGetLastError();                                                           \
   }
-  TK_F64_SHAPES(TK_GEMM_CASE)
+  TK_GEMM_SHAPES(TK_GEMM_CASE)
 #undef TK_GEMM_CASE
   return hipErrorInvalidValue;
 }
@@ -562,13 +868,21 @@ hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n
   if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>(ngroups) * tile_m * tile_n;
   const unsigned nblk = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 65536));
-#define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                                   \
-  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                       \
-    hipLaunchKernelGGL((splitk_reduce_kernel<BM_, BN_, WM_, WN_>), dim3(nblk), dim3(256), 0, stream, args, groups, \
-                       total);                                                                                 \
-    return hipGetLastError();                                                                                  \
+  const bool f64rows = compute_kind(dtype, precision) == 0;
+#define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                                        \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                            \
+    if (dtype == 0 && f64rows)                                                                                      \
+      hipLaunchKernelGGL((splitk_reduce_kernel<double, BM_, BN_, WM_, WN_, 0>), dim3(nblk), dim3(256), 0, stream, \
+                         args, groups, total);                                                                      \
+    else if (dtype == 0)                                                                                            \
+      hipLaunchKernelGGL((splitk_reduce_kernel<double, BM_, BN_, WM_, WN_, 1>), dim3(nblk), dim3(256), 0, stream, \
+                         args, groups, total);                                                                      \
+    else                                                                                                            \
+      hipLaunchKernelGGL((splitk_reduce_kernel<float, BM_, BN_, WM_, WN_, 1>), dim3(nblk), dim3(256), 0, stream,  \
+                         args, groups, total);                                                                      \
+    return hipGetLastError();                                                                                       \
   }
-  TK_F64_SHAPES(TK_RED_CASE)
+  TK_GEMM_SHAPES(TK_RED_CASE)
 #undef TK_RED_CASE
   return hipErrorInvalidValue;
 }

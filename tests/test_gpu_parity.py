@@ -298,3 +298,60 @@ def test_split_k_tall_k_exact_and_repeatable(ctx):
             fill(Cg)
             tk.tensor_contract(ctx, A, [0], [1], B, [0], [1], pAB, qAB, C_=Cg)
             assert np.array_equal(download(Cg), want), (pAB, rep)
+
+
+# ---------------------------------------------------------------------------
+# precision variants
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["f32", "bf16x3"])
+def test_precision_modes_exact_on_integers(ctx, precision):
+    """Integers in [-3, 3] are exact in fp32 and in bf16 (hi = x, lo = 0), and
+    every partial sum stays below 2^24, so both modes must be bit-exact."""
+    rng = np.random.default_rng(3000 + len(precision))
+    for trial in range(8):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _contract_case(rng, "U1xFZ2" if trial % 2 else "U1")
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        fill(Cg)
+        tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, precision=precision, C_=Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB)
+        assert np.array_equal(download(Cg), ref), (precision, trial)
+    # MFMA-sized sectors too (the random cases are small)
+    cfg = synth.heff_config(160, 4, 1.6, 91)
+    data = heff_data(cfg, 91, ints=True, rng=rng)
+    T = run_heff_gpu(ctx, cfg, data, precision=precision)
+    _, v = run_heff_oracle(cfg, data)
+    assert np.array_equal(download(T["T1"]), v["T1"])
+
+
+def test_fp32_storage_exact_on_integers(ctx):
+    rng = np.random.default_rng(3100)
+    for trial in range(6):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _contract_case(rng, "U1")
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a, dtype="f32"), make(ctx, tB, b, dtype="f32")
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        fill(Cg)
+        tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, C_=Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB)
+        assert np.array_equal(download(Cg), ref), trial
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", 2e-5), ("bf16x3", 2e-4)])
+def test_heff_precision_error_bound(ctx, precision, tol):
+    """Gaussian D = 1024 H_eff apply.  Bounds from the arithmetic: fp32 keeps
+    24 bits (products exact to 2^-24, sums of K <= 700 terms add ~sqrt(K)
+    2^-24); bf16x3 keeps 16 bits of each operand (hi + lo) and drops lo*lo,
+    ~2^-15 per product.  The measured error is printed for the record."""
+    cfg = synth.config2()
+    data = heff_data(cfg, 2)
+    T = run_heff_gpu(ctx, cfg, data, precision=precision)
+    _, v = run_heff_oracle(cfg, data)
+    got = download(T["y"])
+    err = np.linalg.norm(got - v["y"]) / np.linalg.norm(v["y"])
+    print(f"{precision}: normwise error of y {err:.3e}")
+    assert err <= tol
+    assert err > 1e-12      # the reduced precision really was used
