@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the symmetric-contraction hot path on one MI355X.
 
-Default workload: one single-site effective-Hamiltonian application
-y = L . W . x . R (three U(1) pairwise contractions, Alg. "Single-site
-Benchmark") at virtual bond dimension D = 4096 over charges -12..12, fp64.
-A step is the whole application: for each of the three contractions the
-operand permutes, the grouped sector GEMM with its fused output scatter and
-the zero blocks.  Inputs are resident in HBM before the timed region.
+Default workload (heff_d4096): one single-site effective-Hamiltonian
+application y = L . W . x . R (three U(1) pairwise contractions, Alg.
+"Single-site Benchmark") at virtual bond dimension D = 4096 over charges
+-12..12, fp64.  A step is the whole application: for each contraction the
+operand permutes, the grouped sector GEMM with its fused output scatter, the
+small-K stream and the zero blocks.  Inputs are resident in HBM before the
+timed region.  The same workload is then run with the fp32 and split-BF16x3
+GEMM modes and their errors against the fp64 CPU oracle are reported.
 
-Prints ONE JSON line.  value = useful block flops (sum over coupled charges of
-2 M N K) per second, whole job.  roofline = the grouped sector-GEMM kernel of
-the two MFMA-bound contractions, timed with HIP events on its own stream
-inside the timed region.  cpu_baseline = the CPU oracle (numpy blockwise,
-fp64) timed on a bounded sample of the same workload.
+Other workloads (--workload): heff_d1024; batch64 (64 independent
+rank-3 x rank-4 contractions, one persistent grouped launch replayed from a
+HIP graph, fp64 and fp32); peps (fermionic U(1) x fZ2 double layer
+E = A^dagger o A interleaved to rank 8, D = 16).
+
+Prints ONE JSON line.  value = useful block flops (sum over coupled charges
+of 2 M N K) per second, whole job.  roofline = the dominant kernel, timed
+with HIP events on its own stream inside the timed region.  cpu_baseline =
+the CPU oracle (numpy blockwise, fp64) timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -28,6 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK = 8000.0                                     # GB/s
 METRIC = "symmetric contract TFLOP/s (block flops) + % MFMA peak; max rel err vs FP64"
+PEAK_KEY = {"native": "f64", "f32": "f32", "bf16x3": "bf16"}
 
 
 def parse():
@@ -35,8 +42,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024"])
+    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024", "batch64", "peps"])
     ap.add_argument("--precision", default="native", choices=["native", "f32", "bf16x3"])
+    ap.add_argument("--no-variants", action="store_true", help="skip the fp32 / bf16x3 side runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile configuration")
@@ -44,11 +52,306 @@ def parse():
     return ap.parse_args()
 
 
-def heff_workload(name):
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    except Exception:
+        return os.cpu_count()
+
+
+def ostruct(t):
+    from oracle.graded import Space, Structure
+    osp = lambda s: Space(s.sectors, s.degs, s.dual)
+    return Structure(t["sym"], [osp(s) for s in t["cod"]], [osp(s) for s in t["dom"]])
+
+
+# ---------------------------------------------------------------------------
+# H_eff application
+# ---------------------------------------------------------------------------
+class Heff:
+    def __init__(self, tk, torch, cfg, cid, ctx, stream, precision):
+        from paper_2508_10076_amd import synth
+        self.tk, self.torch, self.cfg, self.stream = tk, torch, cfg, stream
+        self.T = {}
+        for i, k in enumerate(cfg["inputs"]):
+            t = cfg["tensors"][k]
+            self.T[k] = tk.tensor_create(ctx, t["sym"], t["cod"], t["dom"])
+            self.T[k].storage[: self.T[k].nelem].copy_(torch.from_numpy(synth.normal(self.T[k].nelem, cid, i)))
+        self.plans = []
+        self.flops = 0.0
+        for out, a, b, call in cfg["calls"]:
+            T = self.T
+            T[out] = tk.tensor_create_contracted(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"],
+                                                 call["pAB"], call["qAB"])
+            P = tk.Plan(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"], call["pAB"], call["qAB"],
+                        T[out], precision=precision)
+            info = P.info()
+            self.flops += info["flops"]
+            self.plans.append((P, T[a], T[b], T[out], info))
+        # the MFMA-bound contractions: GEMMs with K well above the small-K limit
+        self.mfma = [i for i, (P, *_r) in enumerate(self.plans) if P.gemms()[:, 2].max() > 64]
+        self.gemm_flops = sum(self.plans[i][4]["flops"] for i in self.mfma)
+        torch.cuda.synchronize()
+
+    def tune(self, precision, cache):
+        from paper_2508_10076_amd import autotune
+        tk, s = self.tk, self.stream
+        out = {}
+        for i in self.mfma:
+            P, A, B, Cc, _ = self.plans[i]
+            best, times = autotune.tune(P, lambda P=P, A=A, B=B, Cc=Cc: P.execute_stages(A, B, Cc, tk.STAGE_GEMM,
+                                                                                           stream=s),
+                                        P.gemms().tolist(), s, cache_path=cache, force=cache is None,
+                                        tag=("f64", precision))
+            out[f"step{i + 1}"] = {"tile": list(best),
+                                   "ms": {"x".join(map(str, c)): round(t, 4) for c, t in times.items()}}
+        return out
+
+    def step(self, ev=None):
+        tk, s = self.tk, self.stream
+        for i, (P, A, B, Cc, _) in enumerate(self.plans):
+            if ev is not None and i in self.mfma:
+                P.execute_stages(A, B, Cc, tk.STAGE_PERMUTE, stream=s)
+                ev.append(self.torch.cuda.Event(enable_timing=True))
+                ev[-1].record(s)
+                P.execute_stages(A, B, Cc, tk.STAGE_GEMM, stream=s)
+                ev.append(self.torch.cuda.Event(enable_timing=True))
+                ev[-1].record(s)
+                P.execute_stages(A, B, Cc, tk.STAGE_ZERO, stream=s)
+            else:
+                P.execute(A, B, Cc, stream=s)
+
+    def run(self, steps, warmup):
+        torch, s = self.torch, self.stream
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        evs = []
+        t0.record(s)
+        for _ in range(steps):
+            self.step(evs)
+        t1.record(s)
+        torch.cuda.synchronize()
+        total_ms = t0.elapsed_time(t1)
+        gemm_ms = sum(evs[2 * j].elapsed_time(evs[2 * j + 1]) for j in range(len(evs) // 2))
+        gemm_avg_s = gemm_ms / 1e3 / (len(evs) // 2)
+        return dict(total_ms=total_ms, ms_per_step=total_ms / steps,
+                    value=self.flops * steps / (total_ms / 1e3) / 1e12,
+                    gemm_avg_us=gemm_avg_s * 1e6,
+                    gemm_tflops=self.gemm_flops / len(self.mfma) / gemm_avg_s / 1e12)
+
+    def output(self):
+        y = self.T[self.cfg["output"]]
+        return y.storage[: y.nelem].double().cpu().numpy()
+
+
+def oracle_heff(cfg, cid, seconds):
+    """The CPU oracle on the same inputs: (y, reps, seconds spent)."""
+    from oracle import blockwise
     from paper_2508_10076_amd import synth
-    if name == "heff_d4096":
-        return synth.config3(), 3
-    return synth.config2(), 2
+    st = {k: ostruct(cfg["tensors"][k]) for k in cfg["inputs"]}
+    v0 = {k: synth.normal(st[k].size, cid, i) for i, k in enumerate(cfg["inputs"])}
+    reps, spent, y = 0, 0.0, None
+    while (spent < seconds or reps == 0) and reps < 50:
+        s2, v = dict(st), dict(v0)
+        c0 = time.perf_counter()
+        for out_, a, b, call in cfg["calls"]:
+            s2[out_], v[out_] = blockwise.contract_storage(s2[a], v[a], call["pA"], call["qA"], s2[b], v[b],
+                                                           call["pB"], call["qB"], call["pAB"], call["qAB"])
+        spent += time.perf_counter() - c0
+        reps += 1
+        y = v[cfg["output"]]
+    return y, reps, spent
+
+
+def bench_heff(args, tk, torch, np):
+    from paper_2508_10076_amd import synth
+    cfg, cid = (synth.config3(), 3) if args.workload == "heff_d4096" else (synth.config2(), 2)
+    ctx = tk.Context(0)
+    stream = torch.cuda.Stream()
+    H = Heff(tk, torch, cfg, cid, ctx, stream, args.precision)
+    tuning = {} if args.no_tune else H.tune(args.precision, args.tune_cache)
+    torch.cuda.synchronize()
+    r = H.run(args.steps, args.warmup)
+    pk = PEAK_KEY[args.precision]
+    D = 4096 if args.workload == "heff_d4096" else 1024
+    out = {
+        "metric": METRIC, "value": round(r["value"], 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "native" else args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{cfg['name']}: single-site H_eff apply y=L.W.x.R, U(1), D={D}, "
+                               f"charges -{12 if D == 4096 else 8}..{12 if D == 4096 else 8}",
+                   "precision": args.precision, "block_flops_per_step": H.flops, "parallelism": "1 GPU"},
+        "pct_fp64_mfma_peak": round(100.0 * r["value"] / PEAK["f64"], 2),
+        "roofline": {"bound": "mfma", "achieved": round(r["gemm_tflops"], 4), "peak": PEAK[pk], "unit": "TFLOP/s",
+                     "frac": round(r["gemm_tflops"] / PEAK[pk], 4), "traffic": None,
+                     "kernel": "grouped sector GEMM of the two MFMA-bound contractions (incl. split-K reduce)",
+                     "avg_launch_us": round(r["gemm_avg_us"], 2)},
+        "tiles": {f"step{i + 1}": list(H.plans[i][0].info()["tile"]) for i in H.mfma},
+        "tuning": tuning,
+    }
+    y_gpu = H.output()
+    variants = {}
+    if not args.no_variants and args.precision == "native":
+        for prec in ("f32", "bf16x3"):
+            Hv = Heff(tk, torch, cfg, cid, ctx, stream, prec)
+            if not args.no_tune:
+                Hv.tune(prec, args.tune_cache)
+            rv = Hv.run(args.steps, args.warmup)
+            variants[prec] = {"value": round(rv["value"], 4), "ms_per_step": round(rv["ms_per_step"], 5),
+                              "gemm_tflops": round(rv["gemm_tflops"], 3),
+                              "speedup_vs_fp64": round(r["ms_per_step"] / rv["ms_per_step"], 3),
+                              "y": Hv.output()}
+            del Hv
+    if not args.no_cpu_baseline:
+        y_ref, reps, spent = oracle_heff(cfg, cid, args.cpu_seconds)
+        nrm = np.linalg.norm(y_ref)
+        out["cpu_baseline"] = {"value": round(H.flops * reps / spent / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": f"{reps} full H_eff applications of the same workload (numpy blockwise "
+                                         f"fp64, OpenBLAS), {spent:.1f} s"}
+        out["max_rel_err"] = float(np.linalg.norm(y_gpu - y_ref) / nrm)
+        out["max_entry_err_rel_to_max"] = float(np.max(np.abs(y_gpu - y_ref)) / np.max(np.abs(y_ref)))
+        for prec, v in variants.items():
+            v["max_rel_err"] = float(np.linalg.norm(v.pop("y") - y_ref) / nrm)
+    for v in variants.values():
+        v.pop("y", None)
+    if variants:
+        out["precision_variants"] = variants
+    return out
+
+
+# ---------------------------------------------------------------------------
+# batch of 64 contractions, one grouped launch replayed from a graph
+# ---------------------------------------------------------------------------
+def bench_batch(args, tk, torch, np):
+    from paper_2508_10076_amd import autotune, synth
+    cfg = synth.config4()
+    call = cfg["call"]
+    ctx = tk.Context(0)
+    stream = torch.cuda.Stream()
+    res = {}
+    for dtype in ("f64", "f32"):
+        plans, As, Bs, Cs, flops = [], [], [], [], 0.0
+        for i, it in enumerate(cfg["items"]):
+            A = tk.tensor_create(ctx, "U1", it["A"]["cod"], it["A"]["dom"], dtype=dtype)
+            B = tk.tensor_create(ctx, "U1", it["B"]["cod"], it["B"]["dom"], dtype=dtype)
+            A.storage.copy_(torch.from_numpy(synth.normal(A.storage.numel(), 4, 2 * i)))
+            B.storage.copy_(torch.from_numpy(synth.normal(B.storage.numel(), 4, 2 * i + 1)))
+            C = tk.tensor_create_contracted(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"],
+                                            call["qAB"])
+            P = tk.Plan(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"], call["qAB"], C)
+            flops += P.info()["flops"]
+            plans.append(P)
+            As.append(A)
+            Bs.append(B)
+            Cs.append(C)
+        batch = tk.Batch(ctx, plans, As, Bs, Cs)
+        mnk = [g for P in plans for g in P.gemms().tolist()]
+        best = None
+        if not args.no_tune:
+            best, _ = autotune.tune(batch, lambda: batch.launch(stream), mnk, stream, cache_path=args.tune_cache,
+                                    force=args.tune_cache is None, tag=(dtype, "native"))
+        batch.capture(stream)
+
+        def timed(fn, reps):
+            with torch.cuda.stream(stream):
+                for _ in range(args.warmup):
+                    fn()
+            stream.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_graph = timed(lambda: batch.replay(stream), args.steps)
+        ms_seq = timed(lambda: [P.execute(A, B, C, stream=stream) for P, A, B, C in zip(plans, As, Bs, Cs)],
+                       max(3, args.steps // 4))
+        info = batch.info()
+        res[dtype] = {"value": round(flops / ms_graph / 1e9, 4), "ms_per_step": round(ms_graph, 5),
+                      "sequential_ms": round(ms_seq, 4), "speedup_vs_sequential": round(ms_seq / ms_graph, 3),
+                      "ngemm": info["ngemm"], "ntiles": info["ntiles"], "tile": list(info["tile"]),
+                      "block_flops": flops}
+        if dtype == "f64":
+            # parity spot check of one member against the oracle
+            from oracle import blockwise
+            it = cfg["items"][0]
+            stA, stB = ostruct(it["A"]), ostruct(it["B"])
+            a = As[0].storage[: stA.size].double().cpu().numpy()
+            b = Bs[0].storage[: stB.size].double().cpu().numpy()
+            _, ref = blockwise.contract_storage(stA, a, call["pA"], call["qA"], stB, b, call["pB"], call["qB"],
+                                                call["pAB"], call["qAB"])
+            got = Cs[0].storage[: Cs[0].nelem].double().cpu().numpy()
+            res[dtype]["member0_rel_err"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del batch, plans
+    f64 = res["f64"]
+    return {"metric": METRIC, "value": f64["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": f64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{cfg['name']}: 64 U(1) contractions A[a;a',w] B[a',w,p;b], D~U{{256..2048}}, "
+                                   f"one grouped launch in a HIP graph", "parallelism": "1 GPU"},
+            "pct_fp64_mfma_peak": round(100 * f64["value"] / PEAK["f64"], 2),
+            "roofline": {"bound": "mfma", "achieved": f64["value"], "peak": PEAK["f64"], "unit": "TFLOP/s",
+                         "frac": round(f64["value"] / PEAK["f64"], 4), "traffic": None,
+                         "kernel": "whole graph (permutes + grouped GEMM + reduce)"},
+            "batch": res}
+
+
+# ---------------------------------------------------------------------------
+# fermionic PEPS double layer
+# ---------------------------------------------------------------------------
+def bench_peps(args, tk, torch, np):
+    from paper_2508_10076_amd import synth
+    cfg = synth.config5()
+    call = cfg["call"]
+    tA = cfg["tensors"]["A"]
+    ctx = tk.Context(0)
+    stream = torch.cuda.Stream()
+    A = tk.tensor_create(ctx, tA["sym"], tA["cod"], tA["dom"])
+    A.storage[: A.nelem].copy_(torch.from_numpy(synth.normal(A.nelem, 5, 0)))
+    Ad = tk.tensor_adjoint(ctx, A)
+    E = tk.tensor_create_contracted(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"],
+                                    call["qAB"])
+    res = {}
+    for prec in ("native", "bf16x3"):
+        P = tk.Plan(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"], call["qAB"], E,
+                    precision=prec)
+        flops = P.info()["flops"]
+
+        def step():
+            tk.tensor_adjoint(ctx, A, Ad, stream=stream)
+            P.execute(Ad, A, E, stream=stream)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                step()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[prec] = {"ms_per_step": round(ms, 5), "value": round(flops / ms / 1e9, 5),
+                     "gbps_output": round(8 * E.nelem / ms / 1e6, 1), "counts": P.counts()}
+    nat = res["native"]
+    return {"metric": METRIC, "value": nat["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": nat["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{cfg['name']}: E = A^dagger o A over P, interleaved rank 8, U(1)xfZ2, D=16",
+                       "E_entries": E.nelem, "parallelism": "1 GPU"},
+            "roofline": {"bound": "hbm", "achieved": nat["gbps_output"], "peak": HBM_PEAK, "unit": "GB/s",
+                         "frac": round(nat["gbps_output"] / HBM_PEAK, 4), "traffic": None,
+                         "kernel": "whole step (output write of E dominates)"},
+            "peps": res}
 
 
 def main():
@@ -60,140 +363,14 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2508_10076_amd import synth, tk
-
+    from paper_2508_10076_amd import tk
     torch.cuda.set_device(0)
-    cfg, cid = heff_workload(args.workload)
-    ctx = tk.Context(0)
-    stream = torch.cuda.Stream()
-
-    # tensors and seeded inputs (identical draws to the parity tests)
-    T = {}
-    for i, k in enumerate(cfg["inputs"]):
-        t = cfg["tensors"][k]
-        T[k] = tk.tensor_create(ctx, t["sym"], t["cod"], t["dom"])
-        T[k].storage[: T[k].nelem].copy_(torch.from_numpy(synth.normal(T[k].nelem, cid, i)))
-    plans = []
-    flops = 0.0
-    for out, a, b, call in cfg["calls"]:
-        T[out] = tk.tensor_create_contracted(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"],
-                                             call["pAB"], call["qAB"])
-        P = tk.Plan(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"], call["pAB"], call["qAB"],
-                    T[out], precision=args.precision)
-        info = P.info()
-        flops += info["flops"]
-        plans.append((P, T[a], T[b], T[out], info))
-    torch.cuda.synchronize()
-
-    # the MFMA-bound contractions: those whose GEMMs have K well above 16
-    mfma_steps = [i for i, (P, *_r) in enumerate(plans) if P.gemms()[:, 2].max() > 64]
-    gemm_flops = sum(plans[i][4]["flops"] for i in mfma_steps)
-
-    # tile configuration per contraction, chosen by the autotuner
-    from paper_2508_10076_amd import autotune
-    tuning = {}
-    for i in mfma_steps:
-        P, A, B, Cc, _ = plans[i]
-        if args.no_tune:
-            break
-        best, times = autotune.tune(P, lambda P=P, A=A, B=B, Cc=Cc: P.execute_stages(A, B, Cc, tk.STAGE_GEMM,
-                                                                                       stream=stream),
-                                    P.gemms().tolist(), stream, cache_path=args.tune_cache, force=True,
-                                    tag=("f64", args.precision))
-        tuning[f"step{i + 1}"] = {"tile": list(best), "ms": {"x".join(map(str, c)): round(t, 4)
-                                                             for c, t in times.items()}}
-    torch.cuda.synchronize()
-
-    def step(ev=None):
-        for i, (P, A, B, Cc, _) in enumerate(plans):
-            if ev is not None and i in mfma_steps:
-                P.execute_stages(A, B, Cc, tk.STAGE_PERMUTE, stream=stream)
-                ev.append(torch.cuda.Event(enable_timing=True))
-                ev[-1].record(stream)
-                P.execute_stages(A, B, Cc, tk.STAGE_GEMM, stream=stream)
-                ev.append(torch.cuda.Event(enable_timing=True))
-                ev[-1].record(stream)
-                P.execute_stages(A, B, Cc, tk.STAGE_ZERO, stream=stream)
-            else:
-                P.execute(A, B, Cc, stream=stream)
-
-    with torch.cuda.stream(stream):
-        for _ in range(args.warmup):
-            step()
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    evs = []
-    t0.record(stream)
-    for _ in range(args.steps):
-        step(evs)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    ms_per_step = total_ms / args.steps
-    gemm_ms = sum(evs[2 * j].elapsed_time(evs[2 * j + 1]) for j in range(len(evs) // 2))
-    gemm_launches = len(evs) // 2
-    gemm_avg_s = gemm_ms / 1e3 / gemm_launches
-    achieved = gemm_flops / len(mfma_steps) / gemm_avg_s / 1e12
-    value = flops * args.steps / (total_ms / 1e3) / 1e12
-    peak_key = {"native": "f64", "f32": "f32", "bf16x3": "bf16"}[args.precision]
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 4),
-        "unit": "TFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "native" else args.precision,
-        "data": "synthetic",
-        "config": {"workload": f"{cfg['name']}: single-site H_eff apply y=L.W.x.R, U(1), D=4096, charges -12..12"
-                               if args.workload == "heff_d4096" else cfg["name"],
-                   "precision": args.precision, "block_flops_per_step": flops,
-                   "parallelism": "1 GPU"},
-        "pct_fp64_mfma_peak": round(100.0 * value / PEAK["f64"], 2),
-        "tiles": {f"step{i + 1}": list(plans[i][0].info()["tile"]) for i in mfma_steps},
-        "tuning": tuning,
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK[peak_key], "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK[peak_key], 4), "traffic": None,
-                     "kernel": "gemm grouped sector GEMM (steps 1 and 3)",
-                     "avg_launch_us": round(gemm_avg_s * 1e6, 2)},
-    }
-
-    # parity spot check + CPU baseline: the oracle on the same inputs
-    if not args.no_cpu_baseline:
-        from oracle import blockwise
-        from oracle.graded import Space, Structure
-        osp = lambda s: Space(s.sectors, s.degs, s.dual)
-        st = {k: Structure(cfg["tensors"][k]["sym"], [osp(s) for s in cfg["tensors"][k]["cod"]],
-                           [osp(s) for s in cfg["tensors"][k]["dom"]]) for k in cfg["inputs"]}
-        v0 = {k: synth.normal(st[k].size, cid, i) for i, k in enumerate(cfg["inputs"])}
-        reps, spent, y_ref = 0, 0.0, None
-        while spent < args.cpu_seconds and reps < 50:
-            s2, v = dict(st), dict(v0)
-            c0 = time.perf_counter()
-            for out_, a, b, call in cfg["calls"]:
-                s2[out_], v[out_] = blockwise.contract_storage(s2[a], v[a], call["pA"], call["qA"], s2[b], v[b],
-                                                               call["pB"], call["qB"], call["pAB"], call["qAB"])
-            spent += time.perf_counter() - c0
-            reps += 1
-            y_ref = v[cfg["output"]]
-        try:
-            from threadpoolctl import threadpool_info
-            cores = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-        except Exception:
-            cores = os.cpu_count()
-        out["cpu_baseline"] = {"value": round(flops * reps / spent / 1e12, 6), "unit": "TFLOP/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": f"{reps} full H_eff applications of the same workload (numpy blockwise "
-                                         f"fp64, OpenBLAS), {spent:.1f} s"}
-        y = T[cfg["output"]].storage[: T[cfg["output"]].nelem].double().cpu().numpy()
-        out["max_rel_err"] = float(np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref))
-        out["max_abs_rel_err_entry"] = float(np.max(np.abs(y - y_ref)) / np.max(np.abs(y_ref)))
+    if args.workload.startswith("heff"):
+        out = bench_heff(args, tk, torch, np)
+    elif args.workload == "batch64":
+        out = bench_batch(args, tk, torch, np)
+    else:
+        out = bench_peps(args, tk, torch, np)
     print(json.dumps(out), flush=True)
 
 

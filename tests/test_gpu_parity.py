@@ -355,3 +355,33 @@ def test_heff_precision_error_bound(ctx, precision, tol):
     print(f"{precision}: normwise error of y {err:.3e}")
     assert err <= tol
     assert err > 1e-12      # the reduced precision really was used
+
+
+# ---------------------------------------------------------------------------
+# fermionic PEPS double layer (reduced sizes; full size in test_gpu_peps.py)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pattern", [(1, 1, 1), (1, 2, 1)])
+def test_peps_double_layer_against_graph_evaluator(ctx, pattern):
+    """E = A^dagger o A over the physical leg, interleaved ket/bra (rank 8,
+    U(1) x fZ2), against the dense graph evaluator; integer data, exact."""
+    cfg = synth.config5(pattern)
+    tA, call = cfg["tensors"]["A"], cfg["call"]
+    stA = ostruct(tA)
+    rng = np.random.default_rng(500 + sum(pattern))
+    a = int_vec(rng, stA.size)
+    A = make(ctx, tA, a)
+    Ad = tk.tensor_adjoint(ctx, A)
+    E = tk.tensor_contract(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"], call["qAB"])
+    sAd, bAd = blockwise.adjoint(stA, stA.to_blocks(a))
+    vAd = sAd.from_blocks(bAd)
+    D, dcod, ddom = dense.contract_dense("U1xFZ2", sAd.to_dense(vAd), sAd.cod, sAd.dom, call["pA"], call["qA"],
+                                         stA.to_dense(a), stA.cod, stA.dom, call["pB"], call["qB"],
+                                         call["pAB"], call["qAB"])
+    stE = Structure("U1xFZ2", dcod, ddom)
+    assert stE.size == E.nelem
+    got = stE.to_dense(download(E))
+    assert np.array_equal(got, D)
+    # the interleave really moves odd legs past each other: the bosonic
+    # (sign-free) result differs
+    Db = np.einsum(sAd.to_dense(vAd), [0, 1, 2, 3, 8], stA.to_dense(a), [8, 4, 5, 6, 7], [0, 4, 1, 5, 2, 6, 3, 7])
+    assert not np.array_equal(Db, D) and np.array_equal(np.abs(Db), np.abs(D))
