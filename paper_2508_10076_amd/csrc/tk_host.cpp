@@ -872,18 +872,19 @@ void upload_schedule(DevBuf& d_tiles, DevBuf& d_wg, DevBuf& d_partials, DevBuf& 
   d_groups.upload(sc.groups);
 }
 
-void plan_reschedule(tk_plan& P, int tm, int tn, int tk) {
+void plan_reschedule(tk_plan& P, int tm, int tn, int tk, bool upload = true) {
   P.tile_m = tm;
   P.tile_n = tn;
   P.tile_k = tk;
-  Sched sc = schedule_tiles(P.descs, tm, tn, tk, P.ctx ? P.ctx->num_cu : 256);
+  const int per_cu = P.ctx ? tk::gemm_blocks_per_cu(P.dtype, P.precision, tm, tn, tk) : 1;
+  Sched sc = schedule_tiles(P.descs, tm, tn, tk, (P.ctx ? P.ctx->num_cu : 256) * per_cu);
   P.tiles = sc.tiles;
   P.wg_first = sc.wg_first;
   P.groups = sc.groups;
   P.ngroups = sc.ngroups;
   P.nslots = sc.nslots;
   P.makespan = sc.makespan;
-  if (P.ctx) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
+  if (P.ctx && upload) upload_schedule(P.d_tiles, P.d_wg, P.d_partials, P.d_groups, sc, tm, tn);
 }
 
 void choose_default_tile(const std::vector<GemmDesc>& descs, int precision, int* tm, int* tn, int* tk) {
@@ -1145,12 +1146,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
   for (auto& l : P->smallk) pack_workgroups(l);
   int tm, tn, tkk;
   choose_default_tile(P->descs, precision, &tm, &tn, &tkk);
-  {
-    tk_context* keep = P->ctx;
-    P->ctx = nullptr;  // schedule only; uploads follow below
-    plan_reschedule(*P, tm, tn, tkk);
-    P->ctx = keep;
-  }
+  plan_reschedule(*P, tm, tn, tkk, false);  // uploads follow below
 
   if (ctx) {
     const size_t es = A->esize();
@@ -1743,7 +1739,7 @@ void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
   b.tile_m = tm;
   b.tile_n = tn;
   b.tile_k = tk;
-  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu);
+  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu * tk::gemm_blocks_per_cu(b.dtype, b.precision, tm, tn, tk));
   b.tiles = sc.tiles;
   b.wg_first = sc.wg_first;
   b.groups = sc.groups;

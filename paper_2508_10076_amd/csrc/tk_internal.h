@@ -138,6 +138,9 @@ hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k);
+// Workgroups of the grouped GEMM a CU holds at once for this configuration
+// (registers and LDS); the persistent grid is this many per CU.
+int gemm_blocks_per_cu(int dtype, int precision, int tile_m, int tile_n, int tile_k);
 int num_tile_shapes();
 void tile_shape(int i, int* tm, int* tn, int* tk);
 

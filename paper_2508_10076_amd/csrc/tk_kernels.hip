@@ -862,6 +862,38 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
   return hipErrorInvalidValue;
 }
 
+template <typename TS, int BM, int BN, int WM, int WN, int BK>
+static int blocks_per_cu_kind(int kind) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+  if (kind == 0) {
+    if constexpr (sizeof(TS) == 8)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_f64_kernel<BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+  } else if (kind == 1) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_f32_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+  } else {
+    if constexpr (BK % 32 == 0)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n < 1 ? 1 : n;
+}
+
+int gemm_blocks_per_cu(int dtype, int precision, int tile_m, int tile_n, int tile_k) {
+  if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return 1;
+  const int kind = compute_kind(dtype, precision);
+#define TK_OCC_CASE(BM_, BN_, BK_, WM_, WN_)                                                       \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_)                                             \
+    return dtype == 0 ? blocks_per_cu_kind<double, BM_, BN_, WM_, WN_, BK_>(kind)                  \
+                      : blocks_per_cu_kind<float, BM_, BN_, WM_, WN_, BK_>(kind);
+  TK_GEMM_SHAPES(TK_OCC_CASE)
+#undef TK_OCC_CASE
+  return 1;
+}
+
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream) {
   if (ngroups <= 0) return hipSuccess;
