@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile configuration")
     ap.add_argument("--tune-cache", default=None, help="JSON file to read/write tuned tile configurations")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -365,6 +367,14 @@ def main():
 
     from paper_2508_10076_amd import tk
     torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.randn(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload.startswith("heff"):
         out = bench_heff(args, tk, torch, np)
     elif args.workload == "batch64":
