@@ -48,7 +48,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile configuration")
-    ap.add_argument("--tune-cache", default=None, help="JSON file to read/write tuned tile configurations")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of tuned tile configurations (default: the one shipped with the package)")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every tile configuration again and write the winners to the tune cache")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -96,7 +99,7 @@ class Heff:
         self.gemm_flops = sum(self.plans[i][4]["flops"] for i in self.mfma)
         torch.cuda.synchronize()
 
-    def tune(self, precision, cache):
+    def tune(self, precision, cache, force):
         from paper_2508_10076_amd import autotune
         tk, s = self.tk, self.stream
         out = {}
@@ -104,7 +107,7 @@ class Heff:
             P, A, B, Cc, _ = self.plans[i]
             best, times = autotune.tune(P, lambda P=P, A=A, B=B, Cc=Cc: P.execute_stages(A, B, Cc, tk.STAGE_GEMM,
                                                                                            stream=s),
-                                        P.gemms().tolist(), s, cache_path=cache, force=cache is None,
+                                        P.gemms().tolist(), s, cache_path=cache, force=force,
                                         tag=("f64", precision))
             out[f"step{i + 1}"] = {"tile": list(best),
                                    "ms": {"x".join(map(str, c)): round(t, 4) for c, t in times.items()}}
@@ -176,7 +179,7 @@ def bench_heff(args, tk, torch, np):
     ctx = tk.Context(0)
     stream = torch.cuda.Stream()
     H = Heff(tk, torch, cfg, cid, ctx, stream, args.precision)
-    tuning = {} if args.no_tune else H.tune(args.precision, args.tune_cache)
+    tuning = {} if args.no_tune else H.tune(args.precision, args.tune_cache, args.retune)
     torch.cuda.synchronize()
     r = H.run(args.steps, args.warmup)
     pk = PEAK_KEY[args.precision]
@@ -203,7 +206,7 @@ def bench_heff(args, tk, torch, np):
         for prec in ("f32", "bf16x3"):
             Hv = Heff(tk, torch, cfg, cid, ctx, stream, prec)
             if not args.no_tune:
-                Hv.tune(prec, args.tune_cache)
+                Hv.tune(prec, args.tune_cache, args.retune)
             rv = Hv.run(args.steps, args.warmup)
             variants[prec] = {"value": round(rv["value"], 4), "ms_per_step": round(rv["ms_per_step"], 5),
                               "gemm_tflops": round(rv["gemm_tflops"], 3),
@@ -258,7 +261,7 @@ def bench_batch(args, tk, torch, np):
         best = None
         if not args.no_tune:
             best, _ = autotune.tune(batch, lambda: batch.launch(stream), mnk, stream, cache_path=args.tune_cache,
-                                    force=args.tune_cache is None, tag=(dtype, "native"))
+                                    force=args.retune, tag=(dtype, "native"))
         batch.capture(stream)
 
         def timed(fn, reps):
@@ -365,7 +368,9 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2508_10076_amd import tk
+    from paper_2508_10076_amd import autotune, tk
+    if args.tune_cache is None:
+        args.tune_cache = autotune.DEFAULT_CACHE
     torch.cuda.set_device(0)
     if args.copy_probe_mib:
         n = args.copy_probe_mib * (1 << 20) // 8

@@ -784,13 +784,20 @@ double tile_activity(int tm, int tn, int64_t mrem, int64_t nrem) {
   return double(busiest) / per_simd;
 }
 
-Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg, int64_t split_target) {
-  struct U {
-    GemmTile t;
-    int64_t cost;
-  };
-  std::vector<U> units;
-  Sched out;
+// Work units of the tiles, each tagged with a cluster: tiles of one sector
+// GEMM that share a band of row panels (and so their A panels and all B
+// panels of the sector) form one cluster.
+struct Unit {
+  GemmTile t;
+  int64_t cost;
+  int64_t cluster;
+};
+
+std::vector<Unit> make_units(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int64_t split_target,
+                             Sched& out) {
+  constexpr int kBand = 4;  // row panels per cluster
+  std::vector<Unit> units;
+  int64_t cluster = 0;
   for (size_t g = 0; g < descs.size(); ++g) {
     const GemmDesc& d = descs[g];
     const int64_t stages = (d.K + BK - 1) / BK;
@@ -799,7 +806,8 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
       S = std::min<int64_t>((stages + split_target - 1) / split_target, 16);
       S = std::min<int64_t>(S, std::max<int64_t>(1, stages / 4));
     }
-    for (int m0 = 0; m0 < d.M; m0 += tm)
+    for (int m0 = 0; m0 < d.M; m0 += tm) {
+      if ((m0 / tm) % kBand == 0) ++cluster;
       for (int n0 = 0; n0 < d.N; n0 += tn) {
         const int32_t group = S > 1 ? out.ngroups++ : -1;
         const int32_t slot0 = S > 1 ? out.nslots : -1;
@@ -821,16 +829,20 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
           // activity, plus prologue/epilogue (~3 stages)
           const double act = tile_activity(tm, tn, d.M - m0, d.N - n0);
           const int64_t cost = static_cast<int64_t>(4.0 * (s1 - s0) * (BK / 16) * act) + 12;
-          units.push_back({t, cost});
+          units.push_back({t, cost, cluster});
         }
       }
+    }
   }
-  std::stable_sort(units.begin(), units.end(), [](const U& a, const U& b) { return a.cost > b.cost; });
-  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(units.size())));
-  std::vector<std::vector<GemmTile>> per(nwg);
+  return units;
+}
+
+// LPT of units over a set of workgroups; returns the makespan.
+int64_t lpt_assign(std::vector<Unit>& units, const std::vector<int>& wgs, std::vector<std::vector<GemmTile>>& per) {
+  std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
   using E = std::pair<int64_t, int>;
   std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
-  for (int w = 0; w < nwg; ++w) heap.push({0, w});
+  for (int w : wgs) heap.push({0, w});
   int64_t mk = 0;
   for (const auto& u : units) {
     E e = heap.top();
@@ -838,6 +850,49 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
     per[e.second].push_back(u.t);
     mk = std::max(mk, e.first + u.cost);
     heap.push({e.first + u.cost, e.second});
+  }
+  return mk;
+}
+
+// Schedule with nxcd > 1: clusters are first spread over the XCDs by LPT on
+// their total cost, then each XCD's units are LPT-scheduled over the
+// workgroups that run on it (workgroup w runs on XCD w % nxcd), so tiles
+// sharing operand panels share that XCD's L2.
+Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg, int64_t split_target,
+          int nxcd = 1) {
+  Sched out;
+  std::vector<Unit> units = make_units(descs, tm, tn, BK, split_target, out);
+  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(units.size())));
+  std::vector<std::vector<GemmTile>> per(nwg);
+  int64_t mk = 0;
+  if (nxcd <= 1 || nwg < 2 * nxcd) {
+    std::vector<int> all(nwg);
+    std::iota(all.begin(), all.end(), 0);
+    mk = lpt_assign(units, all, per);
+  } else {
+    std::map<int64_t, int64_t> ccost;
+    for (const auto& u : units) ccost[u.cluster] += u.cost;
+    std::vector<std::pair<int64_t, int64_t>> cl(ccost.begin(), ccost.end());  // (cluster, cost)
+    std::stable_sort(cl.begin(), cl.end(), [](auto& a, auto& b) { return a.second > b.second; });
+    // capacity of an XCD is proportional to its workgroup count
+    std::vector<int> nw(nxcd, 0);
+    for (int w = 0; w < nwg; ++w) ++nw[w % nxcd];
+    std::vector<double> load(nxcd, 0.0);
+    std::map<int64_t, int> where;
+    for (const auto& c : cl) {
+      int best = 0;
+      for (int x = 1; x < nxcd; ++x)
+        if ((load[x] + c.second) / nw[x] < (load[best] + c.second) / nw[best]) best = x;
+      load[best] += c.second;
+      where[c.first] = best;
+    }
+    std::vector<std::vector<Unit>> ux(nxcd);
+    for (const auto& u : units) ux[where[u.cluster]].push_back(u);
+    for (int x = 0; x < nxcd; ++x) {
+      std::vector<int> wgs;
+      for (int w = x; w < nwg; w += nxcd) wgs.push_back(w);
+      mk = std::max(mk, lpt_assign(ux[x], wgs, per));
+    }
   }
   // the reduce kernel reads and writes every partial once: at ~5 TB/s one
   // 16-deep fp64 stage of MFMA work (4096 cycles at 2.4 GHz) moves ~8.5 MB
@@ -851,15 +906,23 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
   return out;
 }
 
+// XCDs of the device: workgroups are dispatched round robin over them.
+int g_nxcd = 8;
+
 Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int max_wg) {
-  Sched best = lpt(descs, tm, tn, tk, max_wg, 0);
+  Sched best = lpt(descs, tm, tn, tk, max_wg, 0, 1);
   if (descs.empty()) return best;
   int64_t total = 0;
   for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + tk - 1) / tk);
-  for (int per_wg : {2, 3, 4, 6, 8}) {
-    const int64_t target = std::max<int64_t>(4, total / (int64_t(max_wg) * per_wg));
-    Sched s = lpt(descs, tm, tn, tk, max_wg, target);
-    if (s.makespan < 0.97 * best.makespan) best = std::move(s);
+  std::vector<int64_t> targets = {0};
+  for (int per_wg : {2, 3, 4, 6, 8}) targets.push_back(std::max<int64_t>(4, total / (int64_t(max_wg) * per_wg)));
+  for (int64_t target : targets) {
+    for (int nx : {1, g_nxcd}) {
+      Sched s = lpt(descs, tm, tn, tk, max_wg, target, nx);
+      // L2 locality is worth a few percent of modelled makespan
+      const double bias = nx > 1 ? 0.95 : 1.0;
+      if (s.makespan * bias < 0.97 * best.makespan) best = std::move(s);
+    }
   }
   return best;
 }
