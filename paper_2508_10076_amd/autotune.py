@@ -68,7 +68,8 @@ def tune(target, run, mnk, stream, cache_path=DEFAULT_CACHE, reps=5, force=False
     if not force and key in cache:
         cfg = tuple(cache[key]["tile"])
         target.set_tile(*cfg)
-        return cfg, cache[key].get("times", {})
+        times = {tuple(int(x) for x in c.split("x")): t for c, t in cache[key].get("times", {}).items()}
+        return cfg, times
     times = {}
     for cfg in tk.tile_shapes():
         try:

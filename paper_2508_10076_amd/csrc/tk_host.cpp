@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -784,20 +785,22 @@ double tile_activity(int tm, int tn, int64_t mrem, int64_t nrem) {
   return double(busiest) / per_simd;
 }
 
-// Work units of the tiles, each tagged with a cluster: tiles of one sector
-// GEMM that share a band of row panels (and so their A panels and all B
-// panels of the sector) form one cluster.
+// XCDs of the device: workgroups are dispatched round robin over them.
+constexpr int kNumXcd = 8;
+
+// Work units of the tiles, each tagged with a cluster: a block of bm x bn
+// tiles of one sector GEMM, which shares bm row panels of A and bn column
+// panels of B.  Tiles are generated cluster by cluster, so that the units
+// dealt out together to the CUs of one XCD (and run at the same time) read
+// the same panels through that XCD's L2.
 struct Unit {
   GemmTile t;
   int64_t cost;
-  int64_t cluster;
 };
 
 std::vector<Unit> make_units(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int64_t split_target,
-                             Sched& out) {
-  constexpr int kBand = 4;  // row panels per cluster
+                             int bm, int bn, Sched& out) {
   std::vector<Unit> units;
-  int64_t cluster = 0;
   for (size_t g = 0; g < descs.size(); ++g) {
     const GemmDesc& d = descs[g];
     const int64_t stages = (d.K + BK - 1) / BK;
@@ -806,93 +809,74 @@ std::vector<Unit> make_units(const std::vector<GemmDesc>& descs, int tm, int tn,
       S = std::min<int64_t>((stages + split_target - 1) / split_target, 16);
       S = std::min<int64_t>(S, std::max<int64_t>(1, stages / 4));
     }
-    for (int m0 = 0; m0 < d.M; m0 += tm) {
-      if ((m0 / tm) % kBand == 0) ++cluster;
-      for (int n0 = 0; n0 < d.N; n0 += tn) {
-        const int32_t group = S > 1 ? out.ngroups++ : -1;
-        const int32_t slot0 = S > 1 ? out.nslots : -1;
-        if (S > 1) out.nslots += static_cast<int32_t>(S);
-        for (int64_t sp = 0; sp < S; ++sp) {
-          const int64_t s0 = stages * sp / S, s1 = stages * (sp + 1) / S;
-          GemmTile t{};
-          t.gemm = static_cast<int32_t>(g);
-          t.m0 = m0;
-          t.n0 = n0;
-          t.k0 = static_cast<int32_t>(s0 * BK);
-          t.k1 = static_cast<int32_t>(std::min<int64_t>(s1 * BK, d.K));
-          t.nsplit = static_cast<int32_t>(S);
-          t.split = static_cast<int32_t>(sp);
-          t.group = group;
-          t.slot0 = slot0;
-          if (S > 1 && sp == 0) out.groups.push_back(t);
-          // cost in quarter 16-deep stages: MFMA work scaled by the tile's
-          // activity, plus prologue/epilogue (~3 stages)
-          const double act = tile_activity(tm, tn, d.M - m0, d.N - n0);
-          const int64_t cost = static_cast<int64_t>(4.0 * (s1 - s0) * (BK / 16) * act) + 12;
-          units.push_back({t, cost, cluster});
-        }
-      }
-    }
+    const int mt = (d.M + tm - 1) / tm, nt = (d.N + tn - 1) / tn;
+    for (int cm = 0; cm < mt; cm += bm)
+      for (int cn = 0; cn < nt; cn += bn)
+        for (int im = cm; im < std::min(mt, cm + bm); ++im)
+          for (int in = cn; in < std::min(nt, cn + bn); ++in) {
+            const int m0 = im * tm, n0 = in * tn;
+            const int32_t group = S > 1 ? out.ngroups++ : -1;
+            const int32_t slot0 = S > 1 ? out.nslots : -1;
+            if (S > 1) out.nslots += static_cast<int32_t>(S);
+            for (int64_t sp = 0; sp < S; ++sp) {
+              const int64_t s0 = stages * sp / S, s1 = stages * (sp + 1) / S;
+              GemmTile t{};
+              t.gemm = static_cast<int32_t>(g);
+              t.m0 = m0;
+              t.n0 = n0;
+              t.k0 = static_cast<int32_t>(s0 * BK);
+              t.k1 = static_cast<int32_t>(std::min<int64_t>(s1 * BK, d.K));
+              t.nsplit = static_cast<int32_t>(S);
+              t.split = static_cast<int32_t>(sp);
+              t.group = group;
+              t.slot0 = slot0;
+              if (S > 1 && sp == 0) out.groups.push_back(t);
+              // cost in quarter 16-deep stages: MFMA work scaled by the
+              // tile's activity, plus prologue/epilogue (~3 stages)
+              const double act = tile_activity(tm, tn, d.M - m0, d.N - n0);
+              const int64_t cost = static_cast<int64_t>(4.0 * (s1 - s0) * (BK / 16) * act) + 12;
+              units.push_back({t, cost});
+            }
+          }
   }
   return units;
 }
 
-// LPT of units over a set of workgroups; returns the makespan.
-int64_t lpt_assign(std::vector<Unit>& units, const std::vector<int>& wgs, std::vector<std::vector<GemmTile>>& per) {
+// LPT (longest unit first, to the least loaded workgroup) over the
+// workgroups taken in the order given, ties going to the earlier one.  The
+// order fills one workgroup slot of every CU before the next slot, and
+// within a slot walks the CUs of one XCD before the next XCD (workgroup w
+// runs on XCD w % kNumXcd, and resident workgroups of an XCD spread over its
+// CUs in turn).  So the most expensive units land on distinct CUs (the
+// workgroups of a CU share its matrix cores), and runs of consecutive units,
+// which come from one cluster, share an XCD.
+Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu, int bpc, int64_t split_target) {
+  Sched out;
+  const int cpx = std::max(1, num_cu / kNumXcd);
+  const int bm = std::max(1, static_cast<int>(std::sqrt(double(cpx))));
+  const int bn = std::max(1, cpx / bm);
+  std::vector<Unit> units = make_units(descs, tm, tn, BK, split_target, bm, bn, out);
+  const int nwg = static_cast<int>(std::min<int64_t>(int64_t(num_cu) * bpc, static_cast<int64_t>(units.size())));
+  std::vector<int> order;
+  for (int slot = 0; slot < bpc; ++slot)
+    for (int x = 0; x < kNumXcd; ++x)
+      for (int c = 0; c < cpx; ++c) {
+        const int w = x + kNumXcd * (c + cpx * slot);
+        if (w < nwg) order.push_back(w);
+      }
+  for (int w = kNumXcd * cpx * bpc; w < nwg; ++w) order.push_back(w);  // CU counts not a multiple of 8
   std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
-  using E = std::pair<int64_t, int>;
+  std::vector<std::vector<GemmTile>> per(nwg);
+  using E = std::pair<int64_t, int>;  // (load, rank in order)
   std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
-  for (int w : wgs) heap.push({0, w});
+  for (int v = 0; v < static_cast<int>(order.size()); ++v) heap.push({0, v});
   int64_t mk = 0;
   for (const auto& u : units) {
     E e = heap.top();
     heap.pop();
-    per[e.second].push_back(u.t);
+    per[order[e.second]].push_back(u.t);
     mk = std::max(mk, e.first + u.cost);
     heap.push({e.first + u.cost, e.second});
-  }
-  return mk;
-}
-
-// Schedule with nxcd > 1: clusters are first spread over the XCDs by LPT on
-// their total cost, then each XCD's units are LPT-scheduled over the
-// workgroups that run on it (workgroup w runs on XCD w % nxcd), so tiles
-// sharing operand panels share that XCD's L2.
-Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg, int64_t split_target,
-          int nxcd = 1) {
-  Sched out;
-  std::vector<Unit> units = make_units(descs, tm, tn, BK, split_target, out);
-  const int nwg = static_cast<int>(std::min<int64_t>(max_wg, static_cast<int64_t>(units.size())));
-  std::vector<std::vector<GemmTile>> per(nwg);
-  int64_t mk = 0;
-  if (nxcd <= 1 || nwg < 2 * nxcd) {
-    std::vector<int> all(nwg);
-    std::iota(all.begin(), all.end(), 0);
-    mk = lpt_assign(units, all, per);
-  } else {
-    std::map<int64_t, int64_t> ccost;
-    for (const auto& u : units) ccost[u.cluster] += u.cost;
-    std::vector<std::pair<int64_t, int64_t>> cl(ccost.begin(), ccost.end());  // (cluster, cost)
-    std::stable_sort(cl.begin(), cl.end(), [](auto& a, auto& b) { return a.second > b.second; });
-    // capacity of an XCD is proportional to its workgroup count
-    std::vector<int> nw(nxcd, 0);
-    for (int w = 0; w < nwg; ++w) ++nw[w % nxcd];
-    std::vector<double> load(nxcd, 0.0);
-    std::map<int64_t, int> where;
-    for (const auto& c : cl) {
-      int best = 0;
-      for (int x = 1; x < nxcd; ++x)
-        if ((load[x] + c.second) / nw[x] < (load[best] + c.second) / nw[best]) best = x;
-      load[best] += c.second;
-      where[c.first] = best;
-    }
-    std::vector<std::vector<Unit>> ux(nxcd);
-    for (const auto& u : units) ux[where[u.cluster]].push_back(u);
-    for (int x = 0; x < nxcd; ++x) {
-      std::vector<int> wgs;
-      for (int w = x; w < nwg; w += nxcd) wgs.push_back(w);
-      mk = std::max(mk, lpt_assign(ux[x], wgs, per));
-    }
   }
   // the reduce kernel reads and writes every partial once: at ~5 TB/s one
   // 16-deep fp64 stage of MFMA work (4096 cycles at 2.4 GHz) moves ~8.5 MB
@@ -906,23 +890,16 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int max_wg
   return out;
 }
 
-// XCDs of the device: workgroups are dispatched round robin over them.
-int g_nxcd = 8;
-
-Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int max_wg) {
-  Sched best = lpt(descs, tm, tn, tk, max_wg, 0, 1);
+Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int num_cu, int bpc) {
+  Sched best = lpt(descs, tm, tn, tk, num_cu, bpc, 0);
   if (descs.empty()) return best;
+  const int64_t max_wg = int64_t(num_cu) * bpc;
   int64_t total = 0;
   for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + tk - 1) / tk);
-  std::vector<int64_t> targets = {0};
-  for (int per_wg : {2, 3, 4, 6, 8}) targets.push_back(std::max<int64_t>(4, total / (int64_t(max_wg) * per_wg)));
-  for (int64_t target : targets) {
-    for (int nx : {1, g_nxcd}) {
-      Sched s = lpt(descs, tm, tn, tk, max_wg, target, nx);
-      // L2 locality is worth a few percent of modelled makespan
-      const double bias = nx > 1 ? 0.95 : 1.0;
-      if (s.makespan * bias < 0.97 * best.makespan) best = std::move(s);
-    }
+  for (int per_wg : {2, 3, 4, 6, 8}) {
+    const int64_t target = std::max<int64_t>(4, total / (max_wg * per_wg));
+    Sched s = lpt(descs, tm, tn, tk, num_cu, bpc, target);
+    if (s.makespan < 0.97 * best.makespan) best = std::move(s);
   }
   return best;
 }
@@ -940,7 +917,7 @@ void plan_reschedule(tk_plan& P, int tm, int tn, int tk, bool upload = true) {
   P.tile_n = tn;
   P.tile_k = tk;
   const int per_cu = P.ctx ? tk::gemm_blocks_per_cu(P.dtype, P.precision, tm, tn, tk) : 1;
-  Sched sc = schedule_tiles(P.descs, tm, tn, tk, (P.ctx ? P.ctx->num_cu : 256) * per_cu);
+  Sched sc = schedule_tiles(P.descs, tm, tn, tk, P.ctx ? P.ctx->num_cu : 256, per_cu);
   P.tiles = sc.tiles;
   P.wg_first = sc.wg_first;
   P.groups = sc.groups;
@@ -1058,6 +1035,10 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       d.K = checked_i32(K, "K");
       d.lda = d.M;
       d.ldb = d.K;
+      // the GEMM kernels address a stage of B with 32-bit byte offsets of a
+      // few columns (at most 3 * ldb + 64 elements)
+      if (K > kSmallK && K >= (int64_t(1) << 26))
+        fail(TK_ERR_UNSUPPORTED, "contracted dimension of one coupled sector above 2^26");
       d.a_buf = abuf;
       d.b_buf = bbuf;
       P->flops += 2.0 * double(M) * double(N) * double(K);
@@ -1802,7 +1783,7 @@ void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
   b.tile_m = tm;
   b.tile_n = tn;
   b.tile_k = tk;
-  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu * tk::gemm_blocks_per_cu(b.dtype, b.precision, tm, tn, tk));
+  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu, tk::gemm_blocks_per_cu(b.dtype, b.precision, tm, tn, tk));
   b.tiles = sc.tiles;
   b.wg_first = sc.wg_first;
   b.groups = sc.groups;

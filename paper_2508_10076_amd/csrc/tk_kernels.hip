@@ -20,10 +20,22 @@ namespace tk {
 // the buffer table would otherwise be generic (flat) pointers, whose loads
 // count against the LDS wait counter and serialise with LDS traffic.
 #define TK_GLOBAL __attribute__((address_space(1)))
+// read-only tables (tiles, GEMM descriptors) read through the constant
+// address space: uniform loads from it become scalar loads even in kernels
+// that store to global memory
+#ifdef __HIP_DEVICE_COMPILE__
+#define TK_CONST __attribute__((address_space(4)))
+#else
+#define TK_CONST
+#endif
+template <typename T>
+__device__ __forceinline__ const TK_CONST T* const_ptr(const T* p) {
+  return (const TK_CONST T*)p;
+}
 
 template <typename T>
 __device__ __forceinline__ TK_GLOBAL T* buf_ptr(const Ptrs& P, int id) {
-  return (TK_GLOBAL T*)(P.table ? reinterpret_cast<void*>(P.table[id]) : P.p[id]);
+  return (TK_GLOBAL T*)(P.table ? reinterpret_cast<void*>(const_ptr(P.table)[id]) : P.p[id]);
 }
 
 // ---------------------------------------------------------------------------
@@ -150,6 +162,62 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
   Cbase[idx] = static_cast<TC>(v);
 }
 
+// Epilogue of an fp64 tile held transposed: value v of acc[mi][ni] is
+// C[r0 + 16 mi][c0 + 16 ni + 4 v] (r0, c0 already include the lane's row
+// and column).  Scatter outputs (mode 1) look up the row map once per row
+// and the column map once per column; the map and pair tables are read
+// through restrict pointers so their loads may move ahead of the stores.
+template <int TM, int TN>
+__device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL double* __restrict__ C,
+                                             int r0, int c0, const d4_t (&acc)[TM][TN]) {
+  const double alpha = args.alpha, beta = args.beta;
+  if (d.mode == 0) {
+#pragma unroll
+    for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = c0 + 16 * ni + 4 * v;
+        if (c >= d.N) continue;
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) {
+          const int r = r0 + 16 * mi;
+          if (r >= d.M) continue;
+          const int64_t x = d.c + static_cast<int64_t>(c) * d.ldc + r;
+          double val = alpha * acc[mi][ni][v];
+          if (beta != 0.0) val += beta * C[x];
+          C[x] = val;
+        }
+      }
+    return;
+  }
+  const LegMap* __restrict__ rmap = args.row_map + d.row_map;
+  const LegMap* __restrict__ cmap = args.col_map + d.col_map;
+  const PairDesc* __restrict__ pairs = args.pairs + d.pair_base;
+  LegMap rm[TM];
+#pragma unroll
+  for (int mi = 0; mi < TM; ++mi) rm[mi] = rmap[min(r0 + 16 * mi, d.M - 1)];
+#pragma unroll
+  for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int c = c0 + 16 * ni + 4 * v;
+      if (c >= d.N) continue;
+      const LegMap cm = cmap[c];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi) {
+        if (r0 + 16 * mi >= d.M) continue;
+        const PairDesc& pd = pairs[static_cast<int64_t>(rm[mi].chan) * d.ncc + cm.chan];
+        int64_t x = pd.base;
+#pragma unroll
+        for (int l = 0; l < 4; ++l)
+          x += static_cast<int64_t>(rm[mi].idx[l]) * pd.S[l] + static_cast<int64_t>(cm.idx[l]) * pd.S[4 + l];
+        double val = alpha * pd.sign * acc[mi][ni][v];
+        if (beta != 0.0) val += beta * C[x];
+        C[x] = val;
+      }
+    }
+}
+
 // Grouped sector GEMM, fp64 MFMA 16x16x4.  A workgroup of WGM x WGN waves
 // owns a BM x BN tile; each wave a (BM/WGM) x (BN/WGN) sub-tile made of 16 x 16
 // MFMA tiles.  K advances in stages of 16 through a double-buffered LDS tile:
@@ -230,127 +298,217 @@ __device__ __forceinline__ void wave_origin(int w, int* wm, int* wn) {
   }
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK_>
-__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs args) {
+#ifndef TK_F64_PREFETCH
+#define TK_F64_PREFETCH 2
+#endif
+
+// third word of a raw buffer resource on gfx9 (32-bit data format, no
+// swizzle, no stride)
+constexpr int kBufWord3 = 0x00020000;
+
+// waves per SIMD the register budget is sized for: four workgroups per CU
+// for the 64 x 64 x 16 tile (128 VGPRs), two waves per SIMD otherwise
+template <int BM, int BN, int BK>
+constexpr int kF64WavesPerEu = (BM * BN <= 64 * 64 && BK == 16) ? 4 : 2;
+
+template <int BM, int BN, int WGM, int WGN, int BK_, int PF = TK_F64_PREFETCH>
+__global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void gemm_f64_kernel(GemmArgs args) {
   using TT = F64Tile<BM, BN, WGM, WGN, BK_>;
   constexpr int NT = TT::NT, BK = TT::BK, TM = TT::TM, TN = TT::TN;
-  constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD, B_CPL = TT::B_CPL, B_LD = TT::B_LD;
+  constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD;
   __shared__ double As[2][BK][BM + TT::APAD];
   __shared__ double Bs[2][BN][BK + TT::BPAD];
 
+  const TK_CONST GemmTile* tiles = const_ptr(args.tiles);
+  const TK_CONST GemmDesc* descs = const_ptr(args.descs);
+  const int t_begin = const_ptr(args.wg_first)[blockIdx.x], t_end = const_ptr(args.wg_first)[blockIdx.x + 1];
+  if (t_begin >= t_end) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   int wm, wn;
   wave_origin<TT>(wave, &wm, &wn);
-  const int a_m = tid % BM, a_k = tid / BM;
-  const int b_k = tid % BK, b_n = tid / BK;
+  static_assert(BM % 64 == 0 && 64 % BK == 0, "load mapping");
+  // wave-uniform parts of the load mapping (A: one k row per instruction;
+  // B: 64/BK columns per instruction)
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int a_k = (wv * 64) / BM, a_m0 = (wv * 64) % BM, a_m = a_m0 + lane;
   constexpr int B_NPL = NT / BK;  // columns of B covered per load
   constexpr int B_LDK = BN / B_NPL;
+  const int b_c0 = wv * (64 / BK), b_cl = lane / BK, b_k = lane % BK, b_n = b_c0 + b_cl;
 
-  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
-    const GemmTile tile = args.tiles[ti];
-    const GemmDesc d = args.descs[tile.gemm];
-    const TK_GLOBAL double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a;
-    const TK_GLOBAL double* B = buf_ptr<const double>(args.ptrs, d.b_buf) + d.b;
+  // The workgroup's tiles form one stream of K stages, each tile's stage
+  // count rounded up to a multiple of PF (the extra stages load zeros and
+  // skip their MFMAs).  A load cursor runs PF + 1 stages ahead of the
+  // multiply cursor through a register ring of PF stages and a double
+  // buffered LDS stage, across tile boundaries: the first stages of the next
+  // tile are in flight before the epilogue of the current one issues its
+  // stores, and no tile starts with an empty pipeline.
+  auto padded_stages = [&](int t) {
+    const GemmTile tt = tiles[t];
+    const int n = max(1, (tt.k1 - tt.k0 + BK - 1) / BK);
+    return (n + PF - 1) / PF * PF;
+  };
+  int total = 0;
+  for (int t = t_begin; t < t_end; ++t) total += padded_stages(t);
 
-    d4_t acc[TM][TN];
+  // Operand loads are raw buffer loads, one resource per load instruction
+  // with a wave-uniform base: a load whose offset reaches past the
+  // resource's record count reads zero, which pads ragged tile edges, the K
+  // tail and the stages past the last tile without branches (so the loads
+  // form straight-line code and the waits for them can be counted exactly).
+  // A: each instruction of a wave reads 64 consecutive m of one k row; its
+  // record count is the number of valid m of that run, or zero past the K
+  // range.  B: each instruction reads 64/BK columns of BK consecutive k;
+  // invalid lanes get an out-of-range offset.
+  // load cursor: tile, stage, stage count and K range of the tile, operand
+  // bases and strides (wave-uniform, kept in scalar registers), plus the
+  // lane's B offset and column validity
+  int l_t = 0, l_s = 0, l_ns = 0, l_k0 = 0, l_kend = 0;
+  const char* a_base = nullptr;
+  const char* b_base = nullptr;
+  int64_t lda8 = 0, ldb8 = 0;
+  uint32_t a_recs = 0, b_off = 0;
+  bool b_nok[B_LDK];
+  auto uni = [](int x) { return __builtin_amdgcn_readfirstlane(x); };
+  auto uni64 = [](int64_t x) {
+    const uint64_t u = static_cast<uint64_t>(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+  };
+  auto load_tile = [&](int t_) {
+    const int t = uni(t_);
+    l_t = t;
+    l_s = 0;
+    if (t >= t_end) {  // past the last tile: every later load reads zero
+      l_ns = 1 << 30;
+      l_kend = l_k0;
+      return;
+    }
+    const GemmTile tile = tiles[t];
+    const GemmDesc d = descs[tile.gemm];
+    l_ns = uni(padded_stages(t));
+    l_k0 = uni(tile.k0);
+    l_kend = uni(tile.k1);
+    lda8 = uni64(static_cast<int64_t>(d.lda) * 8);
+    ldb8 = uni64(static_cast<int64_t>(d.ldb) * 8);
+    const TK_GLOBAL double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a + tile.m0 + a_m0;
+    const TK_GLOBAL double* B =
+        buf_ptr<const double>(args.ptrs, d.b_buf) + d.b + static_cast<int64_t>(tile.n0 + b_c0) * d.ldb;
+    a_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const double*)A)));
+    b_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const double*)B)));
+    a_recs = static_cast<uint32_t>(uni(max(0, min(64, d.M - tile.m0 - a_m0)) * 8));
+    b_off = static_cast<uint32_t>((static_cast<int64_t>(b_cl) * d.ldb + b_k) * 8);
+#pragma unroll
+    for (int i = 0; i < B_LDK; ++i) b_nok[i] = tile.n0 + b_c0 + B_NPL * i + b_cl < d.N;
+  };
+  double ra[PF][A_LD], rb[PF][B_LDK];
+  // loads the load cursor's stage into ring slot `slot` and advances it
+  auto gload_next = [&](int slot) {
+    const int k0 = l_k0 + l_s * BK;
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) {
+      const int k = k0 + a_k + A_TPM * i;
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(a_base + k * lda8), 0, k < l_kend ? a_recs : 0u, kBufWord3);
+      ra[slot][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, 0, 0));
+    }
+    const bool k_ok = k0 + b_k < l_kend;
+#pragma unroll
+    for (int i = 0; i < B_LDK; ++i) {
+      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<char*>(b_base + B_NPL * i * ldb8 + int64_t(k0) * 8), 0, 0x7fffffff, kBufWord3);
+      rb[slot][i] = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(r, (k_ok && b_nok[i]) ? b_off : 0x80000000u, 0, 0));
+    }
+    if (++l_s == l_ns) load_tile(l_t + 1);
+  };
+  auto lstore = [&](int slot, int buf) {
+#pragma unroll
+    for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[slot][i];
+#pragma unroll
+    for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[slot][i];
+  };
+
+  d4_t acc[TM][TN];
+  auto compute = [&](int cur) {
+#pragma unroll
+    for (int j = 0; j < BK / 4; ++j) {
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
+#pragma unroll
+      for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][(BK / 4) * g + j];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ni], af[mi], acc[mi][ni], 0, 0, 0);
+    }
+  };
+
+  // multiply cursor: tile ct, its first stage number in the stream, its
+  // true stage count, and whether this wave's sub-tile has any valid entry
+  // (a wave whose whole sub-tile lies past M or N skips its MFMAs; see
+  // wave_origin for why that shortens edge tiles)
+  int ct = t_begin, cbase = 0, cnst = 0;
+  bool active = false;
+  auto compute_tile = [&](int t) {
+    const GemmTile tile = tiles[t];
+    const GemmDesc d = descs[tile.gemm];
+    cnst = max(1, (tile.k1 - tile.k0 + BK - 1) / BK);
+    active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+  };
+  compute_tile(ct);
 
-    double ra[A_LD], rb[B_LDK];
-    const int am = tile.m0 + a_m;
-    const bool a_ok = am < d.M;
-    const TK_GLOBAL double* Arow = A + am;
-    const int kend = tile.k1;
-    auto gload = [&](int k0) {
+  load_tile(t_begin);
 #pragma unroll
-      for (int i = 0; i < A_LD; ++i) {
-        const int k = k0 + a_k + A_TPM * i;
-        ra[i] = (a_ok && k < kend) ? Arow[static_cast<int64_t>(k) * d.lda] : 0.0;
-      }
+  for (int p = 0; p < PF; ++p) gload_next(p);
+  lstore(0, 0);
+  gload_next(0);
+  // stream stage G lives in ring slot G % PF and in LDS buffer G % 2
+  for (int G0 = 0; G0 < total; G0 += PF) {
 #pragma unroll
-      for (int i = 0; i < B_LDK; ++i) {
-        const int n = tile.n0 + b_n + B_NPL * i;
-        const int k = k0 + b_k;
-        rb[i] = (n < d.N && k < kend) ? B[static_cast<int64_t>(n) * d.ldb + k] : 0.0;
-      }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
-#pragma unroll
-      for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[i];
-    };
-    // a wave whose whole sub-tile lies past M or N skips its MFMAs (uniform
-    // per wave); see wave_origin for why that shortens edge tiles
-    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
-    auto compute = [&](int cur) {
-      if (!active) return;
-#pragma unroll
-      for (int j = 0; j < BK / 4; ++j) {
-        double af[TM], bf[TN];
-#pragma unroll
-        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
-#pragma unroll
-        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][(BK / 4) * g + j];
+    for (int u = 0; u < PF; ++u) {
+      const int G = G0 + u;
+      __syncthreads();
+      lstore((u + 1) % PF, (G + 1) & 1);
+      gload_next((u + 1) % PF);
+      if (active && G - cbase < cnst) compute(G & 1);
+    }
+    if (G0 + PF - cbase >= cnst) {
+      // tile ct is complete: epilogue, then move the multiply cursor on.
+      // The MFMAs take B as their first operand, so each 16x16 accumulator
+      // holds the transposed tile: value v of lane l is C[row l % 16][col
+      // l / 16 + 4v] (the fp64 MFMA places value v of lane l at row
+      // l/16 + 4v, column l % 16 of its result; measured with a lane-layout
+      // probe on gfx950).  One store instruction then writes 16 consecutive
+      // rows of 4 columns.
+      const GemmTile tile = tiles[ct];
+      const GemmDesc d = descs[tile.gemm];
+      if (tile.nsplit > 1) {
+        // partial tile of one K split: stored lane-major for the reduce kernel
+        double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
           for (int ni = 0; ni < TN; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + g + 4 * v < d.N)
+                mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
+      } else {
+        store_tile_t<TM, TN>(args, d, buf_ptr<double>(args.ptrs, d.c_buf), tile.m0 + wm + l16, tile.n0 + wn + g,
+                             acc);
       }
-    };
-
-    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
-    gload(tile.k0);
-    lstore(0);
-    if (nst > 1) gload(tile.k0 + BK);
-    int st = 0;
-    // steady state: store stage st+1, fetch stage st+2, multiply stage st
-    for (; st + 2 < nst; ++st) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      gload(tile.k0 + (st + 2) * BK);
-      compute(st & 1);
+      cbase = G0 + PF;
+      if (++ct < t_end) compute_tile(ct);
     }
-    if (st + 1 < nst) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      compute(st & 1);
-      ++st;
-    }
-    __syncthreads();
-    compute(st & 1);
-
-    // D[row][col] of a 16x16 f64 MFMA tile: col = lane % 16 and value v of
-    // the lane is row lane/16 + 4v (rows interleave across the lane groups;
-    // measured with a lane-layout probe on gfx950)
-    if (tile.nsplit > 1) {
-      // partial tile of one K split: stored lane-major for the reduce kernel
-      double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
-#pragma unroll
-      for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (tile.m0 + wm + 16 * mi + g + 4 * v < d.M && tile.n0 + wn + 16 * ni + l16 < d.N)
-              mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
-    } else {
-      TK_GLOBAL double* C = buf_ptr<double>(args.ptrs, d.c_buf);
-#pragma unroll
-      for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            store_elem<double>(args, d, C, tile.m0 + wm + 16 * mi + g + 4 * v, tile.n0 + wn + 16 * ni + l16,
-                               acc[mi][ni][v]);
-    }
-    __syncthreads();
   }
 }
 
@@ -359,7 +517,8 @@ __global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f64_kernel(GemmArgs arg
 // then the same epilogue as an unsplit tile.  A flat stream over (group,
 // element) pairs: element e of a partial tile is the accumulator value the
 // GEMM thread e % NT held as its value number e / NT.
-// LAYOUT 0: fp64 MFMA rows (lane/16 + 4v); 1: fp32 / bf16 MFMA rows (4*(lane/16) + v).
+// LAYOUT 0: fp64 kernel, transposed accumulators (row lane % 16, column
+// lane/16 + 4v); 1: fp32 / bf16 MFMA rows (4*(lane/16) + v), column lane % 16.
 template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
@@ -376,8 +535,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const GemmDesc d = args.descs[tile.gemm];
     int wm, wn;
     wave_origin<TT>(wave, &wm, &wn);
-    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
-    const int c = tile.n0 + wn + 16 * ni + (lane & 15);
+    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 0 ? (lane & 15) : 4 * (lane >> 4) + v);
+    const int c = tile.n0 + wn + 16 * ni + (LAYOUT == 0 ? (lane >> 4) + 4 * v : (lane & 15));
     if (r >= d.M || c >= d.N) continue;
     double sum = 0.0;
     const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
