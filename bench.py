@@ -57,6 +57,33 @@ def parse():
     return ap.parse_args()
 
 
+PROFILE = os.path.join(ROOT, "profiles", "heff_d4096_all_kernels.md")
+PROFILED_SOURCES = ["paper_2508_10076_amd/csrc/tk_kernels.hip", "paper_2508_10076_amd/csrc/tk_host.cpp",
+                    "paper_2508_10076_amd/tuned_tiles.json"]
+
+
+def profiled_traffic():
+    """HBM bytes per GEMM-stage launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the plain-copy
+    calibration), or None when the kernel sources, scheduler or tile table
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = None
+        for line in open(PROFILE):
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+        h = hashlib.sha256()
+        for src in PROFILED_SOURCES:
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                h.update(fh.read())
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("sources_sha256") != h.hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -194,7 +221,10 @@ def bench_heff(args, tk, torch, np):
                    "precision": args.precision, "block_flops_per_step": H.flops, "parallelism": "1 GPU"},
         "pct_fp64_mfma_peak": round(100.0 * r["value"] / PEAK["f64"], 2),
         "roofline": {"bound": "mfma", "achieved": round(r["gemm_tflops"], 4), "peak": PEAK[pk], "unit": "TFLOP/s",
-                     "frac": round(r["gemm_tflops"] / PEAK[pk], 4), "traffic": None,
+                     "frac": round(r["gemm_tflops"] / PEAK[pk], 4),
+                     "traffic": profiled_traffic() if (args.workload == "heff_d4096" and args.precision == "native")
+                     else None,
+                     "traffic_unit": "HBM bytes per launch",
                      "kernel": "grouped sector GEMM of the two MFMA-bound contractions (incl. split-K reduce)",
                      "avg_launch_us": round(r["gemm_avg_us"], 2)},
         "tiles": {f"step{i + 1}": list(H.plans[i][0].info()["tile"]) for i in H.mfma},
