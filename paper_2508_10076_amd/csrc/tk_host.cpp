@@ -439,7 +439,14 @@ struct TaskListT {
 };
 
 using TaskList = TaskListT<PermTask>;
-using SmallKList = TaskListT<tk::SmallKTask>;
+
+// Small-K tasks of one K value (one workgroup each).
+struct SmallKSet {
+  std::vector<tk::SmallKTask> tasks;
+  DevBuf d_tasks;
+  int n() const { return static_cast<int>(tasks.size()); }
+  void upload() { d_tasks.upload(tasks); }
+};
 
 int32_t checked_i32(int64_t v, const char* what) {
   if (v > INT32_MAX || v < INT32_MIN) fail(TK_ERR_UNSUPPORTED, std::string(what) + " exceeds 32 bits");
@@ -493,48 +500,11 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
 
 // Sector GEMMs with K at most this run as an output-stationary stream.
 constexpr int64_t kSmallK = 8;
+// columns per small-K task
+constexpr int64_t kSkCols = 64;
 
 // Add one output block of a small-K sector GEMM (dims and strides in output
 // leg order) as chunked tasks, merging dims contiguous in r, s and dst.
-void add_smallk_tasks(SmallKList& tl, const tk::SmallKTask& proto, int n, const int64_t* dim, const int64_t* rs,
-                      const int64_t* cs, const int64_t* ds) {
-  int64_t D[tk::kMaxDims], R[tk::kMaxDims], S[tk::kMaxDims], T[tk::kMaxDims];
-  int m = 0;
-  for (int i = 0; i < n; ++i) {
-    if (dim[i] == 1) continue;
-    if (m > 0 && rs[i] == R[m - 1] * D[m - 1] && cs[i] == S[m - 1] * D[m - 1] && ds[i] == T[m - 1] * D[m - 1]) {
-      D[m - 1] *= dim[i];
-      continue;
-    }
-    D[m] = dim[i];
-    R[m] = rs[i];
-    S[m] = cs[i];
-    T[m] = ds[i];
-    ++m;
-  }
-  if (m == 0) {
-    D[0] = 1;
-    R[0] = S[0] = T[0] = 0;
-    m = 1;
-  }
-  int64_t total = 1;
-  for (int i = 0; i < m; ++i) total *= D[i];
-  if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
-  tk::SmallKTask t = proto;
-  t.n = m;
-  for (int i = 0; i < tk::kMaxDims; ++i) {
-    t.dim[i] = i < m ? checked_i32(D[i], "dim") : 1;
-    t.rs[i] = i < m ? checked_i32(R[i], "stride") : 0;
-    t.cs[i] = i < m ? checked_i32(S[i], "stride") : 0;
-    t.ds[i] = i < m ? checked_i32(T[i], "stride") : 0;
-  }
-  for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
-    t.start = static_cast<int32_t>(s0);
-    t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
-    tl.tasks.push_back(t);
-  }
-}
-
 // Pack consecutive tasks into workgroups of about kPermChunk elements.
 template <typename TL>
 void pack_workgroups(TL& tl) {
@@ -710,7 +680,10 @@ struct tk_plan {
   double makespan = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
-  SmallKList smallk[9];  // indexed by K
+  SmallKSet smallk[9];  // indexed by K
+  std::vector<tk::SkChan> skchans;  // row / column channels of the small-K sectors
+  std::vector<PairDesc> skpairs;    // output placement of their channel pairs
+  DevBuf d_skchans, d_skpairs;
   std::vector<int64_t> mnk;  // (M, N, K) of every sector GEMM with K > 0, MFMA or streamed
   DevBuf wsA, wsB, wsC;
   double flops = 0;
@@ -722,7 +695,10 @@ struct tk_batch {
   int n = 0, dtype = 0, precision = 0;
   double alpha = 1.0, beta = 0.0;
   TaskList pre, zero, postp;
-  SmallKList smallk[9];
+  SmallKSet smallk[9];
+  std::vector<tk::SkChan> skchans;
+  std::vector<PairDesc> skpairs;
+  DevBuf d_skchans, d_skpairs;
   int32_t ngroups = 0, nslots = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
@@ -1044,51 +1020,90 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       P->flops += 2.0 * double(M) * double(N) * double(K);
       P->mnk.insert(P->mnk.end(), {M, N, K});
       if (K <= kSmallK) {
-        // output-stationary stream over the output blocks of this sector
-        for (int32_t j = 0; j < cg.n(); ++j)
-          for (int32_t i = 0; i < rg.n(); ++i) {
-            std::copy(rg.idx.begin() + size_t(i) * Ct.N1(), rg.idx.begin() + size_t(i + 1) * Ct.N1(), tup.begin());
-            std::copy(cg.idx.begin() + size_t(j) * Ct.N2(), cg.idx.begin() + size_t(j + 1) * Ct.N2(),
-                      tup.begin() + Ct.N1());
-            int64_t cdim[TK_MAX_RANK], crs[TK_MAX_RANK], ccs[TK_MAX_RANK];
-            int64_t acc = 1;
-            for (int l = 0; l < Ct.N1(); ++l) {
-              cdim[l] = Ct.cod[l].deg[tup[l]];
-              crs[l] = acc;
-              ccs[l] = 0;
-              acc *= cdim[l];
+        // row-stationary stream (one thread per row of A~, all columns):
+        // channel tables, the output placement of every channel pair, and
+        // tasks of up to 256 rows x kSkCols columns.  Outputs go straight
+        // to C (identity or fused permute) or, when the output permute runs
+        // afterwards, to C~ in its own layout.
+        // with the fused scatter (at most 4 legs per side) a channel is
+        // decomposed into its legs; in C~'s own layout the position inside
+        // a channel is the channel-local index itself (one merged leg)
+        const int nrleg = P->scatter ? Ct.N1() : 1, ncleg = P->scatter ? Ct.N2() : 1;
+        const int32_t rbase = checked_i32(static_cast<int64_t>(P->skchans.size()), "channel table");
+        for (int32_t i = 0; i < rg.n(); ++i) {
+          tk::SkChan c{};
+          c.off = checked_i32(rg.off[i], "row");
+          c.count = checked_i32(rg.size[i], "row");
+          for (int l = 0; l < 4; ++l)
+            c.dim[l] = !P->scatter ? (l == 0 ? c.count : 1)
+                       : l < Ct.N1() ? checked_i32(Ct.cod[l].deg[rg.idx[size_t(i) * Ct.N1() + l]], "dim")
+                                     : 1;
+          P->skchans.push_back(c);
+        }
+        const int32_t cbase = checked_i32(static_cast<int64_t>(P->skchans.size()), "channel table");
+        for (int32_t j = 0; j < cg.n(); ++j) {
+          tk::SkChan c{};
+          c.off = checked_i32(cg.off[j], "column");
+          c.count = checked_i32(cg.size[j], "column");
+          for (int l = 0; l < 4; ++l)
+            c.dim[l] = !P->scatter ? (l == 0 ? c.count : 1)
+                       : l < Ct.N2() ? checked_i32(Ct.dom[l].deg[cg.idx[size_t(j) * Ct.N2() + l]], "dim")
+                                     : 1;
+          P->skchans.push_back(c);
+        }
+        const int32_t pbase = checked_i32(static_cast<int64_t>(P->skpairs.size()), "pair table");
+        int64_t cbase_elem = 0;
+        if (idC) cbase_elem = sC.soff[sC.sector_of_key(key)];
+        else if (P->post) cbase_elem = Ct.soff[s];
+        for (int32_t i = 0; i < rg.n(); ++i)
+          for (int32_t j = 0; j < cg.n(); ++j) {
+            PairDesc pd{};
+            pd.sign = 1.0f;
+            if (P->scatter) {
+              std::copy(rg.idx.begin() + size_t(i) * Ct.N1(), rg.idx.begin() + size_t(i + 1) * Ct.N1(), tup.begin());
+              std::copy(cg.idx.begin() + size_t(j) * Ct.N2(), cg.idx.begin() + size_t(j + 1) * Ct.N2(),
+                        tup.begin() + Ct.N1());
+              for (int n = 0; n < Ct.N(); ++n) otup[n] = tup[src[n]];
+              const BlockLoc bl = locate(sC, otup.data());
+              if (bl.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
+              block_strides(sC, otup.data(), bl.R, odim, ostr);
+              pd.base = bl.offset;
+              if (sA.si.fermionic && channel_parity(Ct, tup.data(), outpairs)) pd.sign = -1.0f;
+              for (int l = 0; l < Ct.N1(); ++l) pd.S[l] = checked_i32(ostr[pos[l]], "stride");
+              for (int l = 0; l < Ct.N2(); ++l) pd.S[4 + l] = checked_i32(ostr[pos[Ct.N1() + l]], "stride");
+            } else {
+              // C~ layout: column-major M x N sector, channels in order
+              pd.base = cbase_elem + rg.off[i] + cg.off[j] * M;
+              pd.S[0] = 1;
+              pd.S[4] = checked_i32(M, "stride");
             }
-            acc = 1;
-            for (int l = Ct.N1(); l < Ct.N(); ++l) {
-              cdim[l] = Ct.leg(l).deg[tup[l]];
-              ccs[l] = acc;
-              crs[l] = 0;
-              acc *= cdim[l];
-            }
-            for (int n = 0; n < Ct.N(); ++n) otup[n] = tup[src[n]];
-            const BlockLoc bl = locate(sC, otup.data());
-            if (bl.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
-            block_strides(sC, otup.data(), bl.R, odim, ostr);
-            const int par = (sA.si.fermionic && !idC) ? channel_parity(Ct, tup.data(), outpairs) : 0;
-            tk::SmallKTask t{};
-            t.a = At.soff[sa] + rg.off[i];
-            t.b = Bt.soff[sb] + cg.off[j] * K;
-            t.dst = bl.offset;
-            t.K = static_cast<int32_t>(K);
-            t.lda = d.M;
-            t.ldb = d.K;
-            t.a_buf = abuf;
-            t.b_buf = bbuf;
-            t.dst_buf = tk::kBufC;
-            t.sign = par ? -1.0f : 1.0f;
-            int64_t dd[TK_MAX_RANK], rr[TK_MAX_RANK], cc2[TK_MAX_RANK];
-            for (int n = 0; n < Ct.N(); ++n) {
-              dd[n] = cdim[src[n]];
-              rr[n] = crs[src[n]];
-              cc2[n] = ccs[src[n]];
-            }
-            add_smallk_tasks(P->smallk[K], t, Ct.N(), dd, rr, cc2, ostr);
+            P->skpairs.push_back(pd);
           }
+        const int16_t dbuf = P->post ? tk::kBufCt : tk::kBufC;
+        for (int32_t i = 0; i < rg.n(); ++i)
+          for (int64_t r0 = 0; r0 < rg.size[i]; r0 += tk::kThreads)
+            for (int64_t n0 = 0, j = 0; n0 < N; n0 += kSkCols) {
+              while (cg.off[j] + cg.size[j] <= n0) ++j;
+              tk::SmallKTask t{};
+              t.a = At.soff[sa] + rg.off[i] + r0;
+              t.b = Bt.soff[sb];
+              t.lda = d.M;
+              t.ldb = d.K;
+              t.rows = static_cast<int32_t>(std::min<int64_t>(tk::kThreads, rg.size[i] - r0));
+              t.r0 = static_cast<int32_t>(r0);
+              t.rchan = rbase + i;
+              t.cchan = cbase + static_cast<int32_t>(j);
+              t.c0 = static_cast<int32_t>(n0 - cg.off[j]);
+              t.ncols = static_cast<int32_t>(std::min<int64_t>(kSkCols, N - n0));
+              t.bcol = static_cast<int32_t>(n0);
+              t.pair = pbase + i * cg.n() + static_cast<int32_t>(j);
+              t.nrleg = static_cast<int16_t>(nrleg);
+              t.ncleg = static_cast<int16_t>(ncleg);
+              t.a_buf = abuf;
+              t.b_buf = bbuf;
+              t.dst_buf = dbuf;
+              P->smallk[K].tasks.push_back(t);
+            }
         continue;
       }
       if (idC) {
@@ -1187,7 +1202,6 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     pack_workgroups(P->postp);
   }
 
-  for (auto& l : P->smallk) pack_workgroups(l);
   int tm, tn, tkk;
   choose_default_tile(P->descs, precision, &tm, &tn, &tkk);
   plan_reschedule(*P, tm, tn, tkk, false);  // uploads follow below
@@ -1205,6 +1219,8 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     P->d_colmap.upload(P->col_map);
     P->d_pairs.upload(P->pairs);
     for (auto& l : P->smallk) l.upload();
+    P->d_skchans.upload(P->skchans);
+    P->d_skpairs.upload(P->skpairs);
     Sched sc;
     sc.tiles = P->tiles;
     sc.wg_first = P->wg_first;
@@ -1269,10 +1285,11 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
   }
   if (stages & TK_STAGE_GEMM)
     for (int K = 1; K <= kSmallK; ++K)
-      if (P.smallk[K].nwg() > 0)
+      if (P.smallk[K].n() > 0)
         hip_check(tk::launch_smallk(P.dtype, P.precision, K, static_cast<const tk::SmallKTask*>(P.smallk[K].d_tasks.p),
-                                    static_cast<const int32_t*>(P.smallk[K].d_wg.p), P.smallk[K].nwg(), ptrs, alpha,
-                                    beta, stream),
+                                    P.smallk[K].n(), static_cast<const tk::SkChan*>(P.d_skchans.p),
+                                    static_cast<const PairDesc*>(P.d_skpairs.p), ptrs, P.post ? 1.0 : alpha,
+                                    P.post ? 0.0 : beta, stream),
                   "small-K launch");
   if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
     hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
@@ -1672,7 +1689,7 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
     int64_t skt = 0, skw = 0;
     for (const auto& l : P.smallk) {
       skt += static_cast<int64_t>(l.tasks.size());
-      skw += l.nwg();
+      skw += l.n();
     }
     const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
                            static_cast<int64_t>(P.zero.tasks.size()), P.zero.nwg(), skt, skw,
@@ -1768,15 +1785,16 @@ void merge_tasks(TaskList& dst, const TaskList& src, int member) {
   for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
 }
 
-void merge_smallk(SmallKList& dst, const SmallKList& src, int member) {
-  const int base = static_cast<int>(dst.tasks.size());
+void merge_smallk(SmallKSet& dst, const SmallKSet& src, int member, int32_t chan_base, int32_t pair_base) {
   for (tk::SmallKTask t : src.tasks) {
     t.a_buf = static_cast<int16_t>(t.a_buf + member * tk::kBufsPerPlan);
     t.b_buf = static_cast<int16_t>(t.b_buf + member * tk::kBufsPerPlan);
     t.dst_buf = static_cast<int16_t>(t.dst_buf + member * tk::kBufsPerPlan);
+    t.rchan += chan_base;
+    t.cchan += chan_base;
+    t.pair += pair_base;
     dst.tasks.push_back(t);
   }
-  for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
 }
 
 void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
@@ -1819,10 +1837,10 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
               "split-K reduce launch");
   }
   for (int K = 1; K <= kSmallK; ++K)
-    if (b.smallk[K].nwg() > 0)
+    if (b.smallk[K].n() > 0)
       hip_check(tk::launch_smallk(b.dtype, b.precision, K, static_cast<const tk::SmallKTask*>(b.smallk[K].d_tasks.p),
-                                  static_cast<const int32_t*>(b.smallk[K].d_wg.p), b.smallk[K].nwg(), ptrs, b.alpha,
-                                  b.beta, stream),
+                                  b.smallk[K].n(), static_cast<const tk::SkChan*>(b.d_skchans.p),
+                                  static_cast<const PairDesc*>(b.d_skpairs.p), ptrs, b.alpha, b.beta, stream),
                 "small-K launch");
   if (b.zero.nwg() > 0)
     hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
@@ -1869,7 +1887,10 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       b->ws.push_back(std::move(wb));
       merge_tasks(b->pre, P.pre, i);
       merge_tasks(b->zero, P.zero, i);
-      for (int K = 1; K <= kSmallK; ++K) merge_smallk(b->smallk[K], P.smallk[K], i);
+      const int32_t skc = static_cast<int32_t>(b->skchans.size()), skp = static_cast<int32_t>(b->skpairs.size());
+      for (int K = 1; K <= kSmallK; ++K) merge_smallk(b->smallk[K], P.smallk[K], i, skc, skp);
+      b->skchans.insert(b->skchans.end(), P.skchans.begin(), P.skchans.end());
+      b->skpairs.insert(b->skpairs.end(), P.skpairs.begin(), P.skpairs.end());
       const int32_t rb = static_cast<int32_t>(b->row_map.size()), cb = static_cast<int32_t>(b->col_map.size());
       const int32_t pb = static_cast<int32_t>(b->pairs.size());
       for (GemmDesc d : P.descs) {
@@ -1895,6 +1916,8 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     b->pre.upload();
     b->zero.upload();
     for (auto& l : b->smallk) l.upload();
+    b->d_skchans.upload(b->skchans);
+    b->d_skpairs.upload(b->skpairs);
     b->d_descs.upload(b->descs);
     b->d_rowmap.upload(b->row_map);
     b->d_colmap.upload(b->col_map);

@@ -85,16 +85,29 @@ struct GemmTile {
 // of C (dims/dst strides in C's leg order) whose element i has C~ row
 // r = sum i_d rs[d] and column s = sum i_d cs[d] relative to a and b, and value
 // sign * sum_k A~[a + r + k lda] B~[b + k + s ldb].
+// Rows or columns of one channel of a small-K sector: first index in the
+// sector, count, and the degeneracy of each leg of the channel (the index of
+// a row/column within the channel is colex over these, first leg fastest).
+struct SkChan {
+  int32_t off, count;
+  int32_t dim[4];
+};
+
+// Rows r0 .. r0 + rows - 1 of one row channel of a sector GEMM with K <= 8,
+// against a run of ncols consecutive columns of the sector starting at
+// column bcol (which lies at column c0 of column channel cchan; the run
+// crosses channels in order).  Output element (row, column) goes to
+// pairs[pair + (column channel - cchan)]: base + sum of leg index x stride,
+// times the pair's sign.
 struct SmallKTask {
-  int64_t a, b, dst;
-  int32_t K, lda, ldb, n;
-  int32_t count, start;
+  int64_t a;  // A~ element of the task's first row, column 0
+  int64_t b;  // B~ element of row 0, column 0 of the sector
+  int32_t lda, ldb;
+  int32_t rows, r0;
+  int32_t rchan, cchan, c0, ncols, bcol;
+  int32_t pair;
+  int16_t nrleg, ncleg;
   int16_t a_buf, b_buf, dst_buf, pad_;
-  float sign;
-  int32_t dim[kMaxDims];
-  int32_t rs[kMaxDims];
-  int32_t cs[kMaxDims];
-  int32_t ds[kMaxDims];
 };
 
 // Row (or column) r of a sector of C~: its channel inside the sector and the
@@ -134,9 +147,10 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
                        int nwg, hipStream_t stream);
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
-// Small-K sector GEMM tasks that all share the same K (1..8).
-hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
-                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
+// Small-K sector GEMM tasks that all share the same K (1..8): one
+// workgroup per task.
+hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,
+                         const PairDesc* pairs, const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
 bool gemm_tile_supported(int dtype, int precision, int tile_m, int tile_n, int tile_k);
 // Workgroups of the grouped GEMM a CU holds at once for this configuration
 // (registers and LDS); the persistent grid is this many per CU.

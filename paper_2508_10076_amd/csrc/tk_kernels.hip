@@ -830,82 +830,99 @@ __device__ __forceinline__ double smallk_dot(const double* a, const double* b) {
   }
 }
 
-template <typename T, int MODE, int KK>
-__device__ __forceinline__ void smallk_task(const SmallKTask* __restrict__ tk, const Ptrs& P, double alpha,
-                                            double beta, int lt, int nthr) {
-  const int n = tk->n, count = tk->count;
-  const int lda = tk->lda, ldb = tk->ldb;
-  const uint32_t start = static_cast<uint32_t>(tk->start);
-  const double scale = alpha * static_cast<double>(tk->sign);
-  int32_t dim[kMaxDims], rs[kMaxDims], cs[kMaxDims], ds[kMaxDims];
-#pragma unroll
-  for (int d = 0; d < kMaxDims; ++d) {
-    dim[d] = tk->dim[d];
-    rs[d] = tk->rs[d];
-    cs[d] = tk->cs[d];
-    ds[d] = tk->ds[d];
-  }
-  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk->a_buf) + tk->a;
-  const TK_GLOBAL T* __restrict__ B = buf_ptr<const T>(P, tk->b_buf) + tk->b;
-  TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  constexpr int U = KK <= 2 ? 8 : 4;
-  for (int e0 = 0; e0 < count; e0 += nthr * U) {
-    int64_t r[U], c[U], o[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = min(e0 + u * nthr + lt, count - 1);
-      uint32_t lin = start + static_cast<uint32_t>(e);
-      int64_t rr = 0, cc = 0, oo = 0;
-#pragma unroll
-      for (int d = 0; d < kMaxDims; ++d) {
-        if (d < n) {
-          const uint32_t ext = static_cast<uint32_t>(dim[d]);
-          const uint32_t q = lin / ext;
-          const uint32_t i = lin - q * ext;
-          lin = q;
-          rr += static_cast<int64_t>(i) * rs[d];
-          cc += static_cast<int64_t>(i) * cs[d];
-          oo += static_cast<int64_t>(i) * ds[d];
-        }
-      }
-      r[u] = rr;
-      c[u] = cc * ldb;
-      o[u] = oo;
-    }
-    double av[U][KK], bv[U][KK];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) {
-        av[u][k] = static_cast<double>(A[r[u] + static_cast<int64_t>(k) * lda]);
-        bv[u][k] = static_cast<double>(B[c[u] + k]);
-      }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * nthr + lt;
-      double v = scale * smallk_dot<MODE, KK>(av[u], bv[u]);
-      if (beta != 0.0) v += beta * static_cast<double>(D[o[u]]);
-      if (e < count) D[o[u]] = static_cast<T>(v);
-    }
-  }
-}
-
-// Small-K sector GEMMs with K = KK fixed at compile time.  MODE 0: fp64
-// arithmetic (fp64 tensors); 1: fp32 (fp32 tensors, or the fp32 mode);
-// 2: two-term bf16 split of each operand, three products, fp32 accumulation
-// (the compensated mode).  Work distribution as in permute_kernel.
+// Sector GEMMs with K = KK <= 8 fixed at compile time: HBM-bound, no MFMA.
+// One workgroup per task (up to 256 rows of one row channel), one thread per
+// row: the row's KK values of A~ are loaded once (consecutive rows are
+// consecutive in A~, so the loads are coalesced), then the task's columns are
+// walked in order; B~ values, channel tables and pair descriptors are the
+// same for every lane (scalar loads), and each output is written from
+// registers (consecutive rows of a channel land at a stride of the output's
+// row-leg layout, unit stride when its first leg leads the output block).
+// MODE 0: fp64 arithmetic (fp64 tensors); 1: fp32 (fp32 tensors, or the fp32
+// mode); 2: two-term bf16 split of each operand, three products, fp32
+// accumulation (the compensated mode).
 template <typename T, int MODE, int KK>
 __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __restrict__ tasks,
-                                                          const int32_t* __restrict__ wg_first, Ptrs P,
-                                                          double alpha, double beta) {
-  const int t0 = wg_first[blockIdx.x];
-  const int t1 = wg_first[blockIdx.x + 1];
-  if (t1 - t0 == 1) {
-    smallk_task<T, MODE, KK>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
-    return;
+                                                          const SkChan* __restrict__ chans,
+                                                          const PairDesc* __restrict__ pairs, Ptrs P, double alpha,
+                                                          double beta) {
+  const SmallKTask tk = const_ptr(tasks)[blockIdx.x];
+  const TK_CONST SkChan* ch = const_ptr(chans);
+  const TK_CONST PairDesc* pr = const_ptr(pairs);
+  const int t = threadIdx.x;
+  const bool ok = t < tk.rows;
+  const int rr = ok ? t : tk.rows - 1;
+  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk.a_buf) + tk.a + rr;
+  const TK_CONST T* Bc = const_ptr((const T*)(buf_ptr<const T>(P, tk.b_buf) + tk.b));
+  TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk.dst_buf);
+  double a[KK];
+#pragma unroll
+  for (int k = 0; k < KK; ++k) a[k] = static_cast<double>(A[static_cast<int64_t>(k) * tk.lda]);
+  // leg indices of this row inside its channel (colex, first leg fastest)
+  int ri[4] = {0, 0, 0, 0};
+  {
+    const SkChan rc = ch[tk.rchan];
+    int rem = tk.r0 + rr;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      if (l < tk.nrleg) {
+        ri[l] = rem % rc.dim[l];
+        rem /= rc.dim[l];
+      }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = t0 + wave; t < t1; t += kThreads / 64) smallk_task<T, MODE, KK>(tasks + t, P, alpha, beta, lane, 64);
+  int j = tk.cchan, pi = tk.pair;
+  SkChan cc = ch[j];
+  PairDesc pd = pr[pi];
+  int64_t rowpart = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) rowpart += static_cast<int64_t>(ri[l]) * pd.S[l];
+  // column leg indices of the current column (colex counter, first leg
+  // fastest), started at column c0 of channel cchan
+  int ci[4] = {0, 0, 0, 0};
+  {
+    int rem = tk.c0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      if (l < tk.ncleg) {
+        ci[l] = rem % cc.dim[l];
+        rem /= cc.dim[l];
+      }
+  }
+  int c = tk.c0;
+  for (int n = 0; n < tk.ncols; ++n) {
+    if (c == cc.count) {  // next column channel (uniform)
+      ++j;
+      ++pi;
+      c = 0;
+      cc = ch[j];
+      pd = pr[pi];
+      rowpart = 0;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        rowpart += static_cast<int64_t>(ri[l]) * pd.S[l];
+        ci[l] = 0;
+      }
+    }
+    int64_t colpart = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) colpart += static_cast<int64_t>(ci[l]) * pd.S[4 + l];
+    double b[KK];
+    const int64_t bo = static_cast<int64_t>(tk.bcol + n) * tk.ldb;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) b[k] = static_cast<double>(Bc[bo + k]);
+    double v = alpha * static_cast<double>(pd.sign) * smallk_dot<MODE, KK>(a, b);
+    const int64_t x = pd.base + rowpart + colpart;
+    if (ok) {
+      if (beta != 0.0) v += beta * static_cast<double>(D[x]);
+      D[x] = static_cast<T>(v);
+    }
+    ++c;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {  // advance the colex counter
+      if (l < tk.ncleg && ++ci[l] < cc.dim[l]) break;
+      if (l < tk.ncleg) ci[l] = 0;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -924,31 +941,32 @@ hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_fi
 }
 
 template <typename T, int MODE>
-static void launch_smallk_k(int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg, const Ptrs& ptrs,
-                            double alpha, double beta, hipStream_t stream) {
+static void launch_smallk_k(int K, const SmallKTask* tasks, int ntasks, const SkChan* chans, const PairDesc* pairs,
+                            const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
   switch (K) {
-#define TK_SK(KK_)                                                                                            \
-  case KK_:                                                                                                   \
-    hipLaunchKernelGGL((smallk_kernel<T, MODE, KK_>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, \
-                       ptrs, alpha, beta);                                                                    \
+#define TK_SK_CASE(KK_)                                                                                     \
+  case KK_:                                                                                                 \
+    hipLaunchKernelGGL((smallk_kernel<T, MODE, KK_>), dim3(ntasks), dim3(kThreads), 0, stream, tasks, chans, \
+                       pairs, ptrs, alpha, beta);                                                           \
     break;
-    TK_SK(1) TK_SK(2) TK_SK(3) TK_SK(4) TK_SK(5) TK_SK(6) TK_SK(7) TK_SK(8)
-#undef TK_SK
-    default: break;
+    TK_SK_CASE(1) TK_SK_CASE(2) TK_SK_CASE(3) TK_SK_CASE(4) TK_SK_CASE(5) TK_SK_CASE(6) TK_SK_CASE(7) TK_SK_CASE(8)
+#undef TK_SK_CASE
+    default:
+      break;
   }
 }
 
-hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, const int32_t* wg_first, int nwg,
-                         const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
-  if (nwg <= 0) return hipSuccess;
+hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,
+                         const PairDesc* pairs, const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
+  if (ntasks <= 0) return hipSuccess;
   if (K < 1 || K > 8) return hipErrorInvalidValue;
   if (dtype == 0) {
-    if (precision == 0) launch_smallk_k<double, 0>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
-    else if (precision == 1) launch_smallk_k<double, 1>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
-    else launch_smallk_k<double, 2>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+    if (precision == 0) launch_smallk_k<double, 0>(K, tasks, ntasks, chans, pairs, ptrs, alpha, beta, stream);
+    else if (precision == 1) launch_smallk_k<double, 1>(K, tasks, ntasks, chans, pairs, ptrs, alpha, beta, stream);
+    else launch_smallk_k<double, 2>(K, tasks, ntasks, chans, pairs, ptrs, alpha, beta, stream);
   } else {
-    if (precision == 2) launch_smallk_k<float, 2>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
-    else launch_smallk_k<float, 1>(K, tasks, wg_first, nwg, ptrs, alpha, beta, stream);
+    if (precision == 2) launch_smallk_k<float, 2>(K, tasks, ntasks, chans, pairs, ptrs, alpha, beta, stream);
+    else launch_smallk_k<float, 1>(K, tasks, ntasks, chans, pairs, ptrs, alpha, beta, stream);
   }
   return hipGetLastError();
 }

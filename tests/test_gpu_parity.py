@@ -127,6 +127,45 @@ def test_contract_random_integer_bit_exact(ctx, sym):
         assert np.array_equal(download(Cg), ref), (sym, trial)
 
 
+def _wide_case(rng, sym, kdeg):
+    """C~ with five row legs (beyond the fused-scatter limit of four legs per
+    side), so the output permute runs after the sector GEMMs; kdeg bounds the
+    degeneracies of the contracted leg (small: K <= 8 stream; large: MFMA)."""
+    while True:
+        kl = synth.random_space(rng, sym, max_deg=kdeg)
+        if kdeg > 8:  # every sector of the contracted leg longer than the small-K limit
+            kl = synth.space(kl.sectors, [d + 8 for d in kl.degs], kl.dual)
+        tA = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=2) for _ in range(3)],
+                  dom=[synth.random_space(rng, sym, max_deg=2) for _ in range(2)] + [kl])
+        stA = ostruct(tA)
+        if not stA.size:
+            continue
+        pA, qA = (0, 1, 2, 3, 4), (5,)
+        _, Adom = permute_spaces(stA.cod, stA.dom, pA, qA)
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in Adom],
+                  dom=[synth.random_space(rng, sym, max_deg=3)])
+        if not ostruct(tB).size:
+            continue
+        return tA, pA, qA, tB, (0,), (1,), (5, 0, 4), (1, 3, 2)
+
+
+@pytest.mark.parametrize("sym", ["Z2", "U1", "U1xFZ2"])
+@pytest.mark.parametrize("kdeg", [2, 12])
+def test_contract_wide_output_permuted_after(ctx, sym, kdeg):
+    rng = np.random.default_rng(4100 + kdeg + len(sym))
+    for trial in range(4):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _wide_case(rng, sym, kdeg)
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        c0 = int_vec(rng, Cg.nelem)
+        upload(Cg, c0)
+        tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
+        assert np.array_equal(download(Cg), ref), (sym, kdeg, trial)
+
+
 def test_contract_fermionic_against_graph_evaluator(ctx):
     """U(1) x fZ2: the GPU result against the dense graph evaluator (O1)."""
     rng = np.random.default_rng(77)
