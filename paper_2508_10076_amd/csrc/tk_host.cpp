@@ -453,6 +453,19 @@ int32_t checked_i32(int64_t v, const char* what) {
   return static_cast<int32_t>(v);
 }
 
+// Multiply-high form of division by d (1 <= d < 2^31) for dividends below
+// 2^31 (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", 1994): with l = ceil(log2 d) and M = floor(2^(31+l)/d) + 1,
+// floor(x M / 2^(31+l)) = floor(x / d), since the error M - 2^(31+l)/d lies in
+// (0, 1] and so adds less than x / 2^(31+l) < 1/d.  M < 2^32.
+void division_magic(uint32_t d, uint32_t* mag, uint8_t* shr) {
+  int l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  const int k = 31 + l;
+  *mag = static_cast<uint32_t>((uint64_t(1) << k) / d + 1);
+  *shr = static_cast<uint8_t>(k);
+}
+
 // Add one block (dims/strides in output order) as chunked tasks.
 void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int64_t dst, int n, const int64_t* dim,
                      const int64_t* ss, const int64_t* ds, float sign) {
@@ -490,6 +503,7 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
     t.dim[i] = i < m ? checked_i32(D[i], "dim") : 1;
     t.ss[i] = i < m ? checked_i32(S[i], "stride") : 0;
     t.ds[i] = i < m ? checked_i32(T[i], "stride") : 0;
+    division_magic(static_cast<uint32_t>(t.dim[i]), &t.mag[i], &t.shr[i]);
   }
   for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
     t.start = static_cast<int32_t>(s0);

@@ -44,6 +44,10 @@ struct PermTask {
   int32_t dim[kMaxDims];
   int32_t ss[kMaxDims];
   int32_t ds[kMaxDims];
+  // division by dim[d] as a multiply-high: for 0 <= x < 2^31,
+  // x / dim[d] == (x * mag[d]) >> shr[d]
+  uint32_t mag[kMaxDims];
+  uint8_t shr[kMaxDims];
 };
 
 // One sector GEMM  C~^c (M x N) = A~^c (M x K) * B~^c (K x N), all

@@ -56,11 +56,15 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
   const uint32_t start = static_cast<uint32_t>(tk->start);
   const T sign = static_cast<T>(tk->sign);
   int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
+  uint32_t mag[kMaxDims];
+  int shr[kMaxDims];
 #pragma unroll
   for (int d = 0; d < kMaxDims; ++d) {
     dim[d] = tk->dim[d];
     ss[d] = tk->ss[d];
     ds[d] = tk->ds[d];
+    mag[d] = tk->mag[d];
+    shr[d] = tk->shr[d];
   }
   TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
   const bool has_src = tk->src_buf >= 0;
@@ -78,9 +82,9 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
 #pragma unroll
       for (int d = 0; d < kMaxDims; ++d) {
         if (d < n) {
-          const uint32_t ext = static_cast<uint32_t>(dim[d]);
-          const uint32_t q = lin / ext;
-          const uint32_t i = lin - q * ext;
+          // lin < 2^31: division by dim[d] as a multiply-high (host-side magic)
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
+          const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
           lin = q;
           a += static_cast<int64_t>(i) * ss[d];
           b += static_cast<int64_t>(i) * ds[d];
