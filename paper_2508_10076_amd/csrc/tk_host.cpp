@@ -634,6 +634,26 @@ void plan_permute_tasks(const Structure& A, const std::vector<int>& p, const std
   });
 }
 
+// Whether a block with these dims and strides fills one contiguous range
+// (its non-unit dims, ordered by stride, are densely packed from stride 1);
+// *span = number of elements.
+bool contiguous_block(int n, const int64_t* dim, const int64_t* stride, int64_t* span) {
+  std::vector<std::pair<int64_t, int64_t>> ds;  // (stride, dim)
+  int64_t total = 1;
+  for (int i = 0; i < n; ++i) {
+    total *= dim[i];
+    if (dim[i] > 1) ds.push_back({stride[i], dim[i]});
+  }
+  std::sort(ds.begin(), ds.end());
+  int64_t expect = 1;
+  for (const auto& x : ds) {
+    if (x.first != expect) return false;
+    expect *= x.second;
+  }
+  *span = total;
+  return true;
+}
+
 // Zero tasks for the whole storage of a sector range [off, off+count).
 void add_zero_range(TaskList& tl, int16_t dbuf, int64_t off, int64_t count) {
   for (int64_t s0 = 0; s0 < count; s0 += int64_t(1) << 30) {
@@ -1007,6 +1027,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
 
   std::vector<uint8_t> tup(Ct.N()), otup(Ct.N());
   int64_t odim[TK_MAX_RANK], ostr[TK_MAX_RANK];
+  std::vector<std::pair<int64_t, int64_t>> zero_ranges;  // (offset, length) in C
   for (size_t s = 0; s < Ct.keys.size(); ++s) {
     const int64_t key = Ct.keys[s];
     const int sa = At.sector_of_key(key);
@@ -1204,11 +1225,24 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             const BlockLoc b = locate(sC, otup.data());
             if (b.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of C~");
             block_strides(sC, otup.data(), b.R, odim, ostr);
-            int64_t zs[TK_MAX_RANK] = {0};
-            add_block_tasks(P->zero, -1, 0, tk::kBufC, b.offset, sC.N(), odim, zs, ostr, 1.0f);
+            int64_t span = 0;
+            if (contiguous_block(sC.N(), odim, ostr, &span)) {
+              zero_ranges.push_back({b.offset, span});
+            } else {
+              int64_t zs[TK_MAX_RANK] = {0};
+              add_block_tasks(P->zero, -1, 0, tk::kBufC, b.offset, sC.N(), odim, zs, ostr, 1.0f);
+            }
           }
       }
     }
+  }
+  // zero blocks that are contiguous in C: sorted and merged into ranges
+  std::sort(zero_ranges.begin(), zero_ranges.end());
+  for (size_t z = 0; z < zero_ranges.size();) {
+    const int64_t off = zero_ranges[z].first;
+    int64_t end = off + zero_ranges[z].second;
+    for (++z; z < zero_ranges.size() && zero_ranges[z].first == end; ++z) end += zero_ranges[z].second;
+    add_zero_range(P->zero, tk::kBufC, off, end - off);
   }
   pack_workgroups(P->zero);
   if (P->post) {

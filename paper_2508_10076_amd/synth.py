@@ -173,6 +173,11 @@ def small_ints(n: int, config: int, stream: int, lo: int = -3, hi: int = 3) -> n
     return rng(config, 2000 + stream).integers(lo, hi + 1, size=int(n)).astype(np.float64)
 
 
+def signs(n: int, config: int, stream: int) -> np.ndarray:
+    """Random +-1 weights as float64 (for projections of a whole tensor)."""
+    return rng(config, 3000 + stream).integers(0, 2, size=int(n)).astype(np.float64) * 2.0 - 1.0
+
+
 def random_space(g: np.random.Generator, sym: str, max_sect: int = 3, max_deg: int = 3,
                  qrange: int = 2, dual_prob: float = 0.5) -> SpaceSpec:
     """A small random graded space for property tests."""

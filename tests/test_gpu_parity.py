@@ -424,3 +424,74 @@ def test_peps_double_layer_against_graph_evaluator(ctx, pattern):
     # (sign-free) result differs
     Db = np.einsum(sAd.to_dense(vAd), [0, 1, 2, 3, 8], stA.to_dense(a), [8, 4, 5, 6, 7], [0, 4, 1, 5, 2, 6, 3, 7])
     assert not np.array_equal(Db, D) and np.array_equal(np.abs(Db), np.abs(D))
+
+
+# ---------------------------------------------------------------------------
+# config 5 at full size (D = 16): E has 243M stored entries in 4.9M blocks
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def peps_d16(ctx):
+    cfg = synth.config5()
+    tA, call = cfg["tensors"]["A"], cfg["call"]
+    stA = ostruct(tA)
+    a = synth.small_ints(stA.size, 5, 16)
+    A = make(ctx, tA, a)
+    Ad = tk.tensor_adjoint(ctx, A)
+    E = tk.tensor_contract(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"], call["qAB"])
+    e = download(E)
+    del E, Ad, A
+    return cfg, stA, a, e
+
+
+def test_peps_d16_sampled_entries_against_graph_definition(peps_d16):
+    """10^6 stored entries of E drawn uniformly (the structurally zero blocks
+    included) and 2x10^5 uniformly random dense index tuples, each against
+    the graph value of the network at that entry (definition evaluated
+    pointwise, independent of the blockwise path); layout from the oracle's
+    channel enumeration.  Integer data: exact."""
+    from oracle import sampled
+    cfg, stA, a, e = peps_d16
+    call = cfg["call"]
+    sAd, bAd = blockwise.adjoint(stA, stA.to_blocks(a))
+    Ad = sAd.to_dense(sAd.from_blocks(bAd))
+    Ax = stA.to_dense(a)
+    tensors = [(Ad, sAd.cod, sAd.dom), (Ax, stA.cod, stA.dom)]
+    free = [(0, i) for i in call["pA"]] + [(1, j) for j in call["qB"]]
+    out_cod = [free[i] for i in call["pAB"]]
+    pairs = [((0, x), (1, y)) for x, y in zip(call["qA"], call["pB"])]
+    ocod, odom = sampled.graph_output_spaces([(sAd.cod, sAd.dom), (stA.cod, stA.dom)], out_cod, [])
+    assert odom == ()
+    idx, size, off = sampled.codomain_channels("U1xFZ2", ocod)
+    assert int(off[-1] + size[-1]) == e.shape[0] == 243409664
+    rng = np.random.default_rng(51600)
+    pos = rng.integers(0, e.shape[0], size=1_000_000)
+    dense_idx = sampled.positions_to_dense(ocod, idx, size, off, pos)
+    ref = sampled.graph_entries("U1xFZ2", tensors, pairs, out_cod, [], dense_idx)
+    assert np.array_equal(e[pos], ref)
+    assert np.count_nonzero(ref == 0) > 100_000 and np.count_nonzero(ref) > 100_000
+    rnd = np.stack([rng.integers(0, sp.dim, size=200_000) for sp in ocod], axis=1)
+    p2 = sampled.dense_to_positions("U1xFZ2", ocod, idx, size, off, rnd)
+    v2 = sampled.graph_entries("U1xFZ2", tensors, pairs, out_cod, [], rnd)
+    assert np.all(v2[p2 < 0] == 0)                      # outside every stored block: zero
+    assert np.array_equal(e[p2[p2 >= 0]], v2[p2 >= 0])
+
+
+def test_peps_d16_every_block_against_oracle_fingerprint(peps_d16):
+    """Every block of E through projections onto seeded +-1 vectors, against
+    the values the blockwise oracle produced over every block (written by
+    tests/golden/make_peps_d16_fingerprint.py).  Integer data: the entries
+    and the projections are exact integers, so the comparison is exact."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "peps_d16_fingerprint.txt")
+    ref = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            ref[k] = float(v)
+    _, _, _, e = peps_d16
+    assert e.shape[0] == int(ref["size"])
+    assert int(np.count_nonzero(e)) == int(ref["nonzero"])
+    assert float(np.dot(e, e)) == ref["sum_sq"]
+    for k in range(4):
+        w = synth.signs(e.shape[0], 5, k)
+        assert float(np.dot(w, e)) == ref[f"proj{k}"], k

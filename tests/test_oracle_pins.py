@@ -396,3 +396,88 @@ def test_adjoint_inner_product():
     C = stC.to_dense(c)
     tr = np.einsum("ijij->", C)
     assert np.isclose(tr, np.dot(a, a), rtol=1e-13)
+
+
+# ---------------------------------------------------------------------------
+# sampled oracle (full-size checks): layout of codomain-only tensors and the
+# graph value at chosen entries, pinned to the whole-tensor forms
+# ---------------------------------------------------------------------------
+def _codomain_spaces(rng, sym, n):
+    from paper_2508_10076_amd import synth
+    while True:
+        sp = [synth.random_space(rng, sym, max_sect=3, max_deg=3) for _ in range(n)]
+        sp = [Space(s.sectors, s.degs, s.dual) for s in sp]
+        if Structure(sym, sp, ()).size:
+            return sp
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_codomain_channel_layout_matches_structure(sym):
+    from oracle import sampled
+    rng = np.random.default_rng(900 + len(sym))
+    for n in (1, 2, 3, 4, 5):
+        sp = _codomain_spaces(rng, sym, n)
+        st = Structure(sym, sp, ())
+        (u,) = st.sectors
+        rg = st.rows[u]
+        idx, size, off = sampled.codomain_channels(sym, sp)
+        assert np.array_equal(idx, rg.idx) and np.array_equal(size, rg.size) and np.array_equal(off, rg.off)
+        # positions <-> dense indices, against the dense expansion
+        v = np.arange(1, st.size + 1, dtype=np.float64)
+        T = st.to_dense(v)
+        dense_idx = sampled.positions_to_dense(sp, idx, size, off, np.arange(st.size))
+        assert np.array_equal(T[tuple(dense_idx.T)], v)
+        every = np.indices(T.shape).reshape(n, -1).T
+        pos = sampled.dense_to_positions(sym, sp, idx, size, off, every)
+        got = np.where(pos >= 0, v[np.maximum(pos, 0)], 0.0)
+        assert np.array_equal(got, T.reshape(-1))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_graph_entries_match_graph_evaluator(seed):
+    """Entry-wise evaluation equals the whole-tensor graph evaluator on random
+    fermionic contractions (integer data, exact)."""
+    from oracle import sampled
+    from tests.test_abi_host import _plan_case
+    rng = np.random.default_rng(3100 + seed)
+    sym = "U1xFZ2"
+    tA, pA, qA, tB, pB, qB, pAB, qAB = _plan_case(rng, sym)
+    from tests.helpers import ostruct
+    stA, stB = ostruct(tA), ostruct(tB)
+    A = stA.to_dense(int_data(stA.size, rng))
+    B = stB.to_dense(int_data(stB.size, rng))
+    D, dcod, ddom = dense.contract_dense(sym, A, stA.cod, stA.dom, pA, qA, B, stB.cod, stB.dom, pB, qB, pAB, qAB)
+    free = [(0, i) for i in pA] + [(1, j) for j in qB]
+    out_cod, out_dom = [free[i] for i in pAB], [free[i] for i in qAB]
+    pairs = [((0, a), (1, b)) for a, b in zip(qA, pB)]
+    every = np.indices(D.shape).reshape(D.ndim, -1).T if D.ndim else np.zeros((1, 0), np.int64)
+    got = sampled.graph_entries(sym, [(A, stA.cod, stA.dom), (B, stB.cod, stB.dom)], pairs, out_cod, out_dom,
+                                every)
+    assert np.array_equal(got, D.reshape(-1))
+    assert sampled.graph_output_spaces([(stA.cod, stA.dom), (stB.cod, stB.dom)], out_cod, out_dom) == (dcod, ddom)
+
+
+def test_graph_entries_peps_double_layer_small():
+    """The config-5 network at D=6: entry-wise graph value equals the dense
+    graph evaluator everywhere, zeros included."""
+    from oracle import sampled
+    from paper_2508_10076_amd import synth
+    from tests.helpers import ostruct
+    cfg = synth.config5((1, 1, 1))
+    tA, call = cfg["tensors"]["A"], cfg["call"]
+    stA = ostruct(tA)
+    rng = np.random.default_rng(77)
+    a = int_data(stA.size, rng)
+    sAd, bAd = blockwise.adjoint(stA, stA.to_blocks(a))
+    Ad = sAd.to_dense(sAd.from_blocks(bAd))
+    A = stA.to_dense(a)
+    D, dcod, ddom = dense.contract_dense("U1xFZ2", Ad, sAd.cod, sAd.dom, call["pA"], call["qA"], A, stA.cod,
+                                         stA.dom, call["pB"], call["qB"], call["pAB"], call["qAB"])
+    free = [(0, i) for i in call["pA"]] + [(1, j) for j in call["qB"]]
+    out_cod = [free[i] for i in call["pAB"]]
+    pairs = [((0, x), (1, y)) for x, y in zip(call["qA"], call["pB"])]
+    every = np.indices(D.shape).reshape(D.ndim, -1).T
+    got = sampled.graph_entries("U1xFZ2", [(Ad, sAd.cod, sAd.dom), (A, stA.cod, stA.dom)], pairs, out_cod, [],
+                                every)
+    assert np.array_equal(got, D.reshape(-1))
+    assert np.count_nonzero(D) and np.count_nonzero(D == 0)
