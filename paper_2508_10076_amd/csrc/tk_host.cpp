@@ -14,6 +14,7 @@
 #include <numeric>
 #include <queue>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -440,6 +441,56 @@ struct TaskListT {
 
 using TaskList = TaskListT<PermTask>;
 
+// Ranges of elements to zero: collected as (buffer, offset, length), then
+// sorted, merged where adjacent, and laid end to end as one virtual array
+// cut into kZeroChunk-element workgroups.
+struct ZeroSet {
+  std::vector<std::tuple<int32_t, int64_t, int64_t>> raw;
+  std::vector<tk::ZeroRange> ranges;
+  std::vector<int32_t> first;
+  int64_t total = 0;
+  DevBuf d_ranges, d_first;
+  void add(int32_t buf, int64_t off, int64_t len) {
+    if (len > 0) raw.emplace_back(buf, off, len);
+  }
+  void finalize() {
+    std::sort(raw.begin(), raw.end());
+    ranges.clear();
+    total = 0;
+    int64_t end = -1;
+    int32_t cur = -1;
+    for (const auto& r : raw) {
+      const int32_t buf = std::get<0>(r);
+      const int64_t off = std::get<1>(r), len = std::get<2>(r);
+      if (!(buf == cur && off == end)) {
+        tk::ZeroRange z{};
+        z.off = off;
+        z.vstart = total;
+        z.buf = buf;
+        ranges.push_back(z);
+      }
+      cur = buf;
+      end = off + len;
+      total += len;
+    }
+    if (ranges.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many zero ranges");
+    const int64_t nwg = (total + tk::kZeroChunk - 1) / tk::kZeroChunk;
+    if (nwg > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "zero fill too large");
+    first.assign(static_cast<size_t>(nwg) + 1, 0);
+    size_t r = 0;
+    for (int64_t w = 0; w <= nwg; ++w) {
+      const int64_t v = std::min(w * tk::kZeroChunk, std::max<int64_t>(total - 1, 0));
+      while (r + 1 < ranges.size() && ranges[r + 1].vstart <= v) ++r;
+      first[static_cast<size_t>(w)] = static_cast<int32_t>(r);
+    }
+  }
+  int nwg() const { return ranges.empty() ? 0 : static_cast<int>(first.size()) - 1; }
+  void upload() {
+    d_ranges.upload(ranges);
+    d_first.upload(first);
+  }
+};
+
 // Small-K tasks of one K value (one workgroup each).
 struct SmallKSet {
   std::vector<tk::SmallKTask> tasks;
@@ -654,14 +705,6 @@ bool contiguous_block(int n, const int64_t* dim, const int64_t* stride, int64_t*
   return true;
 }
 
-// Zero tasks for the whole storage of a sector range [off, off+count).
-void add_zero_range(TaskList& tl, int16_t dbuf, int64_t off, int64_t count) {
-  for (int64_t s0 = 0; s0 < count; s0 += int64_t(1) << 30) {
-    int64_t c = std::min<int64_t>(int64_t(1) << 30, count - s0);
-    int64_t dim = c, ss = 0, ds = 1;
-    add_block_tasks(tl, -1, 0, dbuf, off + s0, 1, &dim, &ss, &ds, 1.0f);
-  }
-}
 
 }  // namespace
 
@@ -714,6 +757,7 @@ struct tk_plan {
   double makespan = 0;
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
+  ZeroSet zranges;       // zero-fill of empty-K blocks that are contiguous ranges
   SmallKSet smallk[9];  // indexed by K
   std::vector<tk::SkChan> skchans;  // row / column channels of the small-K sectors
   std::vector<PairDesc> skpairs;    // output placement of their channel pairs
@@ -729,6 +773,7 @@ struct tk_batch {
   int n = 0, dtype = 0, precision = 0;
   double alpha = 1.0, beta = 0.0;
   TaskList pre, zero, postp;
+  ZeroSet zranges;
   SmallKSet smallk[9];
   std::vector<tk::SkChan> skchans;
   std::vector<PairDesc> skpairs;
@@ -1027,7 +1072,6 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
 
   std::vector<uint8_t> tup(Ct.N()), otup(Ct.N());
   int64_t odim[TK_MAX_RANK], ostr[TK_MAX_RANK];
-  std::vector<std::pair<int64_t, int64_t>> zero_ranges;  // (offset, length) in C
   for (size_t s = 0; s < Ct.keys.size(); ++s) {
     const int64_t key = Ct.keys[s];
     const int sa = At.sector_of_key(key);
@@ -1212,9 +1256,9 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       ++P->nzero;
       if (idC) {
         const int sc = sC.sector_of_key(key);
-        add_zero_range(P->zero, tk::kBufC, sC.soff[sc], M * N);
+        P->zranges.add(tk::kBufC, sC.soff[sc], M * N);
       } else if (P->post) {
-        add_zero_range(P->zero, tk::kBufCt, Ct.soff[s], M * N);
+        P->zranges.add(tk::kBufCt, Ct.soff[s], M * N);
       } else {
         for (int32_t j = 0; j < cg.n(); ++j)
           for (int32_t i = 0; i < rg.n(); ++i) {
@@ -1227,7 +1271,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             block_strides(sC, otup.data(), b.R, odim, ostr);
             int64_t span = 0;
             if (contiguous_block(sC.N(), odim, ostr, &span)) {
-              zero_ranges.push_back({b.offset, span});
+              P->zranges.add(tk::kBufC, b.offset, span);
             } else {
               int64_t zs[TK_MAX_RANK] = {0};
               add_block_tasks(P->zero, -1, 0, tk::kBufC, b.offset, sC.N(), odim, zs, ostr, 1.0f);
@@ -1236,14 +1280,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       }
     }
   }
-  // zero blocks that are contiguous in C: sorted and merged into ranges
-  std::sort(zero_ranges.begin(), zero_ranges.end());
-  for (size_t z = 0; z < zero_ranges.size();) {
-    const int64_t off = zero_ranges[z].first;
-    int64_t end = off + zero_ranges[z].second;
-    for (++z; z < zero_ranges.size() && zero_ranges[z].first == end; ++z) end += zero_ranges[z].second;
-    add_zero_range(P->zero, tk::kBufC, off, end - off);
-  }
+  P->zranges.finalize();
   pack_workgroups(P->zero);
   if (P->post) {
     plan_permute_tasks(Ct, pAB, qAB, sC, tk::kBufCt, tk::kBufC, false, P->postp);
@@ -1261,6 +1298,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     if (P->post) P->wsC.alloc(Ct.size * es);
     P->pre.upload();
     P->zero.upload();
+    P->zranges.upload();
     P->postp.upload();
     P->d_descs.upload(P->descs);
     P->d_rowmap.upload(P->row_map);
@@ -1339,6 +1377,12 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                     static_cast<const PairDesc*>(P.d_skpairs.p), ptrs, P.post ? 1.0 : alpha,
                                     P.post ? 0.0 : beta, stream),
                   "small-K launch");
+  if ((stages & TK_STAGE_ZERO) && P.zranges.nwg() > 0)
+    hip_check(tk::launch_zero_ranges(P.dtype, static_cast<const tk::ZeroRange*>(P.zranges.d_ranges.p),
+                                     static_cast<int>(P.zranges.ranges.size()),
+                                     static_cast<const int32_t*>(P.zranges.d_first.p), P.zranges.nwg(),
+                                     P.zranges.total, ptrs, P.post ? 0.0 : beta, stream),
+              "zero-range launch");
   if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
     hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
                                  static_cast<const int32_t*>(P.zero.d_wg.p), P.zero.nwg(), ptrs, P.post ? 1.0 : alpha,
@@ -1740,7 +1784,8 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
       skw += l.n();
     }
     const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
-                           static_cast<int64_t>(P.zero.tasks.size()), P.zero.nwg(), skt, skw,
+                           static_cast<int64_t>(P.zero.tasks.size() + P.zranges.ranges.size()),
+                           P.zero.nwg() + P.zranges.nwg(), skt, skw,
                            static_cast<int64_t>(P.descs.size()), static_cast<int64_t>(P.tiles.size()),
                            static_cast<int64_t>(P.wg_first.size()) - 1, P.ngroups, P.nslots,
                            static_cast<int64_t>(P.makespan + 0.5)};
@@ -1890,6 +1935,12 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                   b.smallk[K].n(), static_cast<const tk::SkChan*>(b.d_skchans.p),
                                   static_cast<const PairDesc*>(b.d_skpairs.p), ptrs, b.alpha, b.beta, stream),
                 "small-K launch");
+  if (b.zranges.nwg() > 0)
+    hip_check(tk::launch_zero_ranges(b.dtype, static_cast<const tk::ZeroRange*>(b.zranges.d_ranges.p),
+                                     static_cast<int>(b.zranges.ranges.size()),
+                                     static_cast<const int32_t*>(b.zranges.d_first.p), b.zranges.nwg(),
+                                     b.zranges.total, ptrs, b.beta, stream),
+              "zero-range launch");
   if (b.zero.nwg() > 0)
     hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
                                  static_cast<const int32_t*>(b.zero.d_wg.p), b.zero.nwg(), ptrs, b.alpha, b.beta,
@@ -1935,6 +1986,8 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       b->ws.push_back(std::move(wb));
       merge_tasks(b->pre, P.pre, i);
       merge_tasks(b->zero, P.zero, i);
+      for (const auto& r : P.zranges.raw)
+        b->zranges.add(std::get<0>(r) + i * tk::kBufsPerPlan, std::get<1>(r), std::get<2>(r));
       const int32_t skc = static_cast<int32_t>(b->skchans.size()), skp = static_cast<int32_t>(b->skpairs.size());
       for (int K = 1; K <= kSmallK; ++K) merge_smallk(b->smallk[K], P.smallk[K], i, skc, skp);
       b->skchans.insert(b->skchans.end(), P.skchans.begin(), P.skchans.end());
@@ -1961,8 +2014,10 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     int tm, tn, tkk;
     choose_default_tile(b->descs, b->precision, &tm, &tn, &tkk);
     batch_schedule(*b, tm, tn, tkk);
+    b->zranges.finalize();
     b->pre.upload();
     b->zero.upload();
+    b->zranges.upload();
     for (auto& l : b->smallk) l.upload();
     b->d_skchans.upload(b->skchans);
     b->d_skpairs.upload(b->skpairs);

@@ -89,6 +89,19 @@ struct GemmTile {
 // of C (dims/dst strides in C's leg order) whose element i has C~ row
 // r = sum i_d rs[d] and column s = sum i_d cs[d] relative to a and b, and value
 // sign * sum_k A~[a + r + k lda] B~[b + k + s ldb].
+// One range of elements to zero (scaled by beta when beta != 0): elements
+// off .. off + len - 1 of buffer `buf`, where len = next range's vstart -
+// vstart.  The ranges of a launch are concatenated into one virtual array;
+// vstart is where this range starts in it.
+struct ZeroRange {
+  int64_t off;
+  int64_t vstart;
+  int32_t buf;
+  int32_t pad_;
+};
+// virtual elements per workgroup of the zero-range kernel
+constexpr int kZeroChunk = 2048;
+
 // Rows or columns of one channel of a small-K sector: first index in the
 // sector, count, and the degeneracy of each leg of the channel (the index of
 // a row/column within the channel is colex over these, first leg fastest).
@@ -151,6 +164,10 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
                        int nwg, hipStream_t stream);
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
+// Zero (or beta-scale) the ranges: one workgroup per kZeroChunk virtual
+// elements; first[w] = the range holding virtual element w * kZeroChunk.
+hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first, int nwg,
+                              int64_t total, const Ptrs& ptrs, double beta, hipStream_t stream);
 // Small-K sector GEMM tasks that all share the same K (1..8): one
 // workgroup per task.
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

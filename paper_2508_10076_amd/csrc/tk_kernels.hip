@@ -135,6 +135,52 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
   for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T>(tasks + t, P, alpha, beta, lane, 64);
 }
 
+// Buffer id -> base address with a per-lane id (a select chain over the
+// plan's buffers, or the batch's table).
+template <typename T>
+__device__ __forceinline__ TK_GLOBAL T* buf_ptr_lane(const Ptrs& P, int id) {
+  if (P.table) return (TK_GLOBAL T*)reinterpret_cast<void*>(P.table[id]);
+  void* p = P.p[0];
+#pragma unroll
+  for (int i = 1; i < kBufsPerPlan; ++i) p = id == i ? P.p[i] : p;
+  return (TK_GLOBAL T*)p;
+}
+
+// Zero ranges: workgroup w covers virtual elements [w C, (w+1) C) of the
+// concatenated ranges (C = kZeroChunk).  Its ranges (at most C + 1) are
+// staged in LDS as (virtual start, destination pointer minus virtual
+// start); each element finds its range by binary search there, so
+// consecutive threads write consecutive addresses however short the
+// ranges are.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void zero_ranges_kernel(const ZeroRange* __restrict__ ranges, int nranges,
+                                                               const int32_t* __restrict__ first, int64_t total,
+                                                               Ptrs P, double beta) {
+  __shared__ int64_t s_v[kZeroChunk + 2];
+  __shared__ TK_GLOBAL T* s_p[kZeroChunk + 2];
+  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kZeroChunk;
+  const int64_t c1 = min(total, c0 + kZeroChunk);
+  const int r0 = const_ptr(first)[blockIdx.x];
+  const int r1 = min(nranges, const_ptr(first)[blockIdx.x + 1] + 1);
+  const int nr = r1 - r0;
+  for (int i = threadIdx.x; i < nr; i += kThreads) {
+    const ZeroRange zr = ranges[r0 + i];
+    s_v[i] = zr.vstart;
+    s_p[i] = buf_ptr_lane<T>(P, zr.buf) + (zr.off - zr.vstart);
+  }
+  __syncthreads();
+  for (int64_t v = c0 + threadIdx.x; v < c1; v += kThreads) {
+    int lo = 0, hi = nr - 1;  // largest i with s_v[i] <= v
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_v[mid] <= v) lo = mid;
+      else hi = mid - 1;
+    }
+    TK_GLOBAL T* d = s_p[lo] + v;
+    *d = beta != 0.0 ? static_cast<T>(beta) * *d : static_cast<T>(0);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // grouped sector GEMM, fp64 MFMA
 // ---------------------------------------------------------------------------
@@ -932,6 +978,18 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first, int nwg,
+                              int64_t total, const Ptrs& ptrs, double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(zero_ranges_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first, total,
+                       ptrs, beta);
+  else
+    hipLaunchKernelGGL(zero_ranges_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first, total,
+                       ptrs, beta);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
                           const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
