@@ -440,6 +440,7 @@ struct TaskListT {
 };
 
 using TaskList = TaskListT<PermTask>;
+using SkBlockList = TaskListT<tk::SkBlockTask>;
 
 // Ranges of elements to zero: collected as (buffer, offset, length), then
 // sorted, merged where adjacent, and laid end to end as one virtual array
@@ -758,7 +759,8 @@ struct tk_plan {
   DevBuf d_partials, d_groups;
   std::vector<GemmTile> groups;
   ZeroSet zranges;       // zero-fill of empty-K blocks that are contiguous ranges
-  SmallKSet smallk[9];  // indexed by K
+  SmallKSet smallk[9];  // indexed by K: row-stationary small-K tasks
+  SkBlockList skblocks[9];  // indexed by K: output-stationary small-K tasks
   std::vector<tk::SkChan> skchans;  // row / column channels of the small-K sectors
   std::vector<PairDesc> skpairs;    // output placement of their channel pairs
   DevBuf d_skchans, d_skpairs;
@@ -775,6 +777,7 @@ struct tk_batch {
   TaskList pre, zero, postp;
   ZeroSet zranges;
   SmallKSet smallk[9];
+  SkBlockList skblocks[9];
   std::vector<tk::SkChan> skchans;
   std::vector<PairDesc> skpairs;
   DevBuf d_skchans, d_skpairs;
@@ -1113,10 +1116,12 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
           tk::SkChan c{};
           c.off = checked_i32(rg.off[i], "row");
           c.count = checked_i32(rg.size[i], "row");
-          for (int l = 0; l < 4; ++l)
+          for (int l = 0; l < 4; ++l) {
             c.dim[l] = !P->scatter ? (l == 0 ? c.count : 1)
                        : l < Ct.N1() ? checked_i32(Ct.cod[l].deg[rg.idx[size_t(i) * Ct.N1() + l]], "dim")
                                      : 1;
+            division_magic(static_cast<uint32_t>(c.dim[l]), &c.mag[l], &c.shr[l]);
+          }
           P->skchans.push_back(c);
         }
         const int32_t cbase = checked_i32(static_cast<int64_t>(P->skchans.size()), "channel table");
@@ -1124,10 +1129,12 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
           tk::SkChan c{};
           c.off = checked_i32(cg.off[j], "column");
           c.count = checked_i32(cg.size[j], "column");
-          for (int l = 0; l < 4; ++l)
+          for (int l = 0; l < 4; ++l) {
             c.dim[l] = !P->scatter ? (l == 0 ? c.count : 1)
                        : l < Ct.N2() ? checked_i32(Ct.dom[l].deg[cg.idx[size_t(j) * Ct.N2() + l]], "dim")
                                      : 1;
+            division_magic(static_cast<uint32_t>(c.dim[l]), &c.mag[l], &c.shr[l]);
+          }
           P->skchans.push_back(c);
         }
         const int32_t pbase = checked_i32(static_cast<int64_t>(P->skpairs.size()), "pair table");
@@ -1159,6 +1166,46 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             P->skpairs.push_back(pd);
           }
         const int16_t dbuf = P->post ? tk::kBufCt : tk::kBufC;
+        if (N > kSkCols) {
+          // many columns: output-stationary tasks over each output block, in
+          // the output's leg order (A~ and B~ of such a sector are re-read
+          // from cache; the output is written once, in order)
+          uint32_t order = 0;
+          int nout = 0;
+          if (P->scatter) {
+            for (int n = 0; n < Ct.N(); ++n) order |= static_cast<uint32_t>(src[n]) << (4 * n);
+            nout = Ct.N();
+          } else {
+            order = 0u | (1u << 4);
+            nout = 2;
+          }
+          for (int32_t j = 0; j < cg.n(); ++j)
+            for (int32_t i = 0; i < rg.n(); ++i) {
+              const int64_t total = rg.size[i] * cg.size[j];
+              if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
+              for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
+                tk::SkBlockTask t{};
+                t.a = At.soff[sa] + rg.off[i];
+                t.b = Bt.soff[sb] + cg.off[j] * K;
+                t.lda = d.M;
+                t.ldb = d.K;
+                t.rchan = rbase + i;
+                t.cchan = cbase + j;
+                t.pair = pbase + i * cg.n() + j;
+                t.start = static_cast<int32_t>(s0);
+                t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
+                t.order = order;
+                t.nrleg = static_cast<int16_t>(nrleg);
+                t.ncleg = static_cast<int16_t>(ncleg);
+                t.nout = static_cast<int16_t>(nout);
+                t.a_buf = abuf;
+                t.b_buf = bbuf;
+                t.dst_buf = dbuf;
+                P->skblocks[K].tasks.push_back(t);
+              }
+            }
+          continue;
+        }
         for (int32_t i = 0; i < rg.n(); ++i)
           for (int64_t r0 = 0; r0 < rg.size[i]; r0 += tk::kThreads)
             for (int64_t n0 = 0, j = 0; n0 < N; n0 += kSkCols) {
@@ -1282,6 +1329,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
   }
   P->zranges.finalize();
   pack_workgroups(P->zero);
+  for (auto& l : P->skblocks) pack_workgroups(l);
   if (P->post) {
     plan_permute_tasks(Ct, pAB, qAB, sC, tk::kBufCt, tk::kBufC, false, P->postp);
     pack_workgroups(P->postp);
@@ -1305,6 +1353,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     P->d_colmap.upload(P->col_map);
     P->d_pairs.upload(P->pairs);
     for (auto& l : P->smallk) l.upload();
+    for (auto& l : P->skblocks) l.upload();
     P->d_skchans.upload(P->skchans);
     P->d_skpairs.upload(P->skpairs);
     Sched sc;
@@ -1377,6 +1426,16 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                     static_cast<const PairDesc*>(P.d_skpairs.p), ptrs, P.post ? 1.0 : alpha,
                                     P.post ? 0.0 : beta, stream),
                   "small-K launch");
+  if (stages & TK_STAGE_GEMM)
+    for (int K = 1; K <= kSmallK; ++K)
+      if (P.skblocks[K].nwg() > 0)
+        hip_check(tk::launch_smallk_blocks(P.dtype, P.precision, K,
+                                           static_cast<const tk::SkBlockTask*>(P.skblocks[K].d_tasks.p),
+                                           static_cast<const int32_t*>(P.skblocks[K].d_wg.p), P.skblocks[K].nwg(),
+                                           static_cast<const tk::SkChan*>(P.d_skchans.p),
+                                           static_cast<const PairDesc*>(P.d_skpairs.p), ptrs, P.post ? 1.0 : alpha,
+                                           P.post ? 0.0 : beta, stream),
+                  "small-K block launch");
   if ((stages & TK_STAGE_ZERO) && P.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(P.dtype, static_cast<const tk::ZeroRange*>(P.zranges.d_ranges.p),
                                      static_cast<int>(P.zranges.ranges.size()),
@@ -1783,6 +1842,10 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
       skt += static_cast<int64_t>(l.tasks.size());
       skw += l.n();
     }
+    for (const auto& l : P.skblocks) {
+      skt += static_cast<int64_t>(l.tasks.size());
+      skw += l.nwg();
+    }
     const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
                            static_cast<int64_t>(P.zero.tasks.size() + P.zranges.ranges.size()),
                            P.zero.nwg() + P.zranges.nwg(), skt, skw,
@@ -1935,6 +1998,14 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                   b.smallk[K].n(), static_cast<const tk::SkChan*>(b.d_skchans.p),
                                   static_cast<const PairDesc*>(b.d_skpairs.p), ptrs, b.alpha, b.beta, stream),
                 "small-K launch");
+  for (int K = 1; K <= kSmallK; ++K)
+    if (b.skblocks[K].nwg() > 0)
+      hip_check(tk::launch_smallk_blocks(b.dtype, b.precision, K,
+                                         static_cast<const tk::SkBlockTask*>(b.skblocks[K].d_tasks.p),
+                                         static_cast<const int32_t*>(b.skblocks[K].d_wg.p), b.skblocks[K].nwg(),
+                                         static_cast<const tk::SkChan*>(b.d_skchans.p),
+                                         static_cast<const PairDesc*>(b.d_skpairs.p), ptrs, b.alpha, b.beta, stream),
+                "small-K block launch");
   if (b.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(b.dtype, static_cast<const tk::ZeroRange*>(b.zranges.d_ranges.p),
                                      static_cast<int>(b.zranges.ranges.size()),
@@ -1989,7 +2060,21 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       for (const auto& r : P.zranges.raw)
         b->zranges.add(std::get<0>(r) + i * tk::kBufsPerPlan, std::get<1>(r), std::get<2>(r));
       const int32_t skc = static_cast<int32_t>(b->skchans.size()), skp = static_cast<int32_t>(b->skpairs.size());
-      for (int K = 1; K <= kSmallK; ++K) merge_smallk(b->smallk[K], P.smallk[K], i, skc, skp);
+      for (int K = 1; K <= kSmallK; ++K) {
+        merge_smallk(b->smallk[K], P.smallk[K], i, skc, skp);
+        const int base = static_cast<int>(b->skblocks[K].tasks.size());
+        for (tk::SkBlockTask t : P.skblocks[K].tasks) {
+          t.a_buf = static_cast<int16_t>(t.a_buf + i * tk::kBufsPerPlan);
+          t.b_buf = static_cast<int16_t>(t.b_buf + i * tk::kBufsPerPlan);
+          t.dst_buf = static_cast<int16_t>(t.dst_buf + i * tk::kBufsPerPlan);
+          t.rchan += skc;
+          t.cchan += skc;
+          t.pair += skp;
+          b->skblocks[K].tasks.push_back(t);
+        }
+        for (size_t w = 1; w < P.skblocks[K].wg_first.size(); ++w)
+          b->skblocks[K].wg_first.push_back(base + P.skblocks[K].wg_first[w]);
+      }
       b->skchans.insert(b->skchans.end(), P.skchans.begin(), P.skchans.end());
       b->skpairs.insert(b->skpairs.end(), P.skpairs.begin(), P.skpairs.end());
       const int32_t rb = static_cast<int32_t>(b->row_map.size()), cb = static_cast<int32_t>(b->col_map.size());
@@ -2019,6 +2104,7 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     b->zero.upload();
     b->zranges.upload();
     for (auto& l : b->smallk) l.upload();
+    for (auto& l : b->skblocks) l.upload();
     b->d_skchans.upload(b->skchans);
     b->d_skpairs.upload(b->skpairs);
     b->d_descs.upload(b->descs);

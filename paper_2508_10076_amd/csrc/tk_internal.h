@@ -108,6 +108,9 @@ constexpr int kZeroChunk = 2048;
 struct SkChan {
   int32_t off, count;
   int32_t dim[4];
+  // division by dim[l] as a multiply-high (see PermTask)
+  uint32_t mag[4];
+  uint8_t shr[4];
 };
 
 // Rows r0 .. r0 + rows - 1 of one row channel of a sector GEMM with K <= 8,
@@ -164,6 +167,24 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
                        int nwg, hipStream_t stream);
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
+// Elements start .. start + count - 1 of one output block (row channel
+// rchan x column channel cchan) of a small-K sector with many columns,
+// enumerated in the order of the output's legs (colex, first leg fastest):
+// output leg o is leg ((order >> 4o) & 15) of C~ (rows' legs first).  a, b:
+// A~ element of the channel's first row, B~ element of its first column.
+struct SkBlockTask {
+  int64_t a, b;
+  int32_t lda, ldb;
+  int32_t rchan, cchan, pair;
+  int32_t start, count;
+  uint32_t order;
+  int16_t nrleg, ncleg, nout;
+  int16_t a_buf, b_buf, dst_buf;
+};
+hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTask* tasks, const int32_t* wg_first,
+                                int nwg, const SkChan* chans, const PairDesc* pairs, const Ptrs& ptrs, double alpha,
+                                double beta, hipStream_t stream);
+
 // Zero (or beta-scale) the ranges: one workgroup per kZeroChunk virtual
 // elements; first[w] = the range holding virtual element w * kZeroChunk.
 hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first, int nwg,

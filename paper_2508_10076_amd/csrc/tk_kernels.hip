@@ -975,6 +975,118 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
   }
 }
 
+// Small-K sectors with many columns: output-stationary.  Tasks are chunks
+// of one output block, enumerated in the output's own order (so the stores
+// of consecutive lanes are consecutive when the block is contiguous); each
+// element's row inside the row channel and column inside the column channel
+// come from its output leg indices, and its KK values of A~ and B~ (small,
+// read from cache) are combined as in smallk_kernel.  A workgroup with one
+// task spreads it over all its threads, one with several gives each wave its
+// own tasks.
+template <typename T, int MODE, int KK>
+__device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const TK_CONST SkChan* ch,
+                                                  const TK_CONST PairDesc* pr, const Ptrs& P, double alpha,
+                                                  double beta, int lt, int nthr) {
+  const SkChan rc = ch[tk.rchan], cc = ch[tk.cchan];
+  const PairDesc pd = pr[tk.pair];
+  int32_t dim[8], ra[8], cb[8], so[8];
+  uint32_t mag[8];
+  int shr[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    dim[o] = 1;
+    mag[o] = 0;
+    shr[o] = 0;
+    ra[o] = cb[o] = so[o] = 0;
+    if (o < tk.nout) {
+      const int l = (tk.order >> (4 * o)) & 15;
+      int32_t stride = 1;
+      if (l < tk.nrleg) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < l) stride *= rc.dim[q];
+        dim[o] = rc.dim[l & 3];
+        mag[o] = rc.mag[l & 3];
+        shr[o] = rc.shr[l & 3];
+        ra[o] = stride;
+        so[o] = pd.S[l & 3];
+      } else {
+        const int m = l - tk.nrleg;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < m) stride *= cc.dim[q];
+        dim[o] = cc.dim[m & 3];
+        mag[o] = cc.mag[m & 3];
+        shr[o] = cc.shr[m & 3];
+        cb[o] = stride;
+        so[o] = pd.S[4 + (m & 3)];
+      }
+    }
+  }
+  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk.a_buf) + tk.a;
+  const TK_GLOBAL T* __restrict__ B = buf_ptr<const T>(P, tk.b_buf) + tk.b;
+  TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk.dst_buf) + pd.base;
+  const double scale = alpha * static_cast<double>(pd.sign);
+  constexpr int U = 4;
+  for (int e0 = 0; e0 < tk.count; e0 += nthr * U) {
+    int64_t r[U], c[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint32_t lin = static_cast<uint32_t>(tk.start + min(e0 + u * nthr + lt, tk.count - 1));
+      int64_t rr = 0, cc2 = 0, xx = 0;
+#pragma unroll
+      for (int o = 0; o < 8; ++o)
+        if (o < tk.nout) {
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[o]) >> shr[o]);
+          const uint32_t i = lin - q * static_cast<uint32_t>(dim[o]);
+          lin = q;
+          rr += static_cast<int64_t>(i) * ra[o];
+          cc2 += static_cast<int64_t>(i) * cb[o];
+          xx += static_cast<int64_t>(i) * so[o];
+        }
+      r[u] = rr;
+      c[u] = cc2 * tk.ldb;
+      x[u] = xx;
+    }
+    double av[U][KK], bv[U][KK];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        av[u][k] = static_cast<double>(A[r[u] + static_cast<int64_t>(k) * tk.lda]);
+        bv[u][k] = static_cast<double>(B[c[u] + k]);
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * nthr + lt >= tk.count) continue;
+      double v = scale * smallk_dot<MODE, KK>(av[u], bv[u]);
+      if (beta != 0.0) v += beta * static_cast<double>(D[x[u]]);
+      D[x[u]] = static_cast<T>(v);
+    }
+  }
+}
+
+template <typename T, int MODE, int KK>
+__global__ __launch_bounds__(kThreads) void smallk_blocks_kernel(const SkBlockTask* __restrict__ tasks,
+                                                                 const int32_t* __restrict__ wg_first,
+                                                                 const SkChan* __restrict__ chans,
+                                                                 const PairDesc* __restrict__ pairs, Ptrs P,
+                                                                 double alpha, double beta) {
+  const TK_CONST SkChan* ch = const_ptr(chans);
+  const TK_CONST PairDesc* pr = const_ptr(pairs);
+  const int t0 = const_ptr(wg_first)[blockIdx.x], t1 = const_ptr(wg_first)[blockIdx.x + 1];
+  if (t1 - t0 == 1) {
+    const SkBlockTask tk = const_ptr(tasks)[t0];
+    smallk_block_task<T, MODE, KK>(tk, ch, pr, P, alpha, beta, threadIdx.x, kThreads);
+    return;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t = t0 + __builtin_amdgcn_readfirstlane(wave); t < t1; t += kThreads / 64) {
+    const SkBlockTask tk = const_ptr(tasks)[t];
+    smallk_block_task<T, MODE, KK>(tk, ch, pr, P, alpha, beta, lane, 64);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1016,6 +1128,45 @@ static void launch_smallk_k(int K, const SmallKTask* tasks, int ntasks, const Sk
     default:
       break;
   }
+}
+
+template <typename T, int MODE>
+static void launch_smallk_blocks_k(int K, const SkBlockTask* tasks, const int32_t* wg_first, int nwg,
+                                   const SkChan* chans, const PairDesc* pairs, const Ptrs& ptrs, double alpha,
+                                   double beta, hipStream_t stream) {
+  switch (K) {
+#define TK_SKB_CASE(KK_)                                                                                        \
+  case KK_:                                                                                                     \
+    hipLaunchKernelGGL((smallk_blocks_kernel<T, MODE, KK_>), dim3(nwg), dim3(kThreads), 0, stream, tasks,       \
+                       wg_first, chans, pairs, ptrs, alpha, beta);                                              \
+    break;
+    TK_SKB_CASE(1) TK_SKB_CASE(2) TK_SKB_CASE(3) TK_SKB_CASE(4) TK_SKB_CASE(5) TK_SKB_CASE(6) TK_SKB_CASE(7)
+    TK_SKB_CASE(8)
+#undef TK_SKB_CASE
+    default:
+      break;
+  }
+}
+
+hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTask* tasks, const int32_t* wg_first,
+                                int nwg, const SkChan* chans, const PairDesc* pairs, const Ptrs& ptrs, double alpha,
+                                double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (K < 1 || K > 8) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    if (precision == 0)
+      launch_smallk_blocks_k<double, 0>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+    else if (precision == 1)
+      launch_smallk_blocks_k<double, 1>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+    else
+      launch_smallk_blocks_k<double, 2>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+  } else {
+    if (precision == 2)
+      launch_smallk_blocks_k<float, 2>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+    else
+      launch_smallk_blocks_k<float, 1>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

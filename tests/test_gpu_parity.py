@@ -166,6 +166,45 @@ def test_contract_wide_output_permuted_after(ctx, sym, kdeg):
         assert np.array_equal(download(Cg), ref), (sym, kdeg, trial)
 
 
+def _wide_n_case(rng, sym):
+    """Small K (<= 8 per sector) against free legs of B wide enough that the
+    sectors have well over 64 columns (output-stationary small-K path)."""
+    while True:
+        kl = synth.random_space(rng, sym, max_deg=2)
+        tA = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=3) for _ in range(2)], dom=[kl])
+        wide = [synth.random_space(rng, sym, max_sect=3, max_deg=4) for _ in range(2)]
+        wide = [synth.space(w.sectors, [d + 8 for d in w.degs], w.dual) for w in wide]
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(kl.sectors, kl.degs, kl.dual)], dom=wide)
+        if not (ostruct(tA).size and ostruct(tB).size):
+            continue
+        oc = [int(x) for x in rng.permutation(4)]
+        n1 = int(rng.integers(0, 5))
+        return tA, (0, 1), (2,), tB, (0,), (1, 2), oc[:n1], oc[n1:]
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_contract_small_k_many_columns(ctx, sym):
+    rng = np.random.default_rng(4700 + len(sym))
+    seen_wide = 0
+    for trial in range(6):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _wide_n_case(rng, sym)
+        if trial == 0:
+            pAB, qAB = [0, 1], [2, 3]        # identity output layout
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg)
+        g = P.gemms()
+        seen_wide += int(len(g) > 0 and g[:, 1].max() > 64 and g[:, 2].max() <= 8)
+        c0 = int_vec(rng, Cg.nelem)
+        upload(Cg, c0)
+        tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
+        assert np.array_equal(download(Cg), ref), (sym, trial)
+    assert seen_wide >= 3
+
+
 def test_contract_fermionic_against_graph_evaluator(ctx):
     """U(1) x fZ2: the GPU result against the dense graph evaluator (O1)."""
     rng = np.random.default_rng(77)
