@@ -573,16 +573,19 @@ template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
   constexpr int NT = TT::NT, TN = TT::TN;
+  static_assert((BM * BN) % 256 == 0, "a workgroup's elements must lie in one group");
   for (int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; x < total;
        x += static_cast<int64_t>(gridDim.x) * 256) {
-    const int grp = static_cast<int>(x / (BM * BN));
+    // a workgroup's 256 consecutive elements lie in one group (BM * BN is a
+    // multiple of 256), so the group and its tables are uniform: scalar loads
+    const int grp = __builtin_amdgcn_readfirstlane(static_cast<int>(x / (BM * BN)));
     const int e = static_cast<int>(x % (BM * BN));
     const int tid = e % NT, val = e / NT;
     const int v = val & 3, t = val >> 2;
     const int mi = t / TN, ni = t % TN;
     const int lane = tid & 63, wave = tid >> 6;
-    const GemmTile tile = groups[grp];
-    const GemmDesc d = args.descs[tile.gemm];
+    const GemmTile tile = const_ptr(groups)[grp];
+    const GemmDesc d = const_ptr(args.descs)[tile.gemm];
     int wm, wn;
     wave_origin<TT>(wave, &wm, &wn);
     const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 0 ? (lane & 15) : 4 * (lane >> 4) + v);
