@@ -357,6 +357,46 @@ def test_batch_graph_replays(ctx):
             assert np.array_equal(download(Cg), ref), rep
 
 
+def test_heff_chain_graph_replays_match_eager(ctx):
+    """The three contractions of H_eff (D=1024) captured in one HIP graph
+    (plans execute on the capturing stream) and replayed three times, with
+    eager work and synchronizations between the replays: every replay equals
+    the eager result bit-exactly, and the oracle within fp64 tolerance."""
+    cfg = synth.config2()
+    data = heff_data(cfg, 2)
+    s = torch.cuda.Stream()
+    T = {k: make(ctx, cfg["tensors"][k], data[k]) for k in cfg["inputs"]}
+    plans = []
+    for out, a, b, call in cfg["calls"]:
+        T[out] = tk.tensor_create_contracted(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"],
+                                             call["pAB"], call["qAB"])
+        plans.append((tk.Plan(ctx, T[a], call["pA"], call["qA"], T[b], call["pB"], call["qB"], call["pAB"],
+                              call["qAB"], T[out]), T[a], T[b], T[out]))
+
+    def step():
+        for P, A, B, Cc in plans:
+            P.execute(A, B, Cc, stream=s)
+
+    with torch.cuda.stream(s):
+        step()
+    s.synchronize()
+    y_eager = download(T[cfg["output"]])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        step()
+    for rep in range(3):
+        for _, _, _, Cc in plans:          # eager work between replays: garbage in every output
+            fill(Cc)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        s.synchronize()
+        assert np.array_equal(download(T[cfg["output"]]), y_eager), rep
+    _, v = run_heff_oracle(cfg, data)
+    ref = v[cfg["output"]]
+    assert np.linalg.norm(y_eager - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_split_k_tall_k_exact_and_repeatable(ctx):
     """Few tiles with a long K range take the split-K path (partials reduced
     by the last arriving unit); repeated launches must reset its counters."""
