@@ -212,30 +212,65 @@ __device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc&
   Cbase[idx] = static_cast<TC>(v);
 }
 
-// Epilogue of an fp64 tile held transposed: value v of acc[mi][ni] is
-// C[r0 + 16 mi][c0 + 16 ni + 4 v] (r0, c0 already include the lane's row
+// MFMA of one 16x16x4 step for the arithmetic type: accumulator type, the
+// call (first operand = B, so the result is the transposed tile), and where
+// value v of lane l sits: column GS (l/16) + VS v of the transposed tile.
+template <typename CT>
+struct MfmaOf;
+template <>
+struct MfmaOf<double> {
+  using acc = d4_t;
+  static constexpr int gs = 1, vs = 4;
+  static __device__ __forceinline__ d4_t mma(double b, double a, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c, 0, 0, 0);
+  }
+};
+typedef float f4_t __attribute__((ext_vector_type(4)));
+template <>
+struct MfmaOf<float> {
+  using acc = f4_t;
+  static constexpr int gs = 4, vs = 1;
+  static __device__ __forceinline__ f4_t mma(float b, float a, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(b, a, c, 0, 0, 0);
+  }
+};
+
+// One element through a raw buffer resource (reads zero past its records).
+template <typename TS>
+__device__ __forceinline__ TS buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ double buffer_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// Epilogue of a tile held transposed: value v of acc[mi][ni] is
+// C[r0 + 16 mi][c0 + 16 ni + VS v] (r0, c0 already include the lane's row
 // and column).  Scatter outputs (mode 1) look up the row map once per row
 // and the column map once per column; the map and pair tables are read
 // through restrict pointers so their loads may move ahead of the stores.
-template <int TM, int TN>
-__device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL double* __restrict__ C,
-                                             int r0, int c0, const d4_t (&acc)[TM][TN]) {
+template <typename TS, typename AT, int TM, int TN, int VS>
+__device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL TS* __restrict__ C,
+                                             int r0, int c0, const AT (&acc)[TM][TN]) {
   const double alpha = args.alpha, beta = args.beta;
   if (d.mode == 0) {
 #pragma unroll
     for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int c = c0 + 16 * ni + 4 * v;
+        const int c = c0 + 16 * ni + VS * v;
         if (c >= d.N) continue;
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi) {
           const int r = r0 + 16 * mi;
           if (r >= d.M) continue;
           const int64_t x = d.c + static_cast<int64_t>(c) * d.ldc + r;
-          double val = alpha * acc[mi][ni][v];
-          if (beta != 0.0) val += beta * C[x];
-          C[x] = val;
+          double val = alpha * static_cast<double>(acc[mi][ni][v]);
+          if (beta != 0.0) val += beta * static_cast<double>(C[x]);
+          C[x] = static_cast<TS>(val);
         }
       }
     return;
@@ -250,7 +285,7 @@ __device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDes
   for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int c = c0 + 16 * ni + 4 * v;
+      const int c = c0 + 16 * ni + VS * v;
       if (c >= d.N) continue;
       const LegMap cm = cmap[c];
 #pragma unroll
@@ -261,9 +296,9 @@ __device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDes
 #pragma unroll
         for (int l = 0; l < 4; ++l)
           x += static_cast<int64_t>(rm[mi].idx[l]) * pd.S[l] + static_cast<int64_t>(cm.idx[l]) * pd.S[4 + l];
-        double val = alpha * pd.sign * acc[mi][ni][v];
-        if (beta != 0.0) val += beta * C[x];
-        C[x] = val;
+        double val = alpha * pd.sign * static_cast<double>(acc[mi][ni][v]);
+        if (beta != 0.0) val += beta * static_cast<double>(C[x]);
+        C[x] = static_cast<TS>(val);
       }
     }
 }
@@ -295,7 +330,6 @@ struct F64Tile {
   static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
 };
 
-typedef float f4_t __attribute__((ext_vector_type(4)));
 
 // Epilogue of a tile accumulated in fp32 (fp32 16x16 MFMA layout: value v
 // of lane l is row 4*(l/16) + v).  Split tiles store their partial sums
@@ -361,13 +395,19 @@ constexpr int kBufWord3 = 0x00020000;
 template <int BM, int BN, int BK>
 constexpr int kF64WavesPerEu = (BM * BN <= 64 * 64 && BK == 16) ? 4 : 2;
 
-template <int BM, int BN, int WGM, int WGN, int BK_, int PF = TK_F64_PREFETCH>
-__global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void gemm_f64_kernel(GemmArgs args) {
+// TS: element type in HBM (double or float); CT: arithmetic of the MFMAs
+// (double: fp64 16x16x4, or float: fp32 16x16x4 -- operands rounded to fp32
+// as they enter LDS, fp32 accumulation).
+template <typename TS, typename CT, int BM, int BN, int WGM, int WGN, int BK_, int PF = TK_F64_PREFETCH>
+__global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void gemm_stream_kernel(GemmArgs args) {
   using TT = F64Tile<BM, BN, WGM, WGN, BK_>;
+  using AT = typename MfmaOf<CT>::acc;
   constexpr int NT = TT::NT, BK = TT::BK, TM = TT::TM, TN = TT::TN;
   constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD;
-  __shared__ double As[2][BK][BM + TT::APAD];
-  __shared__ double Bs[2][BN][BK + TT::BPAD];
+  constexpr int ES = sizeof(TS);
+  constexpr int GS = MfmaOf<CT>::gs, VS = MfmaOf<CT>::vs;  // column of value v of lane l: GS (l/16) + VS v
+  __shared__ CT As[2][BK][BM + TT::APAD];
+  __shared__ CT Bs[2][BN][BK + TT::BPAD];
 
   const TK_CONST GemmTile* tiles = const_ptr(args.tiles);
   const TK_CONST GemmDesc* descs = const_ptr(args.descs);
@@ -441,19 +481,19 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
     l_ns = uni(padded_stages(t));
     l_k0 = uni(tile.k0);
     l_kend = uni(tile.k1);
-    lda8 = uni64(static_cast<int64_t>(d.lda) * 8);
-    ldb8 = uni64(static_cast<int64_t>(d.ldb) * 8);
-    const TK_GLOBAL double* A = buf_ptr<const double>(args.ptrs, d.a_buf) + d.a + tile.m0 + a_m0;
-    const TK_GLOBAL double* B =
-        buf_ptr<const double>(args.ptrs, d.b_buf) + d.b + static_cast<int64_t>(tile.n0 + b_c0) * d.ldb;
-    a_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const double*)A)));
-    b_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const double*)B)));
-    a_recs = static_cast<uint32_t>(uni(max(0, min(64, d.M - tile.m0 - a_m0)) * 8));
-    b_off = static_cast<uint32_t>((static_cast<int64_t>(b_cl) * d.ldb + b_k) * 8);
+    lda8 = uni64(static_cast<int64_t>(d.lda) * ES);
+    ldb8 = uni64(static_cast<int64_t>(d.ldb) * ES);
+    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a + tile.m0 + a_m0;
+    const TK_GLOBAL TS* B =
+        buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b + static_cast<int64_t>(tile.n0 + b_c0) * d.ldb;
+    a_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)A)));
+    b_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)B)));
+    a_recs = static_cast<uint32_t>(uni(max(0, min(64, d.M - tile.m0 - a_m0)) * ES));
+    b_off = static_cast<uint32_t>((static_cast<int64_t>(b_cl) * d.ldb + b_k) * ES);
 #pragma unroll
     for (int i = 0; i < B_LDK; ++i) b_nok[i] = tile.n0 + b_c0 + B_NPL * i + b_cl < d.N;
   };
-  double ra[PF][A_LD], rb[PF][B_LDK];
+  TS ra[PF][A_LD], rb[PF][B_LDK];
   // loads the load cursor's stage into ring slot `slot` and advances it
   auto gload_next = [&](int slot) {
     const int k0 = l_k0 + l_s * BK;
@@ -462,30 +502,29 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
       const int k = k0 + a_k + A_TPM * i;
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
           const_cast<char*>(a_base + k * lda8), 0, k < l_kend ? a_recs : 0u, kBufWord3);
-      ra[slot][i] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, 0, 0));
+      ra[slot][i] = buffer_load<TS>(r, lane * ES);
     }
     const bool k_ok = k0 + b_k < l_kend;
 #pragma unroll
     for (int i = 0; i < B_LDK; ++i) {
       const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(b_base + B_NPL * i * ldb8 + int64_t(k0) * 8), 0, 0x7fffffff, kBufWord3);
-      rb[slot][i] = __builtin_bit_cast(
-          double, __builtin_amdgcn_raw_buffer_load_b64(r, (k_ok && b_nok[i]) ? b_off : 0x80000000u, 0, 0));
+          const_cast<char*>(b_base + B_NPL * i * ldb8 + int64_t(k0) * ES), 0, 0x7fffffff, kBufWord3);
+      rb[slot][i] = buffer_load<TS>(r, (k_ok && b_nok[i]) ? b_off : 0x80000000u);
     }
     if (++l_s == l_ns) load_tile(l_t + 1);
   };
   auto lstore = [&](int slot, int buf) {
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[slot][i];
+    for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = static_cast<CT>(ra[slot][i]);
 #pragma unroll
-    for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[slot][i];
+    for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = static_cast<CT>(rb[slot][i]);
   };
 
-  d4_t acc[TM][TN];
+  AT acc[TM][TN];
   auto compute = [&](int cur) {
 #pragma unroll
     for (int j = 0; j < BK / 4; ++j) {
-      double af[TM], bf[TN];
+      CT af[TM], bf[TN];
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
 #pragma unroll
@@ -494,7 +533,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
       for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
         for (int ni = 0; ni < TN; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ni], af[mi], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] = MfmaOf<CT>::mma(bf[ni], af[mi], acc[mi][ni]);
     }
   };
 
@@ -512,7 +551,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = d4_t{0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < TN; ++j) acc[i][j] = AT{0, 0, 0, 0};
   };
   compute_tile(ct);
 
@@ -535,10 +574,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
       // tile ct is complete: epilogue, then move the multiply cursor on.
       // The MFMAs take B as their first operand, so each 16x16 accumulator
       // holds the transposed tile: value v of lane l is C[row l % 16][col
-      // l / 16 + 4v] (the fp64 MFMA places value v of lane l at row
-      // l/16 + 4v, column l % 16 of its result; measured with a lane-layout
-      // probe on gfx950).  One store instruction then writes 16 consecutive
-      // rows of 4 columns.
+      // GS (l/16) + VS v] (the fp64 MFMA places value v of lane l at row
+      // l/16 + 4v, column l % 16 of its result, the fp32 one at row
+      // 4 (l/16) + v; measured with a lane-layout probe on gfx950).  One
+      // store instruction then writes 16 consecutive rows of 4 columns.
       const GemmTile tile = tiles[ct];
       const GemmDesc d = descs[tile.gemm];
       if (tile.nsplit > 1) {
@@ -550,11 +589,11 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
           for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + g + 4 * v < d.N)
-                mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
+              if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + GS * g + VS * v < d.N)
+                mine[((mi * TN + ni) * 4 + v) * NT + tid] = static_cast<double>(acc[mi][ni][v]);
       } else {
-        store_tile_t<TM, TN>(args, d, buf_ptr<double>(args.ptrs, d.c_buf), tile.m0 + wm + l16, tile.n0 + wn + g,
-                             acc);
+        store_tile_t<TS, AT, TM, TN, VS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
+                                         tile.n0 + wn + GS * g, acc);
       }
       cbase = G0 + PF;
       if (++ct < t_end) compute_tile(ct);
@@ -567,8 +606,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
 // then the same epilogue as an unsplit tile.  A flat stream over (group,
 // element) pairs: element e of a partial tile is the accumulator value the
 // GEMM thread e % NT held as its value number e / NT.
-// LAYOUT 0: fp64 kernel, transposed accumulators (row lane % 16, column
-// lane/16 + 4v); 1: fp32 / bf16 MFMA rows (4*(lane/16) + v), column lane % 16.
+// LAYOUT 0: fp64 arithmetic, transposed accumulators (row lane % 16,
+// column lane/16 + 4v); 2: fp32 arithmetic, transposed (row lane % 16,
+// column 4 (lane/16) + v); 1: bf16 kernel rows (4*(lane/16) + v), column
+// lane % 16.
 template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
@@ -588,8 +629,9 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const GemmDesc d = const_ptr(args.descs)[tile.gemm];
     int wm, wn;
     wave_origin<TT>(wave, &wm, &wn);
-    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 0 ? (lane & 15) : 4 * (lane >> 4) + v);
-    const int c = tile.n0 + wn + 16 * ni + (LAYOUT == 0 ? (lane >> 4) + 4 * v : (lane & 15));
+    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 1 ? 4 * (lane >> 4) + v : (lane & 15));
+    const int c = tile.n0 + wn + 16 * ni +
+                  (LAYOUT == 0 ? (lane >> 4) + 4 * v : LAYOUT == 2 ? 4 * (lane >> 4) + v : (lane & 15));
     if (r >= d.M || c >= d.N) continue;
     double sum = 0.0;
     const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
@@ -603,101 +645,6 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-// fp32 MFMA 16x16x4: operands rounded to fp32 as they enter LDS (A as [k][m],
-// B as [n][k], as in the fp64 kernel), fp32 accumulation.  Output layout of
-// the fp32 16x16 MFMA: value v of lane l is row 4*(l/16) + v, column l%16.
-template <typename TS, int BM, int BN, int WGM, int WGN, int BK>
-__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_f32_kernel(GemmArgs args) {
-  using TT = F64Tile<BM, BN, WGM, WGN, BK>;
-  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
-  constexpr int A_TPM = TT::A_TPM, A_LD = TT::A_LD;
-  __shared__ float As[2][BK][BM + 4];
-  __shared__ float Bs[2][BN][BK + 4];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int g = lane >> 4, l16 = lane & 15;
-  int wm, wn;
-  wave_origin<TT>(wave, &wm, &wn);
-  const int a_m = tid % BM, a_k = tid / BM;
-  const int b_k = tid % BK, b_n = tid / BK;
-  constexpr int B_NPL = NT / BK;
-  constexpr int B_LDK = BN / B_NPL;
-
-  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
-    const GemmTile tile = args.tiles[ti];
-    const GemmDesc d = args.descs[tile.gemm];
-    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a;
-    const TK_GLOBAL TS* B = buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b;
-    f4_t acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
-    float ra[A_LD], rb[B_LDK];
-    const int am = tile.m0 + a_m;
-    const bool a_ok = am < d.M;
-    const TK_GLOBAL TS* Arow = A + am;
-    const int kend = tile.k1;
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) {
-        const int k = k0 + a_k + A_TPM * i;
-        ra[i] = (a_ok && k < kend) ? static_cast<float>(Arow[static_cast<int64_t>(k) * d.lda]) : 0.f;
-      }
-#pragma unroll
-      for (int i = 0; i < B_LDK; ++i) {
-        const int n = tile.n0 + b_n + B_NPL * i;
-        const int k = k0 + b_k;
-        rb[i] = (n < d.N && k < kend) ? static_cast<float>(B[static_cast<int64_t>(n) * d.ldb + k]) : 0.f;
-      }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int i = 0; i < A_LD; ++i) As[buf][a_k + A_TPM * i][a_m] = ra[i];
-#pragma unroll
-      for (int i = 0; i < B_LDK; ++i) Bs[buf][b_n + B_NPL * i][b_k] = rb[i];
-    };
-    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
-    auto compute = [&](int cur) {
-      if (!active) return;
-#pragma unroll
-      for (int j = 0; j < BK / 4; ++j) {
-        float af[TM], bf[TN];
-#pragma unroll
-        for (int mi = 0; mi < TM; ++mi) af[mi] = As[cur][(BK / 4) * g + j][wm + 16 * mi + l16];
-#pragma unroll
-        for (int ni = 0; ni < TN; ++ni) bf[ni] = Bs[cur][wn + 16 * ni + l16][(BK / 4) * g + j];
-#pragma unroll
-        for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < TN; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
-      }
-    };
-    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
-    gload(tile.k0);
-    lstore(0);
-    if (nst > 1) gload(tile.k0 + BK);
-    int st = 0;
-    for (; st + 2 < nst; ++st) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      gload(tile.k0 + (st + 2) * BK);
-      compute(st & 1);
-    }
-    if (st + 1 < nst) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      compute(st & 1);
-      ++st;
-    }
-    __syncthreads();
-    compute(st & 1);
-    gemm_epilogue_f32<TT, TS>(args, d, tile, acc, tid, wm, wn, g, l16);
-    __syncthreads();
-  }
-}
 
 // Compensated split-BF16x3: every operand value a (rounded to fp32) is split
 // into hi = bf16(a) and lo = bf16(a - hi) as it enters LDS; each 16x16x32
@@ -1228,9 +1175,10 @@ template <typename TS, int BM, int BN, int WM, int WN, int BK>
 static void launch_gemm_kind(int kind, const GemmArgs& args, int nwg, hipStream_t stream) {
   const dim3 grid(nwg), block(64 * WM * WN);
   if (kind == 0) {
-    if constexpr (sizeof(TS) == 8) hipLaunchKernelGGL((gemm_f64_kernel<BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+    if constexpr (sizeof(TS) == 8)
+      hipLaunchKernelGGL((gemm_stream_kernel<double, double, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
   } else if (kind == 1) {
-    hipLaunchKernelGGL((gemm_f32_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+    hipLaunchKernelGGL((gemm_stream_kernel<TS, float, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
   } else {
     if constexpr (BK % 32 == 0)
       hipLaunchKernelGGL((gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
@@ -1261,9 +1209,11 @@ static int blocks_per_cu_kind(int kind) {
   hipError_t e = hipSuccess;
   if (kind == 0) {
     if constexpr (sizeof(TS) == 8)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_f64_kernel<BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_stream_kernel<double, double, BM, BN, WM, WN, BK>,
+                                                       64 * WM * WN, 0);
   } else if (kind == 1) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_f32_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_stream_kernel<TS, float, BM, BN, WM, WN, BK>,
+                                                     64 * WM * WN, 0);
   } else {
     if constexpr (BK % 32 == 0)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
@@ -1293,22 +1243,28 @@ hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n
   if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
   const int64_t total = static_cast<int64_t>(ngroups) * tile_m * tile_n;
   const unsigned nblk = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 65536));
-  const bool f64rows = compute_kind(dtype, precision) == 0;
-#define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                                        \
-  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                                            \
-    if (dtype == 0 && f64rows)                                                                                      \
-      hipLaunchKernelGGL((splitk_reduce_kernel<double, BM_, BN_, WM_, WN_, 0>), dim3(nblk), dim3(256), 0, stream, \
-                         args, groups, total);                                                                      \
-    else if (dtype == 0)                                                                                            \
-      hipLaunchKernelGGL((splitk_reduce_kernel<double, BM_, BN_, WM_, WN_, 1>), dim3(nblk), dim3(256), 0, stream, \
-                         args, groups, total);                                                                      \
-    else                                                                                                            \
-      hipLaunchKernelGGL((splitk_reduce_kernel<float, BM_, BN_, WM_, WN_, 1>), dim3(nblk), dim3(256), 0, stream,  \
-                         args, groups, total);                                                                      \
-    return hipGetLastError();                                                                                       \
+  const int kind = compute_kind(dtype, precision);
+#define TK_RED_LAUNCH(TS_, L_, BM_, BN_, WM_, WN_)                                                               \
+  hipLaunchKernelGGL((splitk_reduce_kernel<TS_, BM_, BN_, WM_, WN_, L_>), dim3(nblk), dim3(256), 0, stream, args, \
+                     groups, total)
+#define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                   \
+  if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                       \
+    if (dtype == 0 && kind == 0) {                                                             \
+      TK_RED_LAUNCH(double, 0, BM_, BN_, WM_, WN_);                                                                \
+    } else if (dtype == 0 && kind == 1) {                                                      \
+      TK_RED_LAUNCH(double, 2, BM_, BN_, WM_, WN_);                                                                \
+    } else if (dtype == 0) {                                                                   \
+      TK_RED_LAUNCH(double, 1, BM_, BN_, WM_, WN_);                                                                \
+    } else if (kind == 1) {                                                                    \
+      TK_RED_LAUNCH(float, 2, BM_, BN_, WM_, WN_);                                                                 \
+    } else {                                                                                   \
+      TK_RED_LAUNCH(float, 1, BM_, BN_, WM_, WN_);                                                                 \
+    }                                                                                          \
+    return hipGetLastError();                                                                  \
   }
   TK_GEMM_SHAPES(TK_RED_CASE)
 #undef TK_RED_CASE
+#undef TK_RED_LAUNCH
   return hipErrorInvalidValue;
 }
 
