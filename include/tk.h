@@ -235,12 +235,13 @@ tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_ten
  * and the GEMM tile configuration in use (any pointer may be NULL). */
 tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64_t* nzero,
                        int64_t* workspace_bytes, int32_t* tile_m, int32_t* tile_n, int32_t* tile_k);
-/* Work-list sizes of a plan, 12 values: operand-permute tasks and
- * workgroups, zero-block tasks and workgroups, small-K tasks and workgroups,
- * MFMA GEMM descriptors, tiles (work units), workgroups, split-K groups,
- * split-K partial slots, and the schedule's estimated makespan in 16-deep
- * stages (rounded). */
-tk_status tk_plan_counts(const tk_plan* plan, int64_t* counts /* 12 values */);
+/* Work-list sizes of a plan, 14 values: operand-permute tasks and
+ * workgroups, zero-block tasks and workgroups, small-K row / block tasks and
+ * their workgroups, MFMA GEMM descriptors, tiles (work units), workgroups,
+ * split-K groups, split-K partial slots, the schedule's estimated makespan
+ * in 16-deep stages (rounded), and small-K output runs and their
+ * workgroups. */
+tk_status tk_plan_counts(const tk_plan* plan, int64_t* counts /* 14 values */);
 
 /* (M, N, K) of sector GEMMs first..first+count-1 (3 * count values). */
 tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk);

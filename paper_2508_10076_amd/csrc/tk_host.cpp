@@ -492,6 +492,53 @@ struct ZeroSet {
   }
 };
 
+// Output runs and block decoders of the small-K sectors of one K value.
+// Workgroups cut the concatenation of the runs (in destination order) into
+// pieces of at most kRunChunk elements touching at most kRunMax runs.
+struct RunSet {
+  std::vector<tk::SkRun> runs;
+  std::vector<tk::SkRunDec> decs;
+  std::vector<int32_t> first;
+  std::vector<int64_t> wstart;
+  int64_t total = 0;
+  DevBuf d_runs, d_decs, d_first, d_wstart;
+  void finalize() {
+    std::sort(runs.begin(), runs.end(), [](const tk::SkRun& x, const tk::SkRun& y) {
+      return x.buf != y.buf ? x.buf < y.buf : x.off < y.off;
+    });
+    if (runs.size() > static_cast<size_t>(INT32_MAX) || decs.size() > static_cast<size_t>(INT32_MAX))
+      fail(TK_ERR_UNSUPPORTED, "too many output runs");
+    total = 0;
+    for (auto& r : runs) {
+      r.vstart = total;
+      total += r.len;
+    }
+    first.clear();
+    wstart.clear();
+    if (runs.empty()) return;
+    int64_t v = 0;
+    size_t r = 0;
+    wstart.push_back(0);
+    first.push_back(0);
+    while (v < total) {
+      int64_t end = std::min(total, v + tk::kRunChunk);
+      if (r + tk::kRunMax < runs.size()) end = std::min(end, runs[r + tk::kRunMax].vstart);
+      v = end;
+      while (r + 1 < runs.size() && runs[r + 1].vstart <= v) ++r;
+      wstart.push_back(v);
+      first.push_back(static_cast<int32_t>(r));
+    }
+    if (wstart.size() - 1 > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many output-run workgroups");
+  }
+  int nwg() const { return wstart.empty() ? 0 : static_cast<int>(wstart.size()) - 1; }
+  void upload() {
+    d_runs.upload(runs);
+    d_decs.upload(decs);
+    d_first.upload(first);
+    d_wstart.upload(wstart);
+  }
+};
+
 // Small-K tasks of one K value (one workgroup each).
 struct SmallKSet {
   std::vector<tk::SmallKTask> tasks;
@@ -516,6 +563,105 @@ void division_magic(uint32_t d, uint32_t* mag, uint8_t* shr) {
   const int k = 31 + l;
   *mag = static_cast<uint32_t>((uint64_t(1) << k) / d + 1);
   *shr = static_cast<uint8_t>(k);
+}
+
+// Output runs of one small-K sector whose blocks land in C: one decoder per
+// block (row channel i x column channel j) and one run per stretch of the
+// block that is contiguous in C (the leading output dimensions whose strides
+// are those of a dense array).  Returns false, adding nothing, when the runs
+// would be short (under 4 elements on average) or an extent or stride does
+// not fit the decoder.
+bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Group& cg,
+                     const std::vector<tk::SkChan>& chans, int32_t rbase, int32_t cbase,
+                     const std::vector<PairDesc>& pairs, int32_t pbase, const std::vector<int>& src, bool scatter,
+                     int64_t a0, int64_t b0, int64_t M, int64_t K, int16_t abuf, int16_t bbuf) {
+  const int nrow = scatter ? Ct.N1() : 1;
+  const int nout = scatter ? Ct.N() : 2;
+  struct Blk {
+    int64_t dim[8], str[8], so[8];
+    uint32_t bmask;
+    int64_t runlen, count;
+  };
+  std::vector<Blk> blks(static_cast<size_t>(rg.n()) * cg.n());
+  int64_t nruns = 0, nelem = 0;
+  for (int32_t i = 0; i < rg.n(); ++i)
+    for (int32_t j = 0; j < cg.n(); ++j) {
+      const tk::SkChan& rc = chans[rbase + i];
+      const tk::SkChan& cc = chans[cbase + j];
+      const PairDesc& pd = pairs[pbase + i * cg.n() + j];
+      Blk& b = blks[static_cast<size_t>(i) * cg.n() + j];
+      b.bmask = 0;
+      for (int n = 0; n < 8; ++n) {
+        b.dim[n] = 1;
+        b.str[n] = 0;
+        b.so[n] = 0;
+      }
+      for (int n = 0; n < nout; ++n) {
+        const int l = scatter ? src[n] : n;
+        if (l < nrow) {
+          int64_t st = 1;
+          for (int q = 0; q < l; ++q) st *= rc.dim[q];
+          b.dim[n] = rc.dim[l];
+          b.str[n] = st;
+          b.so[n] = pd.S[l];
+        } else {
+          const int m = l - nrow;
+          int64_t st = K;
+          for (int q = 0; q < m; ++q) st *= cc.dim[q];
+          b.dim[n] = cc.dim[m];
+          b.str[n] = st;
+          b.so[n] = pd.S[4 + m];
+          b.bmask |= 1u << n;
+        }
+        if (b.dim[n] >= (int64_t(1) << 24) || b.str[n] * b.dim[n] > INT32_MAX) return false;
+      }
+      b.count = int64_t(rc.count) * cc.count;
+      int64_t run = 1;
+      for (int n = 0; n < nout && (b.dim[n] == 1 || b.so[n] == run); ++n) run *= b.dim[n];
+      b.runlen = run;
+      nruns += b.count / run;
+      nelem += b.count;
+    }
+  if (nruns * 4 > nelem) return false;
+  const int32_t dbase = checked_i32(static_cast<int64_t>(rs.decs.size()), "decoder table");
+  for (int32_t i = 0; i < rg.n(); ++i)
+    for (int32_t j = 0; j < cg.n(); ++j) {
+      const size_t bi = static_cast<size_t>(i) * cg.n() + j;
+      const Blk& b = blks[bi];
+      const PairDesc& pd = pairs[pbase + i * cg.n() + j];
+      tk::SkRunDec d{};
+      d.a = a0 + rg.off[i];
+      d.b = b0 + cg.off[j] * K;
+      d.lda = checked_i32(M, "M");
+      d.sign = pd.sign;
+      d.a_buf = abuf;
+      d.b_buf = bbuf;
+      d.bmask = b.bmask;
+      for (int n = 0; n < 8; ++n) {
+        uint32_t mag = 0;
+        uint8_t shr = 0;
+        division_magic(static_cast<uint32_t>(b.dim[n]), &mag, &shr);
+        d.dimshr[n] = static_cast<uint32_t>(b.dim[n]) | (static_cast<uint32_t>(shr) << 24);
+        d.mag[n] = mag;
+        d.stride[n] = static_cast<int32_t>(b.str[n]);
+      }
+      rs.decs.push_back(d);
+      for (int64_t lin0 = 0; lin0 < b.count; lin0 += b.runlen) {
+        tk::SkRun r{};
+        int64_t rem = lin0, x = 0;
+        for (int n = 0; n < 8; ++n) {
+          x += (rem % b.dim[n]) * b.so[n];
+          rem /= b.dim[n];
+        }
+        r.off = pd.base + x;
+        r.dec = dbase + static_cast<int32_t>(bi);
+        r.lin0 = static_cast<int32_t>(lin0);
+        r.buf = tk::kBufC;
+        r.len = static_cast<int32_t>(b.runlen);
+        rs.runs.push_back(r);
+      }
+    }
+  return true;
 }
 
 // Add one block (dims/strides in output order) as chunked tasks.
@@ -568,6 +714,8 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
 constexpr int64_t kSmallK = 8;
 // columns per small-K task
 constexpr int64_t kSkCols = 64;
+// elements per strip of whole small-K output blocks
+constexpr int64_t kSkStrip = 16384;
 
 // Add one output block of a small-K sector GEMM (dims and strides in output
 // leg order) as chunked tasks, merging dims contiguous in r, s and dst.
@@ -761,6 +909,7 @@ struct tk_plan {
   ZeroSet zranges;       // zero-fill of empty-K blocks that are contiguous ranges
   SmallKSet smallk[9];  // indexed by K: row-stationary small-K tasks
   SkBlockList skblocks[9];  // indexed by K: output-stationary small-K tasks
+  RunSet skruns[9];         // indexed by K: output runs of small-K sectors
   std::vector<tk::SkChan> skchans;  // row / column channels of the small-K sectors
   std::vector<PairDesc> skpairs;    // output placement of their channel pairs
   DevBuf d_skchans, d_skpairs;
@@ -778,6 +927,7 @@ struct tk_batch {
   ZeroSet zranges;
   SmallKSet smallk[9];
   SkBlockList skblocks[9];
+  RunSet skruns[9];
   std::vector<tk::SkChan> skchans;
   std::vector<PairDesc> skpairs;
   DevBuf d_skchans, d_skpairs;
@@ -1166,6 +1316,10 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             P->skpairs.push_back(pd);
           }
         const int16_t dbuf = P->post ? tk::kBufCt : tk::kBufC;
+        if (N > kSkCols && dbuf == tk::kBufC &&
+            add_output_runs(P->skruns[K], Ct, rg, cg, P->skchans, rbase, cbase, P->skpairs, pbase, src, P->scatter,
+                            At.soff[sa], Bt.soff[sb], M, K, abuf, bbuf))
+          continue;
         if (N > kSkCols) {
           // many columns: output-stationary tasks over each output block, in
           // the output's leg order (A~ and B~ of such a sector are re-read
@@ -1179,30 +1333,54 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             order = 0u | (1u << 4);
             nout = 2;
           }
-          for (int32_t j = 0; j < cg.n(); ++j)
-            for (int32_t i = 0; i < rg.n(); ++i) {
-              const int64_t total = rg.size[i] * cg.size[j];
-              if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
-              for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
-                tk::SkBlockTask t{};
-                t.a = At.soff[sa] + rg.off[i];
-                t.b = Bt.soff[sb] + cg.off[j] * K;
-                t.lda = d.M;
-                t.ldb = d.K;
-                t.rchan = rbase + i;
-                t.cchan = cbase + j;
-                t.pair = pbase + i * cg.n() + j;
-                t.start = static_cast<int32_t>(s0);
-                t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
-                t.order = order;
-                t.nrleg = static_cast<int16_t>(nrleg);
-                t.ncleg = static_cast<int16_t>(ncleg);
-                t.nout = static_cast<int16_t>(nout);
-                t.a_buf = abuf;
-                t.b_buf = bbuf;
-                t.dst_buf = dbuf;
-                P->skblocks[K].tasks.push_back(t);
+          auto make = [&](int32_t i, int32_t j) {
+            tk::SkBlockTask t{};
+            t.a = At.soff[sa] + rg.off[i];
+            t.b = Bt.soff[sb];  // the column channel's first column is added per block
+            t.lda = d.M;
+            t.ldb = d.K;
+            t.rchan = rbase + i;
+            t.cchan = cbase + j;
+            t.pair = pbase + i * cg.n() + j;
+            t.order = order;
+            t.nrleg = static_cast<int16_t>(nrleg);
+            t.ncleg = static_cast<int16_t>(ncleg);
+            t.nout = static_cast<int16_t>(nout);
+            t.a_buf = abuf;
+            t.b_buf = bbuf;
+            t.dst_buf = dbuf;
+            t.nblk = 1;
+            return t;
+          };
+          // strips of whole blocks of one row channel (consecutive column
+          // channels, up to kSkStrip elements); a larger block alone, in
+          // chunks
+          for (int32_t i = 0; i < rg.n(); ++i)
+            for (int32_t j = 0; j < cg.n();) {
+              const int64_t blk = rg.size[i] * cg.size[j];
+              if (blk > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
+              if (blk > kSkStrip) {
+                for (int64_t s0 = 0; s0 < blk; s0 += tk::kPermChunk) {
+                  tk::SkBlockTask t = make(i, j);
+                  t.start = static_cast<int32_t>(s0);
+                  t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, blk - s0));
+                  P->skblocks[K].tasks.push_back(t);
+                }
+                ++j;
+                continue;
               }
+              tk::SkBlockTask t = make(i, j);
+              int64_t tot = 0;
+              int32_t n = 0;
+              while (j < cg.n() && rg.size[i] * cg.size[j] <= kSkStrip && tot + rg.size[i] * cg.size[j] <= kSkStrip) {
+                tot += rg.size[i] * cg.size[j];
+                ++j;
+                ++n;
+              }
+              t.start = 0;
+              t.count = static_cast<int32_t>(tot);
+              t.nblk = n;
+              P->skblocks[K].tasks.push_back(t);
             }
           continue;
         }
@@ -1328,6 +1506,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     }
   }
   P->zranges.finalize();
+  for (auto& r : P->skruns) r.finalize();
   pack_workgroups(P->zero);
   for (auto& l : P->skblocks) pack_workgroups(l);
   if (P->post) {
@@ -1354,6 +1533,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     P->d_pairs.upload(P->pairs);
     for (auto& l : P->smallk) l.upload();
     for (auto& l : P->skblocks) l.upload();
+    for (auto& r : P->skruns) r.upload();
     P->d_skchans.upload(P->skchans);
     P->d_skpairs.upload(P->skpairs);
     Sched sc;
@@ -1436,6 +1616,16 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                            static_cast<const PairDesc*>(P.d_skpairs.p), ptrs, P.post ? 1.0 : alpha,
                                            P.post ? 0.0 : beta, stream),
                   "small-K block launch");
+  if (stages & TK_STAGE_GEMM)
+    for (int K = 1; K <= kSmallK; ++K)
+      if (P.skruns[K].nwg() > 0)
+        hip_check(tk::launch_smallk_runs(P.dtype, P.precision, K, static_cast<const tk::SkRun*>(P.skruns[K].d_runs.p),
+                                         static_cast<int>(P.skruns[K].runs.size()),
+                                         static_cast<const int32_t*>(P.skruns[K].d_first.p),
+                                         static_cast<const int64_t*>(P.skruns[K].d_wstart.p), P.skruns[K].nwg(),
+                                         static_cast<const tk::SkRunDec*>(P.skruns[K].d_decs.p), ptrs,
+                                         P.post ? 1.0 : alpha, P.post ? 0.0 : beta, stream),
+                  "small-K run launch");
   if ((stages & TK_STAGE_ZERO) && P.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(P.dtype, static_cast<const tk::ZeroRange*>(P.zranges.d_ranges.p),
                                      static_cast<int>(P.zranges.ranges.size()),
@@ -1846,13 +2036,18 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
       skt += static_cast<int64_t>(l.tasks.size());
       skw += l.nwg();
     }
-    const int64_t v[12] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
+    int64_t nrun = 0, nrw = 0;
+    for (const auto& r : P.skruns) {
+      nrun += static_cast<int64_t>(r.runs.size());
+      nrw += r.nwg();
+    }
+    const int64_t v[14] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
                            static_cast<int64_t>(P.zero.tasks.size() + P.zranges.ranges.size()),
                            P.zero.nwg() + P.zranges.nwg(), skt, skw,
                            static_cast<int64_t>(P.descs.size()), static_cast<int64_t>(P.tiles.size()),
                            static_cast<int64_t>(P.wg_first.size()) - 1, P.ngroups, P.nslots,
-                           static_cast<int64_t>(P.makespan + 0.5)};
-    std::copy(v, v + 12, c);
+                           static_cast<int64_t>(P.makespan + 0.5), nrun, nrw};
+    std::copy(v, v + 14, c);
   });
 }
 
@@ -2006,6 +2201,15 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                          static_cast<const tk::SkChan*>(b.d_skchans.p),
                                          static_cast<const PairDesc*>(b.d_skpairs.p), ptrs, b.alpha, b.beta, stream),
                 "small-K block launch");
+  for (int K = 1; K <= kSmallK; ++K)
+    if (b.skruns[K].nwg() > 0)
+      hip_check(tk::launch_smallk_runs(b.dtype, b.precision, K, static_cast<const tk::SkRun*>(b.skruns[K].d_runs.p),
+                                       static_cast<int>(b.skruns[K].runs.size()),
+                                       static_cast<const int32_t*>(b.skruns[K].d_first.p),
+                                       static_cast<const int64_t*>(b.skruns[K].d_wstart.p), b.skruns[K].nwg(),
+                                       static_cast<const tk::SkRunDec*>(b.skruns[K].d_decs.p), ptrs, b.alpha, b.beta,
+                                       stream),
+                "small-K run launch");
   if (b.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(b.dtype, static_cast<const tk::ZeroRange*>(b.zranges.d_ranges.p),
                                      static_cast<int>(b.zranges.ranges.size()),
@@ -2074,6 +2278,17 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
         }
         for (size_t w = 1; w < P.skblocks[K].wg_first.size(); ++w)
           b->skblocks[K].wg_first.push_back(base + P.skblocks[K].wg_first[w]);
+        const int32_t db = static_cast<int32_t>(b->skruns[K].decs.size());
+        for (tk::SkRunDec d : P.skruns[K].decs) {
+          d.a_buf = static_cast<int16_t>(d.a_buf + i * tk::kBufsPerPlan);
+          d.b_buf = static_cast<int16_t>(d.b_buf + i * tk::kBufsPerPlan);
+          b->skruns[K].decs.push_back(d);
+        }
+        for (tk::SkRun r : P.skruns[K].runs) {
+          r.dec += db;
+          r.buf += i * tk::kBufsPerPlan;
+          b->skruns[K].runs.push_back(r);
+        }
       }
       b->skchans.insert(b->skchans.end(), P.skchans.begin(), P.skchans.end());
       b->skpairs.insert(b->skpairs.end(), P.skpairs.begin(), P.skpairs.end());
@@ -2100,11 +2315,13 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
     choose_default_tile(b->descs, b->precision, &tm, &tn, &tkk);
     batch_schedule(*b, tm, tn, tkk);
     b->zranges.finalize();
+    for (auto& r : b->skruns) r.finalize();
     b->pre.upload();
     b->zero.upload();
     b->zranges.upload();
     for (auto& l : b->smallk) l.upload();
     for (auto& l : b->skblocks) l.upload();
+    for (auto& r : b->skruns) r.upload();
     b->d_skchans.upload(b->skchans);
     b->d_skpairs.upload(b->skpairs);
     b->d_descs.upload(b->descs);

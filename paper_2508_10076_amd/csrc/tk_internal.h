@@ -168,10 +168,14 @@ hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int til
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                                 const GemmTile* groups, int ngroups, hipStream_t stream);
 // Elements start .. start + count - 1 of one output block (row channel
-// rchan x column channel cchan) of a small-K sector with many columns,
+// rchan x column channel cchan), or a strip of whole blocks (below), of a
+// small-K sector with many columns,
 // enumerated in the order of the output's legs (colex, first leg fastest):
 // output leg o is leg ((order >> 4o) & 15) of C~ (rows' legs first).  a, b:
 // A~ element of the channel's first row, B~ element of its first column.
+// nblk > 1: a strip of whole blocks, column channels cchan .. cchan+nblk-1
+// of the same row channel (pairs pair .. pair+nblk-1); count is then the
+// strip's total (used only to pack workgroups).
 struct SkBlockTask {
   int64_t a, b;
   int32_t lda, ldb;
@@ -180,10 +184,49 @@ struct SkBlockTask {
   uint32_t order;
   int16_t nrleg, ncleg, nout;
   int16_t a_buf, b_buf, dst_buf;
+  int32_t nblk;
 };
 hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTask* tasks, const int32_t* wg_first,
                                 int nwg, const SkChan* chans, const PairDesc* pairs, const Ptrs& ptrs, double alpha,
                                 double beta, hipStream_t stream);
+
+// Output runs of the small-K sectors with many columns whose blocks land in
+// C directly.  A run is a stretch of consecutive elements of C inside one
+// output block, over which the block's linear index (its dimensions in the
+// output's leg order, first fastest) also steps by one.
+struct SkRun {
+  int64_t off;     // first element in the destination buffer
+  int64_t vstart;  // first element in the list's concatenation of runs
+  int32_t dec;     // decoder of the run's block
+  int32_t lin0;    // linear index of the run's first element in its block
+  int32_t buf;     // destination buffer
+  int32_t len;     // elements (host side)
+};
+
+// One output block written through runs: its rows in A~, its first column
+// in B~, its sign, and per output dimension (output leg order; unused ones
+// of extent 1 and stride 0) the extent with its division magic and the
+// stride of the leg in A~ (a row leg) or in B~ (a column leg: bit set in
+// bmask; the stride then counts elements of B~, ldb included).
+struct SkRunDec {
+  int64_t a, b;
+  int32_t lda;
+  float sign;
+  int16_t a_buf, b_buf;
+  uint32_t bmask;
+  uint32_t dimshr[8];  // extent | shift << 24
+  uint32_t mag[8];
+  int32_t stride[8];
+};
+constexpr int kRunChunk = 4096;  // elements of one workgroup
+constexpr int kRunMax = 256;     // runs one workgroup touches at most
+
+// Runs of small-K sectors sharing the same K (1..8).  Workgroup w covers
+// elements wstart[w] .. wstart[w+1]-1 of the concatenation; first[w] is the
+// run holding element wstart[w].
+hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs, int nruns, const int32_t* first,
+                              const int64_t* wstart, int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha,
+                              double beta, hipStream_t stream);
 
 // Zero (or beta-scale) the ranges: one workgroup per kZeroChunk virtual
 // elements; first[w] = the range holding virtual element w * kZeroChunk.

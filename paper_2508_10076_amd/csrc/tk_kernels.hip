@@ -933,12 +933,18 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
 // read from cache) are combined as in smallk_kernel.  A workgroup with one
 // task spreads it over all its threads, one with several gives each wave its
 // own tasks.
+// a[i & 3] as a select chain: a dynamic index would put the array in
+// scratch memory
+template <typename V>
+__device__ __forceinline__ V pick4(const V* a, int i) {
+  i &= 3;
+  return i == 0 ? a[0] : i == 1 ? a[1] : i == 2 ? a[2] : a[3];
+}
+
 template <typename T, int MODE, int KK>
-__device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const TK_CONST SkChan* ch,
-                                                  const TK_CONST PairDesc* pr, const Ptrs& P, double alpha,
-                                                  double beta, int lt, int nthr) {
-  const SkChan rc = ch[tk.rchan], cc = ch[tk.cchan];
-  const PairDesc pd = pr[tk.pair];
+__device__ __forceinline__ void smallk_block(const SkBlockTask& tk, const SkChan& rc, const SkChan& cc,
+                                             const PairDesc& pd, int start, int count, const Ptrs& P, double alpha,
+                                             double beta, int lt, int nthr) {
   int32_t dim[8], ra[8], cb[8], so[8];
   uint32_t mag[8];
   int shr[8];
@@ -955,21 +961,21 @@ __device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const T
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (q < l) stride *= rc.dim[q];
-        dim[o] = rc.dim[l & 3];
-        mag[o] = rc.mag[l & 3];
-        shr[o] = rc.shr[l & 3];
+        dim[o] = pick4(rc.dim, l);
+        mag[o] = pick4(rc.mag, l);
+        shr[o] = pick4(rc.shr, l);
         ra[o] = stride;
-        so[o] = pd.S[l & 3];
+        so[o] = pick4(pd.S, l);
       } else {
         const int m = l - tk.nrleg;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
           if (q < m) stride *= cc.dim[q];
-        dim[o] = cc.dim[m & 3];
-        mag[o] = cc.mag[m & 3];
-        shr[o] = cc.shr[m & 3];
+        dim[o] = pick4(cc.dim, m);
+        mag[o] = pick4(cc.mag, m);
+        shr[o] = pick4(cc.shr, m);
         cb[o] = stride;
-        so[o] = pd.S[4 + (m & 3)];
+        so[o] = pick4(pd.S + 4, m);
       }
     }
   }
@@ -978,11 +984,11 @@ __device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const T
   TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk.dst_buf) + pd.base;
   const double scale = alpha * static_cast<double>(pd.sign);
   constexpr int U = 4;
-  for (int e0 = 0; e0 < tk.count; e0 += nthr * U) {
+  for (int e0 = 0; e0 < count; e0 += nthr * U) {
     int64_t r[U], c[U], x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      uint32_t lin = static_cast<uint32_t>(tk.start + min(e0 + u * nthr + lt, tk.count - 1));
+      uint32_t lin = static_cast<uint32_t>(start + min(e0 + u * nthr + lt, count - 1));
       int64_t rr = 0, cc2 = 0, xx = 0;
 #pragma unroll
       for (int o = 0; o < 8; ++o)
@@ -995,7 +1001,7 @@ __device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const T
           xx += static_cast<int64_t>(i) * so[o];
         }
       r[u] = rr;
-      c[u] = cc2 * tk.ldb;
+      c[u] = (cc2 + cc.off) * tk.ldb;
       x[u] = xx;
     }
     double av[U][KK], bv[U][KK];
@@ -1008,7 +1014,7 @@ __device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const T
       }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (e0 + u * nthr + lt >= tk.count) continue;
+      if (e0 + u * nthr + lt >= count) continue;
       double v = scale * smallk_dot<MODE, KK>(av[u], bv[u]);
       if (beta != 0.0) v += beta * static_cast<double>(D[x[u]]);
       D[x[u]] = static_cast<T>(v);
@@ -1016,6 +1022,37 @@ __device__ __forceinline__ void smallk_block_task(const SkBlockTask& tk, const T
   }
 }
 
+// One task: a chunk of one block (nblk <= 1), or blocks b0, b0 + bstep, ...
+// of a strip, each whole; the next block's channel record and pair are
+// read before the current block is written, so their latency overlaps it.
+template <typename T, int MODE, int KK>
+__device__ __forceinline__ void smallk_strip(const SkBlockTask& tk, const TK_CONST SkChan* ch,
+                                             const TK_CONST PairDesc* pr, const Ptrs& P, double alpha, double beta,
+                                             int lt, int nthr, int b0, int bstep) {
+  const SkChan rc = ch[tk.rchan];
+  if (tk.nblk <= 1) {
+    const SkChan cc = ch[tk.cchan];
+    const PairDesc pd = pr[tk.pair];
+    smallk_block<T, MODE, KK>(tk, rc, cc, pd, tk.start, tk.count, P, alpha, beta, lt, nthr);
+    return;
+  }
+  if (b0 >= tk.nblk) return;
+  SkChan cn = ch[tk.cchan + b0];
+  PairDesc pn = pr[tk.pair + b0];
+  for (int b = b0; b < tk.nblk; b += bstep) {
+    const SkChan cc = cn;
+    const PairDesc pd = pn;
+    if (b + bstep < tk.nblk) {
+      cn = ch[tk.cchan + b + bstep];
+      pn = pr[tk.pair + b + bstep];
+    }
+    smallk_block<T, MODE, KK>(tk, rc, cc, pd, 0, rc.count * cc.count, P, alpha, beta, lt, nthr);
+  }
+}
+
+// A workgroup holding one task: a strip is split over the waves by block,
+// a single block over all threads; one holding several tasks gives each
+// wave its own tasks.
 template <typename T, int MODE, int KK>
 __global__ __launch_bounds__(kThreads) void smallk_blocks_kernel(const SkBlockTask* __restrict__ tasks,
                                                                  const int32_t* __restrict__ wg_first,
@@ -1025,15 +1062,111 @@ __global__ __launch_bounds__(kThreads) void smallk_blocks_kernel(const SkBlockTa
   const TK_CONST SkChan* ch = const_ptr(chans);
   const TK_CONST PairDesc* pr = const_ptr(pairs);
   const int t0 = const_ptr(wg_first)[blockIdx.x], t1 = const_ptr(wg_first)[blockIdx.x + 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (t1 - t0 == 1) {
     const SkBlockTask tk = const_ptr(tasks)[t0];
-    smallk_block_task<T, MODE, KK>(tk, ch, pr, P, alpha, beta, threadIdx.x, kThreads);
+    if (tk.nblk > 1)
+      smallk_strip<T, MODE, KK>(tk, ch, pr, P, alpha, beta, lane, 64, wave, kThreads / 64);
+    else
+      smallk_strip<T, MODE, KK>(tk, ch, pr, P, alpha, beta, threadIdx.x, kThreads, 0, 1);
     return;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = t0 + __builtin_amdgcn_readfirstlane(wave); t < t1; t += kThreads / 64) {
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) {
     const SkBlockTask tk = const_ptr(tasks)[t];
-    smallk_block_task<T, MODE, KK>(tk, ch, pr, P, alpha, beta, lane, 64);
+    smallk_strip<T, MODE, KK>(tk, ch, pr, P, alpha, beta, lane, 64, 0, 1);
+  }
+}
+
+// Output runs: workgroup w covers elements wstart[w] .. wstart[w+1]-1 of the
+// concatenated runs of one K.  Its runs (at most kRunMax + 1) are staged in
+// LDS with their block's operand pointers, sign and A~ stride; each element
+// finds its run by binary search, reads the block's dimensions from the
+// decoder (shared by the lanes of a run, so served by the cache), splits
+// its linear index over them and takes the K-term dot product of its row
+// of A~ and column of B~.  Consecutive threads write consecutive elements
+// of C however small the blocks are.
+template <typename T, int MODE, int KK>
+__global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __restrict__ runs, int nruns,
+                                                               const int32_t* __restrict__ first,
+                                                               const int64_t* __restrict__ wstart,
+                                                               const SkRunDec* __restrict__ decs, Ptrs P,
+                                                               double alpha, double beta) {
+  __shared__ int64_t s_v[kRunMax + 1];
+  __shared__ TK_GLOBAL T* s_p[kRunMax + 1];
+  __shared__ const TK_GLOBAL T* s_a[kRunMax + 1];
+  __shared__ const TK_GLOBAL T* s_b[kRunMax + 1];
+  __shared__ int32_t s_d[kRunMax + 1], s_l[kRunMax + 1], s_lda[kRunMax + 1];
+  __shared__ uint32_t s_m[kRunMax + 1];
+  __shared__ float s_sg[kRunMax + 1];
+  const int64_t c0 = const_ptr(wstart)[blockIdx.x], c1 = const_ptr(wstart)[blockIdx.x + 1];
+  const int r0 = const_ptr(first)[blockIdx.x];
+  const int r1 = min(nruns, const_ptr(first)[blockIdx.x + 1] + 1);
+  const int nr = min(r1 - r0, kRunMax + 1);
+  for (int i = threadIdx.x; i < nr; i += kThreads) {
+    const SkRun rn = runs[r0 + i];
+    const SkRunDec* dc = decs + rn.dec;
+    s_v[i] = rn.vstart;
+    s_p[i] = buf_ptr_lane<T>(P, rn.buf) + (rn.off - rn.vstart);
+    s_a[i] = buf_ptr_lane<const T>(P, dc->a_buf) + dc->a;
+    s_b[i] = buf_ptr_lane<const T>(P, dc->b_buf) + dc->b;
+    s_d[i] = rn.dec;
+    s_l[i] = rn.lin0;
+    s_lda[i] = dc->lda;
+    s_m[i] = dc->bmask;
+    s_sg[i] = dc->sign;
+  }
+  __syncthreads();
+  constexpr int U = KK <= 2 ? 4 : 2;
+  for (int64_t e0 = c0; e0 < c1; e0 += kThreads * U) {
+    int lo[U];
+    int64_t ao[U], bo[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = min(e0 + u * kThreads + threadIdx.x, c1 - 1);
+      int l = 0, h = nr - 1;  // largest i with s_v[i] <= v
+      while (l < h) {
+        const int mid = (l + h + 1) >> 1;
+        if (s_v[mid] <= v) l = mid;
+        else h = mid - 1;
+      }
+      lo[u] = l;
+      const SkRunDec* dc = decs + s_d[l];
+      uint32_t lin = static_cast<uint32_t>(s_l[l]) + static_cast<uint32_t>(v - s_v[l]);
+      const uint32_t bm = s_m[l];
+      int64_t a = 0, b = 0;
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const uint32_t ds = dc->dimshr[o];
+        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * dc->mag[o]) >> (ds >> 24));
+        const int64_t i = static_cast<int64_t>(lin - q * (ds & 0xffffffu)) * dc->stride[o];
+        lin = q;
+        if ((bm >> o) & 1u) b += i;
+        else a += i;
+      }
+      ao[u] = a;
+      bo[u] = b;
+    }
+    double av[U][KK], bv[U][KK];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const TK_GLOBAL T* A = s_a[lo[u]] + ao[u];
+      const TK_GLOBAL T* B = s_b[lo[u]] + bo[u];
+      const int64_t lda = s_lda[lo[u]];
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        av[u][k] = static_cast<double>(A[k * lda]);
+        bv[u][k] = static_cast<double>(B[k]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t v = e0 + u * kThreads + threadIdx.x;
+      if (v >= c1) continue;
+      double x = alpha * static_cast<double>(s_sg[lo[u]]) * smallk_dot<MODE, KK>(av[u], bv[u]);
+      TK_GLOBAL T* d = s_p[lo[u]] + v;
+      if (beta != 0.0) x += beta * static_cast<double>(*d);
+      *d = static_cast<T>(x);
+    }
   }
 }
 
@@ -1115,6 +1248,45 @@ hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTa
       launch_smallk_blocks_k<float, 2>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
     else
       launch_smallk_blocks_k<float, 1>(K, tasks, wg_first, nwg, chans, pairs, ptrs, alpha, beta, stream);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static void launch_smallk_runs_k(int K, const SkRun* runs, int nruns, const int32_t* first, const int64_t* wstart,
+                                 int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha, double beta,
+                                 hipStream_t stream) {
+  switch (K) {
+#define TK_SKR_CASE(KK_)                                                                                        \
+  case KK_:                                                                                                     \
+    hipLaunchKernelGGL((smallk_runs_kernel<T, MODE, KK_>), dim3(nwg), dim3(kThreads), 0, stream, runs, nruns,   \
+                       first, wstart, decs, ptrs, alpha, beta);                                                 \
+    break;
+    TK_SKR_CASE(1) TK_SKR_CASE(2) TK_SKR_CASE(3) TK_SKR_CASE(4) TK_SKR_CASE(5) TK_SKR_CASE(6) TK_SKR_CASE(7)
+    TK_SKR_CASE(8)
+#undef TK_SKR_CASE
+    default:
+      break;
+  }
+}
+
+hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs, int nruns, const int32_t* first,
+                              const int64_t* wstart, int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha,
+                              double beta, hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (K < 1 || K > 8) return hipErrorInvalidValue;
+  if (dtype == 0) {
+    if (precision == 0)
+      launch_smallk_runs_k<double, 0>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+    else if (precision == 1)
+      launch_smallk_runs_k<double, 1>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+    else
+      launch_smallk_runs_k<double, 2>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+  } else {
+    if (precision == 2)
+      launch_smallk_runs_k<float, 2>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+    else
+      launch_smallk_runs_k<float, 1>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
   }
   return hipGetLastError();
 }

@@ -380,10 +380,10 @@ class Plan:
                     tile=(tm.value, tn.value, tkk.value))
 
     def counts(self):
-        out = np.zeros(12, np.int64)
+        out = np.zeros(14, np.int64)
         _check(lib.tk_plan_counts(self.h, out.ctypes.data_as(_I64P)))
         keys = ("pre_tasks", "pre_wgs", "zero_tasks", "zero_wgs", "smallk_tasks", "smallk_wgs", "gemm_descs",
-                "tiles", "gemm_wgs", "split_groups", "split_slots", "makespan_stages")
+                "tiles", "gemm_wgs", "split_groups", "split_slots", "makespan_stages", "smallk_runs", "run_wgs")
         return dict(zip(keys, out.tolist()))
 
     def gemms(self):

@@ -185,7 +185,7 @@ def _wide_n_case(rng, sym):
 @pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
 def test_contract_small_k_many_columns(ctx, sym):
     rng = np.random.default_rng(4700 + len(sym))
-    seen_wide = 0
+    seen_wide = seen_runs = 0
     for trial in range(6):
         tA, pA, qA, tB, pB, qB, pAB, qAB = _wide_n_case(rng, sym)
         if trial == 0:
@@ -197,12 +197,77 @@ def test_contract_small_k_many_columns(ctx, sym):
         P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg)
         g = P.gemms()
         seen_wide += int(len(g) > 0 and g[:, 1].max() > 64 and g[:, 2].max() <= 8)
+        seen_runs += int(P.counts()["smallk_runs"] > 0)
         c0 = int_vec(rng, Cg.nelem)
         upload(Cg, c0)
         tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
         _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
         assert np.array_equal(download(Cg), ref), (sym, trial)
     assert seen_wide >= 3
+    assert seen_runs >= 3
+
+
+def _short_run_case(rng, sym, swap):
+    """Small K against wide columns, where the rows of A~ come in channels of
+    one row each (two codomain legs of degeneracy 1 with several sectors):
+    the output blocks are single rows, too short for output runs, so the
+    planner keeps the per-block tasks.  swap reverses the two row legs in the
+    output (fused permute) instead of the identity layout."""
+    cands = {"Z1": [()], "Z2": [(0,), (1,)], "FZ2": [(0,), (1,)], "U1": [(q,) for q in range(-2, 3)],
+             "U1xFZ2": [(q, p) for q in range(-1, 2) for p in (0, 1)]}[sym]
+    while True:
+        rows = [synth.space(cands, [1] * len(cands), bool(rng.random() < 0.5)) for _ in range(2)]
+        kl = synth.random_space(rng, sym, max_deg=2)
+        tA = dict(sym=sym, cod=rows, dom=[kl])
+        wide = synth.random_space(rng, sym, max_sect=3, max_deg=4)
+        wide = synth.space(wide.sectors, [d + 70 for d in wide.degs], wide.dual)
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(kl.sectors, kl.degs, kl.dual)], dom=[wide])
+        if ostruct(tA).size and ostruct(tB).size:
+            return tA, (0, 1), (2,), tB, (0,), (1,), ((1, 0) if swap else (0, 1)), (2,)
+
+
+@pytest.mark.parametrize("sym", ["Z2", "U1", "U1xFZ2"])
+@pytest.mark.parametrize("swap", [False, True])
+def test_contract_small_k_short_runs_use_block_tasks(ctx, sym, swap):
+    rng = np.random.default_rng(5100 + len(sym) + 7 * swap)
+    seen_blocks = 0
+    for trial in range(3):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _short_run_case(rng, sym, swap)
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg)
+        cnt = P.counts()
+        seen_blocks += int(cnt["smallk_tasks"] > 0 and cnt["smallk_runs"] == 0)
+        c0 = int_vec(rng, Cg.nelem)
+        upload(Cg, c0)
+        P.execute(A, B, Cg, alpha=-1.0, beta=2.0)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=-1.0, beta=2.0, vC=c0)
+        assert np.array_equal(download(Cg), ref), (sym, swap, trial)
+    assert seen_blocks >= 1
+
+
+@pytest.mark.parametrize("sym", ["U1", "U1xFZ2"])
+def test_contract_small_k_wide_columns_permuted_after(ctx, sym):
+    """Small K, wide columns and five row legs: the output permute runs after
+    the small-K blocks, which then write C~ in its own layout."""
+    rng = np.random.default_rng(5300 + len(sym))
+    for trial in range(3):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _wide_case(rng, sym, 2)
+        w = tB["dom"][0]
+        tB = dict(tB, dom=[synth.space(w.sectors, [d + 70 for d in w.degs], w.dual)])
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg)
+        assert P.counts()["smallk_runs"] == 0
+        c0 = int_vec(rng, Cg.nelem)
+        upload(Cg, c0)
+        P.execute(A, B, Cg, alpha=2.0, beta=-1.0)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
+        assert np.array_equal(download(Cg), ref), (sym, trial)
 
 
 def test_contract_fermionic_against_graph_evaluator(ctx):
@@ -355,6 +420,35 @@ def test_batch_graph_replays(ctx):
         s.synchronize()
         for Cg, ref in zip(Cs, refs):
             assert np.array_equal(download(Cg), ref), rep
+
+
+def test_batch_small_k_output_runs(ctx):
+    """A batch of small-K contractions with wide columns: the members' output
+    runs and decoders are merged into one run list per K."""
+    rng = np.random.default_rng(5500)
+    plans, As, Bs, Cs, refs = [], [], [], [], []
+    for m in range(4):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = _wide_n_case(rng, "U1xFZ2")
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg)
+        if P.counts()["smallk_runs"] == 0:
+            continue
+        plans.append(P)
+        As.append(A)
+        Bs.append(B)
+        Cs.append(Cg)
+        refs.append(blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB)[1])
+    assert len(plans) >= 2
+    for Cg in Cs:
+        fill(Cg)
+    batch = tk.Batch(ctx, plans, As, Bs, Cs)
+    batch.launch()
+    torch.cuda.synchronize()
+    for Cg, ref in zip(Cs, refs):
+        assert np.array_equal(download(Cg), ref)
 
 
 def test_heff_chain_graph_replays_match_eager(ctx):
