@@ -444,13 +444,15 @@ using SkBlockList = TaskListT<tk::SkBlockTask>;
 
 // Ranges of elements to zero: collected as (buffer, offset, length), then
 // sorted, merged where adjacent, and laid end to end as one virtual array
-// cut into kZeroChunk-element workgroups.
+// cut into workgroups of at most kZeroChunk elements in at most kZeroMax
+// ranges.
 struct ZeroSet {
   std::vector<std::tuple<int32_t, int64_t, int64_t>> raw;
   std::vector<tk::ZeroRange> ranges;
   std::vector<int32_t> first;
+  std::vector<int64_t> wstart;
   int64_t total = 0;
-  DevBuf d_ranges, d_first;
+  DevBuf d_ranges, d_first, d_wstart;
   void add(int32_t buf, int64_t off, int64_t len) {
     if (len > 0) raw.emplace_back(buf, off, len);
   }
@@ -475,20 +477,28 @@ struct ZeroSet {
       total += len;
     }
     if (ranges.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many zero ranges");
-    const int64_t nwg = (total + tk::kZeroChunk - 1) / tk::kZeroChunk;
-    if (nwg > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "zero fill too large");
-    first.assign(static_cast<size_t>(nwg) + 1, 0);
+    first.clear();
+    wstart.clear();
+    if (ranges.empty()) return;
+    int64_t v = 0;
     size_t r = 0;
-    for (int64_t w = 0; w <= nwg; ++w) {
-      const int64_t v = std::min(w * tk::kZeroChunk, std::max<int64_t>(total - 1, 0));
+    wstart.push_back(0);
+    first.push_back(0);
+    while (v < total) {
+      int64_t stop = std::min(total, v + tk::kZeroChunk);
+      if (r + tk::kZeroMax < ranges.size()) stop = std::min(stop, ranges[r + tk::kZeroMax].vstart);
+      v = stop;
       while (r + 1 < ranges.size() && ranges[r + 1].vstart <= v) ++r;
-      first[static_cast<size_t>(w)] = static_cast<int32_t>(r);
+      wstart.push_back(v);
+      first.push_back(static_cast<int32_t>(r));
     }
+    if (wstart.size() - 1 > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "zero fill too large");
   }
-  int nwg() const { return ranges.empty() ? 0 : static_cast<int>(first.size()) - 1; }
+  int nwg() const { return wstart.empty() ? 0 : static_cast<int>(wstart.size()) - 1; }
   void upload() {
     d_ranges.upload(ranges);
     d_first.upload(first);
+    d_wstart.upload(wstart);
   }
 };
 
@@ -521,9 +531,9 @@ struct RunSet {
     wstart.push_back(0);
     first.push_back(0);
     while (v < total) {
-      int64_t end = std::min(total, v + tk::kRunChunk);
-      if (r + tk::kRunMax < runs.size()) end = std::min(end, runs[r + tk::kRunMax].vstart);
-      v = end;
+      int64_t stop = std::min(total, v + tk::kRunChunk);
+      if (r + tk::kRunMax < runs.size()) stop = std::min(stop, runs[r + tk::kRunMax].vstart);
+      v = stop;
       while (r + 1 < runs.size() && runs[r + 1].vstart <= v) ++r;
       wstart.push_back(v);
       first.push_back(static_cast<int32_t>(r));
@@ -1629,8 +1639,8 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
   if ((stages & TK_STAGE_ZERO) && P.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(P.dtype, static_cast<const tk::ZeroRange*>(P.zranges.d_ranges.p),
                                      static_cast<int>(P.zranges.ranges.size()),
-                                     static_cast<const int32_t*>(P.zranges.d_first.p), P.zranges.nwg(),
-                                     P.zranges.total, ptrs, P.post ? 0.0 : beta, stream),
+                                     static_cast<const int32_t*>(P.zranges.d_first.p),
+                                     static_cast<const int64_t*>(P.zranges.d_wstart.p), P.zranges.nwg(), ptrs, P.post ? 0.0 : beta, stream),
               "zero-range launch");
   if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
     hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
@@ -2213,8 +2223,8 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
   if (b.zranges.nwg() > 0)
     hip_check(tk::launch_zero_ranges(b.dtype, static_cast<const tk::ZeroRange*>(b.zranges.d_ranges.p),
                                      static_cast<int>(b.zranges.ranges.size()),
-                                     static_cast<const int32_t*>(b.zranges.d_first.p), b.zranges.nwg(),
-                                     b.zranges.total, ptrs, b.beta, stream),
+                                     static_cast<const int32_t*>(b.zranges.d_first.p),
+                                     static_cast<const int64_t*>(b.zranges.d_wstart.p), b.zranges.nwg(), ptrs, b.beta, stream),
               "zero-range launch");
   if (b.zero.nwg() > 0)
     hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),

@@ -99,8 +99,9 @@ struct ZeroRange {
   int32_t buf;
   int32_t pad_;
 };
-// virtual elements per workgroup of the zero-range kernel
-constexpr int kZeroChunk = 2048;
+// elements and ranges of one workgroup of the zero-range kernel (at most)
+constexpr int kZeroChunk = 8192;
+constexpr int kZeroMax = 256;
 
 // Rows or columns of one channel of a small-K sector: first index in the
 // sector, count, and the degeneracy of each leg of the channel (the index of
@@ -228,10 +229,10 @@ hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs
                               const int64_t* wstart, int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha,
                               double beta, hipStream_t stream);
 
-// Zero (or beta-scale) the ranges: one workgroup per kZeroChunk virtual
-// elements; first[w] = the range holding virtual element w * kZeroChunk.
-hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first, int nwg,
-                              int64_t total, const Ptrs& ptrs, double beta, hipStream_t stream);
+// Zero (or beta-scale) the ranges: workgroup w covers virtual elements
+// wstart[w] .. wstart[w+1]-1; first[w] is the range holding wstart[w].
+hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first,
+                              const int64_t* wstart, int nwg, const Ptrs& ptrs, double beta, hipStream_t stream);
 // Small-K sector GEMM tasks that all share the same K (1..8): one
 // workgroup per task.
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

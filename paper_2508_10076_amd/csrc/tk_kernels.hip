@@ -146,23 +146,23 @@ __device__ __forceinline__ TK_GLOBAL T* buf_ptr_lane(const Ptrs& P, int id) {
   return (TK_GLOBAL T*)p;
 }
 
-// Zero ranges: workgroup w covers virtual elements [w C, (w+1) C) of the
-// concatenated ranges (C = kZeroChunk).  Its ranges (at most C + 1) are
-// staged in LDS as (virtual start, destination pointer minus virtual
-// start); each element finds its range by binary search there, so
-// consecutive threads write consecutive addresses however short the
-// ranges are.
+// Zero ranges: workgroup w covers virtual elements wstart[w] ..
+// wstart[w+1]-1 of the concatenated ranges (at most kZeroChunk elements in
+// at most kZeroMax ranges).  Its ranges are staged in LDS as (virtual
+// start, destination pointer minus virtual start); each element finds its
+// range by binary search there, so consecutive threads write consecutive
+// addresses however short the ranges are.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void zero_ranges_kernel(const ZeroRange* __restrict__ ranges, int nranges,
-                                                               const int32_t* __restrict__ first, int64_t total,
-                                                               Ptrs P, double beta) {
-  __shared__ int64_t s_v[kZeroChunk + 2];
-  __shared__ TK_GLOBAL T* s_p[kZeroChunk + 2];
-  const int64_t c0 = static_cast<int64_t>(blockIdx.x) * kZeroChunk;
-  const int64_t c1 = min(total, c0 + kZeroChunk);
+                                                               const int32_t* __restrict__ first,
+                                                               const int64_t* __restrict__ wstart, Ptrs P,
+                                                               double beta) {
+  __shared__ int64_t s_v[kZeroMax + 1];
+  __shared__ TK_GLOBAL T* s_p[kZeroMax + 1];
+  const int64_t c0 = const_ptr(wstart)[blockIdx.x], c1 = const_ptr(wstart)[blockIdx.x + 1];
   const int r0 = const_ptr(first)[blockIdx.x];
   const int r1 = min(nranges, const_ptr(first)[blockIdx.x + 1] + 1);
-  const int nr = r1 - r0;
+  const int nr = min(r1 - r0, kZeroMax + 1);
   for (int i = threadIdx.x; i < nr; i += kThreads) {
     const ZeroRange zr = ranges[r0 + i];
     s_v[i] = zr.vstart;
@@ -1173,15 +1173,15 @@ __global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __re
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first, int nwg,
-                              int64_t total, const Ptrs& ptrs, double beta, hipStream_t stream) {
+hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first,
+                              const int64_t* wstart, int nwg, const Ptrs& ptrs, double beta, hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
   if (dtype == 0)
-    hipLaunchKernelGGL(zero_ranges_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first, total,
-                       ptrs, beta);
+    hipLaunchKernelGGL(zero_ranges_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first,
+                       wstart, ptrs, beta);
   else
-    hipLaunchKernelGGL(zero_ranges_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first, total,
-                       ptrs, beta);
+    hipLaunchKernelGGL(zero_ranges_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first,
+                       wstart, ptrs, beta);
   return hipGetLastError();
 }
 
