@@ -502,6 +502,9 @@ struct ZeroSet {
   }
 };
 
+// bound of the output-run decoder's 24-bit arithmetic
+constexpr int64_t kRunLimit = int64_t(1) << 24;
+
 // Output runs and block decoders of the small-K sectors of one K value.
 // Workgroups cut the concatenation of the runs (in destination order) into
 // pieces of at most kRunChunk elements touching at most kRunMax runs.
@@ -579,8 +582,9 @@ void division_magic(uint32_t d, uint32_t* mag, uint8_t* shr) {
 // block (row channel i x column channel j) and one run per stretch of the
 // block that is contiguous in C (the leading output dimensions whose strides
 // are those of a dense array).  Returns false, adding nothing, when the runs
-// would be short (under 4 elements on average) or an extent or stride does
-// not fit the decoder.
+// would be short (under 4 elements on average) or a block does not fit the
+// decoder's 24-bit arithmetic (2^24 elements or more, an operand offset or
+// the A~ column stride 2^24 or more).
 bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Group& cg,
                      const std::vector<tk::SkChan>& chans, int32_t rbase, int32_t cbase,
                      const std::vector<PairDesc>& pairs, int32_t pbase, const std::vector<int>& src, bool scatter,
@@ -623,16 +627,18 @@ bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Gro
           b.so[n] = pd.S[4 + m];
           b.bmask |= 1u << n;
         }
-        if (b.dim[n] >= (int64_t(1) << 24) || b.str[n] * b.dim[n] > INT32_MAX) return false;
       }
       b.count = int64_t(rc.count) * cc.count;
+      int64_t amax = 0, bmax = 0;
+      for (int n = 0; n < nout; ++n) ((b.bmask >> n) & 1u ? bmax : amax) += (b.dim[n] - 1) * b.str[n];
+      if (b.count >= kRunLimit || amax >= kRunLimit || bmax >= kRunLimit) return false;
       int64_t run = 1;
       for (int n = 0; n < nout && (b.dim[n] == 1 || b.so[n] == run); ++n) run *= b.dim[n];
       b.runlen = run;
       nruns += b.count / run;
       nelem += b.count;
     }
-  if (nruns * 4 > nelem) return false;
+  if (nruns * 4 > nelem || M >= kRunLimit) return false;
   const int32_t dbase = checked_i32(static_cast<int64_t>(rs.decs.size()), "decoder table");
   for (int32_t i = 0; i < rg.n(); ++i)
     for (int32_t j = 0; j < cg.n(); ++j) {
@@ -646,14 +652,17 @@ bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Gro
       d.sign = pd.sign;
       d.a_buf = abuf;
       d.b_buf = bbuf;
-      d.bmask = b.bmask;
+      d.nd = 0;
       for (int n = 0; n < 8; ++n) {
+        if (b.dim[n] == 1) continue;  // its index is always 0
         uint32_t mag = 0;
         uint8_t shr = 0;
-        division_magic(static_cast<uint32_t>(b.dim[n]), &mag, &shr);
-        d.dimshr[n] = static_cast<uint32_t>(b.dim[n]) | (static_cast<uint32_t>(shr) << 24);
-        d.mag[n] = mag;
-        d.stride[n] = static_cast<int32_t>(b.str[n]);
+        division_magic(static_cast<uint32_t>(b.dim[n]), &mag, &shr);  // shr >= 32 for extents >= 2
+        tk::SkRunDim& o = d.dim[d.nd++];
+        o.mag = mag;
+        o.dimshr = static_cast<uint32_t>(b.dim[n]) | (static_cast<uint32_t>(shr - 32) << 24);
+        o.sa = (b.bmask >> n) & 1u ? 0u : static_cast<uint32_t>(b.str[n]);
+        o.sb = (b.bmask >> n) & 1u ? static_cast<uint32_t>(b.str[n]) : 0u;
       }
       rs.decs.push_back(d);
       for (int64_t lin0 = 0; lin0 < b.count; lin0 += b.runlen) {

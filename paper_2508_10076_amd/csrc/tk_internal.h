@@ -205,22 +205,27 @@ struct SkRun {
 };
 
 // One output block written through runs: its rows in A~, its first column
-// in B~, its sign, and per output dimension (output leg order; unused ones
-// of extent 1 and stride 0) the extent with its division magic and the
-// stride of the leg in A~ (a row leg) or in B~ (a column leg: bit set in
-// bmask; the stride then counts elements of B~, ldb included).
+// in B~, its sign, and its output dimensions of extent above 1 in the
+// output's leg order (first fastest): per dimension the division magic
+// (floor(x / d) = mulhi(x, mag) >> shift for x < 2^24), the extent, and the
+// strides of the leg in A~ and in B~ (one of them 0; the B~ stride counts
+// elements, ldb included).  Blocks hold fewer than 2^24 elements and every
+// operand offset inside a block is below 2^24.
+struct SkRunDim {
+  uint32_t mag;
+  uint32_t dimshr;  // extent | (shift - 32) << 24
+  uint32_t sa, sb;
+};
 struct SkRunDec {
   int64_t a, b;
   int32_t lda;
   float sign;
   int16_t a_buf, b_buf;
-  uint32_t bmask;
-  uint32_t dimshr[8];  // extent | shift << 24
-  uint32_t mag[8];
-  int32_t stride[8];
+  int32_t nd;
+  SkRunDim dim[8];
 };
 constexpr int kRunChunk = 4096;  // elements of one workgroup
-constexpr int kRunMax = 256;     // runs one workgroup touches at most
+constexpr int kRunMax = 128;     // runs one workgroup touches at most
 
 // Runs of small-K sectors sharing the same K (1..8).  Workgroup w covers
 // elements wstart[w] .. wstart[w+1]-1 of the concatenation; first[w] is the

@@ -146,37 +146,91 @@ __device__ __forceinline__ TK_GLOBAL T* buf_ptr_lane(const Ptrs& P, int id) {
   return (TK_GLOBAL T*)p;
 }
 
+// Index map of a workgroup's chunk of concatenated ranges (elements c0 ..
+// c0 + n - 1, n <= CHUNK; range i of the staged ones starts at relative
+// element s_r[i], range 0 at or before the chunk): s_idx[e] = the staged
+// range holding element c0 + e.  Each range marks its first element, then a
+// running maximum over the chunk (per thread over CHUNK / kThreads
+// consecutive entries, across the workgroup by shuffles and LDS) fills the
+// rest, since later ranges have larger indices.
+template <int CHUNK, typename IX>
+__device__ __forceinline__ void chunk_range_map(IX* s_idx, uint32_t* s_wmax, const int32_t* s_r, int nr, int n) {
+  constexpr int E = CHUNK / kThreads;
+  constexpr int PER = 16 / sizeof(IX);  // entries per 16-byte word
+  constexpr int BITS = 8 * sizeof(IX);
+  static_assert(E * kThreads == CHUNK && E % PER == 0, "chunk size");
+  uint4* s4 = reinterpret_cast<uint4*>(s_idx);
+  for (int e = threadIdx.x; e < CHUNK / PER; e += kThreads) s4[e] = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+  for (int i = 1 + threadIdx.x; i < nr; i += kThreads) {
+    const int p = s_r[i];
+    if (p > 0 && p < n) s_idx[p] = static_cast<IX>(i);
+  }
+  __syncthreads();
+  uint32_t loc[E];
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < E / PER; ++q) {
+    const uint4 w = s4[threadIdx.x * (E / PER) + q];
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+      m = max(m, (ws[h / (PER / 4)] >> (BITS * (h % (PER / 4)))) & ((1u << BITS) - 1u));
+      loc[q * PER + h] = m;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = m;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x = max(x, y);
+  }
+  if (lane == 63) s_wmax[wave] = x;
+  uint32_t ex = __shfl_up(x, 1, 64);
+  if (lane == 0) ex = 0;
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) ex = max(ex, s_wmax[w]);
+#pragma unroll
+  for (int q = 0; q < E / PER; ++q) {
+    uint32_t ws[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < PER; ++h) ws[h / (PER / 4)] |= max(ex, loc[q * PER + h]) << (BITS * (h % (PER / 4)));
+    s4[threadIdx.x * (E / PER) + q] = make_uint4(ws[0], ws[1], ws[2], ws[3]);
+  }
+  __syncthreads();
+}
+
 // Zero ranges: workgroup w covers virtual elements wstart[w] ..
 // wstart[w+1]-1 of the concatenated ranges (at most kZeroChunk elements in
-// at most kZeroMax ranges).  Its ranges are staged in LDS as (virtual
-// start, destination pointer minus virtual start); each element finds its
-// range by binary search there, so consecutive threads write consecutive
-// addresses however short the ranges are.
+// at most kZeroMax ranges).  Its ranges are staged in LDS as destination
+// pointers (minus the chunk-relative start); an index map gives each
+// element its range, so consecutive threads write consecutive addresses
+// however short the ranges are.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void zero_ranges_kernel(const ZeroRange* __restrict__ ranges, int nranges,
                                                                const int32_t* __restrict__ first,
                                                                const int64_t* __restrict__ wstart, Ptrs P,
                                                                double beta) {
-  __shared__ int64_t s_v[kZeroMax + 1];
   __shared__ TK_GLOBAL T* s_p[kZeroMax + 1];
+  __shared__ int32_t s_r[kZeroMax + 1];
+  __shared__ __align__(16) uint16_t s_idx[kZeroChunk];
+  __shared__ uint32_t s_wmax[kThreads / 64];
   const int64_t c0 = const_ptr(wstart)[blockIdx.x], c1 = const_ptr(wstart)[blockIdx.x + 1];
+  const int n = static_cast<int>(c1 - c0);
   const int r0 = const_ptr(first)[blockIdx.x];
   const int r1 = min(nranges, const_ptr(first)[blockIdx.x + 1] + 1);
   const int nr = min(r1 - r0, kZeroMax + 1);
   for (int i = threadIdx.x; i < nr; i += kThreads) {
     const ZeroRange zr = ranges[r0 + i];
-    s_v[i] = zr.vstart;
-    s_p[i] = buf_ptr_lane<T>(P, zr.buf) + (zr.off - zr.vstart);
+    const int64_t rel = zr.vstart - c0;  // <= 0 for range 0, in (0, n] for the others
+    s_r[i] = static_cast<int32_t>(max<int64_t>(rel, 0));
+    s_p[i] = buf_ptr_lane<T>(P, zr.buf) + (zr.off - rel);
   }
   __syncthreads();
-  for (int64_t v = c0 + threadIdx.x; v < c1; v += kThreads) {
-    int lo = 0, hi = nr - 1;  // largest i with s_v[i] <= v
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_v[mid] <= v) lo = mid;
-      else hi = mid - 1;
-    }
-    TK_GLOBAL T* d = s_p[lo] + v;
+  if (nr > 1) chunk_range_map<kZeroChunk, uint16_t>(s_idx, s_wmax, s_r, nr, n);
+  for (int e = threadIdx.x; e < n; e += kThreads) {
+    TK_GLOBAL T* d = s_p[nr > 1 ? s_idx[e] : 0] + e;
     *d = beta != 0.0 ? static_cast<T>(beta) * *d : static_cast<T>(0);
   }
 }
@@ -1079,91 +1133,93 @@ __global__ __launch_bounds__(kThreads) void smallk_blocks_kernel(const SkBlockTa
 
 // Output runs: workgroup w covers elements wstart[w] .. wstart[w+1]-1 of the
 // concatenated runs of one K.  Its runs (at most kRunMax + 1) are staged in
-// LDS with their block's operand pointers, sign and A~ stride; each element
-// finds its run by binary search, reads the block's dimensions from the
-// decoder (shared by the lanes of a run, so served by the cache), splits
-// its linear index over them and takes the K-term dot product of its row
-// of A~ and column of B~.  Consecutive threads write consecutive elements
-// of C however small the blocks are.
+// LDS with their block's operand pointers, sign, A~ stride and dimensions,
+// and an index map gives each element its run.  The element splits its
+// linear index over the dimensions (32-bit multiply-high division, 24-bit
+// products) and takes the K-term dot product of its row of A~ and column of
+// B~.  Consecutive threads write consecutive elements of C however small the
+// blocks are.
 template <typename T, int MODE, int KK>
 __global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __restrict__ runs, int nruns,
                                                                const int32_t* __restrict__ first,
                                                                const int64_t* __restrict__ wstart,
                                                                const SkRunDec* __restrict__ decs, Ptrs P,
                                                                double alpha, double beta) {
-  __shared__ int64_t s_v[kRunMax + 1];
+  static_assert(kRunMax < 255, "run index map is 8-bit");
   __shared__ TK_GLOBAL T* s_p[kRunMax + 1];
   __shared__ const TK_GLOBAL T* s_a[kRunMax + 1];
   __shared__ const TK_GLOBAL T* s_b[kRunMax + 1];
-  __shared__ int32_t s_d[kRunMax + 1], s_l[kRunMax + 1], s_lda[kRunMax + 1];
-  __shared__ uint32_t s_m[kRunMax + 1];
-  __shared__ float s_sg[kRunMax + 1];
+  __shared__ int4 s_i[kRunMax + 1];  // dimensions, lin0 - relative start, lda, sign bits
+  __shared__ SkRunDim s_dim[kRunMax + 1][8];
+  __shared__ int32_t s_r[kRunMax + 1];
+  __shared__ __align__(16) uint8_t s_idx[kRunChunk];
+  __shared__ uint32_t s_wmax[kThreads / 64];
   const int64_t c0 = const_ptr(wstart)[blockIdx.x], c1 = const_ptr(wstart)[blockIdx.x + 1];
+  const int n = static_cast<int>(c1 - c0);
   const int r0 = const_ptr(first)[blockIdx.x];
   const int r1 = min(nruns, const_ptr(first)[blockIdx.x + 1] + 1);
   const int nr = min(r1 - r0, kRunMax + 1);
   for (int i = threadIdx.x; i < nr; i += kThreads) {
     const SkRun rn = runs[r0 + i];
     const SkRunDec* dc = decs + rn.dec;
-    s_v[i] = rn.vstart;
-    s_p[i] = buf_ptr_lane<T>(P, rn.buf) + (rn.off - rn.vstart);
+    const int64_t rel = rn.vstart - c0;  // <= 0 for run 0, in (0, n] for the others
+    s_r[i] = static_cast<int32_t>(max<int64_t>(rel, 0));
+    s_p[i] = buf_ptr_lane<T>(P, rn.buf) + (rn.off - rel);
     s_a[i] = buf_ptr_lane<const T>(P, dc->a_buf) + dc->a;
     s_b[i] = buf_ptr_lane<const T>(P, dc->b_buf) + dc->b;
-    s_d[i] = rn.dec;
-    s_l[i] = rn.lin0;
-    s_lda[i] = dc->lda;
-    s_m[i] = dc->bmask;
-    s_sg[i] = dc->sign;
+    s_i[i] = make_int4(dc->nd, static_cast<int32_t>(rn.lin0 - rel), dc->lda, __float_as_int(dc->sign));
+  }
+  // the dimensions: 8 records of 16 bytes per run, one per thread in turn
+  for (int t = threadIdx.x; t < nr * 8; t += kThreads) {
+    const int i = t >> 3;
+    s_dim[i][t & 7] = decs[runs[r0 + i].dec].dim[t & 7];
   }
   __syncthreads();
+  if (nr > 1) chunk_range_map<kRunChunk, uint8_t>(s_idx, s_wmax, s_r, nr, n);
   constexpr int U = KK <= 2 ? 4 : 2;
-  for (int64_t e0 = c0; e0 < c1; e0 += kThreads * U) {
-    int lo[U];
-    int64_t ao[U], bo[U];
+  for (int e0 = 0; e0 < n; e0 += kThreads * U) {
+    int id[U];
+    uint32_t ao[U], bo[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t v = min(e0 + u * kThreads + threadIdx.x, c1 - 1);
-      int l = 0, h = nr - 1;  // largest i with s_v[i] <= v
-      while (l < h) {
-        const int mid = (l + h + 1) >> 1;
-        if (s_v[mid] <= v) l = mid;
-        else h = mid - 1;
-      }
-      lo[u] = l;
-      const SkRunDec* dc = decs + s_d[l];
-      uint32_t lin = static_cast<uint32_t>(s_l[l]) + static_cast<uint32_t>(v - s_v[l]);
-      const uint32_t bm = s_m[l];
-      int64_t a = 0, b = 0;
+      const int e = min(e0 + u * kThreads + static_cast<int>(threadIdx.x), n - 1);
+      const int l = nr > 1 ? s_idx[e] : 0;
+      id[u] = l;
+      const int4 inf = s_i[l];
+      uint32_t lin = static_cast<uint32_t>(inf.y + e);
+      uint32_t a = 0, b = 0;
 #pragma unroll
-      for (int o = 0; o < 8; ++o) {
-        const uint32_t ds = dc->dimshr[o];
-        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * dc->mag[o]) >> (ds >> 24));
-        const int64_t i = static_cast<int64_t>(lin - q * (ds & 0xffffffu)) * dc->stride[o];
-        lin = q;
-        if ((bm >> o) & 1u) b += i;
-        else a += i;
-      }
+      for (int o = 0; o < 8; ++o)
+        if (o < inf.x) {
+          const SkRunDim d = s_dim[l][o];
+          const uint32_t q = __umulhi(lin, d.mag) >> (d.dimshr >> 24);
+          const uint32_t i = lin - __umul24(q, d.dimshr & 0xffffffu);
+          lin = q;
+          a += __umul24(i, d.sa);
+          b += __umul24(i, d.sb);
+        }
       ao[u] = a;
       bo[u] = b;
     }
     double av[U][KK], bv[U][KK];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const TK_GLOBAL T* A = s_a[lo[u]] + ao[u];
-      const TK_GLOBAL T* B = s_b[lo[u]] + bo[u];
-      const int64_t lda = s_lda[lo[u]];
+      const TK_GLOBAL T* A = s_a[id[u]] + ao[u];
+      const TK_GLOBAL T* B = s_b[id[u]] + bo[u];
+      const int lda = s_i[id[u]].z;
 #pragma unroll
       for (int k = 0; k < KK; ++k) {
-        av[u][k] = static_cast<double>(A[k * lda]);
+        av[u][k] = static_cast<double>(A[static_cast<int64_t>(k) * lda]);
         bv[u][k] = static_cast<double>(B[k]);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t v = e0 + u * kThreads + threadIdx.x;
-      if (v >= c1) continue;
-      double x = alpha * static_cast<double>(s_sg[lo[u]]) * smallk_dot<MODE, KK>(av[u], bv[u]);
-      TK_GLOBAL T* d = s_p[lo[u]] + v;
+      const int e = e0 + u * kThreads + static_cast<int>(threadIdx.x);
+      if (e >= n) continue;
+      const float sg = __int_as_float(s_i[id[u]].w);
+      double x = alpha * static_cast<double>(sg) * smallk_dot<MODE, KK>(av[u], bv[u]);
+      TK_GLOBAL T* d = s_p[id[u]] + e;
       if (beta != 0.0) x += beta * static_cast<double>(*d);
       *d = static_cast<T>(x);
     }
