@@ -10,7 +10,9 @@ small-K stream and the zero blocks.  Inputs are resident in HBM before the
 timed region.  The same workload is then run with the fp32 and split-BF16x3
 GEMM modes and their errors against the fp64 CPU oracle are reported.
 
-Other workloads (--workload): heff_d1024; batch64 (64 independent
+Other workloads (--workload): heff_d1024; heff2_d1024 and heff2_d4096
+(two-site effective Hamiltonian y = L . W . W . x2 . R, four contractions,
+Alg. "Two-site Benchmark"); batch64 (64 independent
 rank-3 x rank-4 contractions, one persistent grouped launch replayed from a
 HIP graph, fp64 and fp32); peps (fermionic U(1) x fZ2 double layer
 E = A^dagger o A interleaved to rank 8, D = 16).
@@ -45,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024", "batch64", "peps"])
+    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024", "heff2_d1024", "heff2_d4096", "batch64", "peps"])
     ap.add_argument("--precision", default="native", choices=["native", "f32", "bf16x3"])
     ap.add_argument("--no-variants", action="store_true", help="skip the fp32 / bf16x3 side runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -223,9 +225,21 @@ def oracle_heff(cfg, cid, seconds):
     return y, reps, spent
 
 
-def bench_heff(args, tk, torch, np):
+def heff_workload(name):
+    """(config, seed id, description, D, charge range) of an H_eff workload."""
     from paper_2508_10076_amd import synth
-    cfg, cid = (synth.config3(), 3) if args.workload == "heff_d4096" else (synth.config2(), 2)
+    return {
+        "heff_d4096": (synth.config3, 3, "single-site H_eff apply y=L.W.x.R", 4096, 12),
+        "heff_d1024": (synth.config2, 2, "single-site H_eff apply y=L.W.x.R", 1024, 8),
+        "heff2_d1024": (lambda: synth.heff2_config(1024, 8, 3.0, 6), 6, "two-site H_eff apply y=L.W.W.x2.R", 1024, 8),
+        "heff2_d4096": (lambda: synth.heff2_config(4096, 12, 4.5, 7), 7, "two-site H_eff apply y=L.W.W.x2.R",
+                        4096, 12),
+    }[name]
+
+
+def bench_heff(args, tk, torch, np):
+    make_cfg, cid, desc, D, qr = heff_workload(args.workload)
+    cfg = make_cfg()
     ctx = tk.Context(0)
     stream = torch.cuda.Stream()
     H = Heff(tk, torch, cfg, cid, ctx, stream, args.precision)
@@ -233,14 +247,12 @@ def bench_heff(args, tk, torch, np):
     torch.cuda.synchronize()
     r = H.run(args.steps, args.warmup)
     pk = PEAK_KEY[args.precision]
-    D = 4096 if args.workload == "heff_d4096" else 1024
     out = {
         "metric": METRIC, "value": round(r["value"], 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "native" else args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{cfg['name']}: single-site H_eff apply y=L.W.x.R, U(1), D={D}, "
-                               f"charges -{12 if D == 4096 else 8}..{12 if D == 4096 else 8}",
+        "config": {"workload": f"{cfg['name']}: {desc}, U(1), D={D}, charges -{qr}..{qr}",
                    "precision": args.precision, "block_flops_per_step": H.flops, "parallelism": "1 GPU"},
         "pct_fp64_mfma_peak": round(100.0 * r["value"] / PEAK["f64"], 2),
         "timing": {"mode": "HIP graph replay of the whole application (eager launches: see eager_ms_per_step)",

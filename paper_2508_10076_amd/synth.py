@@ -109,6 +109,32 @@ def heff_config(D: int, qmax: int, sigma: float, config_id: int):
                 inputs=("x", "L", "W", "R"), output="y")
 
 
+# Two-site H_eff: x2[a', p1'; b', p2'] with the second physical leg in the
+# domain as P* (type V x P <- V x P*), contracted with L, W twice and R.
+HEFF2_CALLS = [
+    ("T1", "L", "x", dict(pA=(0, 2), qA=(1,), pB=(0,), qB=(1, 2, 3), pAB=(0, 3, 4), qAB=(1, 2))),
+    ("T2", "T1", "W", dict(pA=(0, 1, 2), qA=(3, 4), pB=(0, 2), qB=(1, 3), pAB=(0, 3, 1), qAB=(4, 2))),
+    ("T3", "T2", "W", dict(pA=(0, 1, 2), qA=(3, 4), pB=(0, 2), qB=(1, 3), pAB=(0, 1, 3), qAB=(4, 2))),
+    ("y", "T3", "R", dict(pA=(0, 1, 2), qA=(3, 4), pB=(0, 1), qB=(2,), pAB=(0, 1), qAB=(3, 2))),
+]
+
+
+def heff2_spaces(D: int, qmax: int, sigma: float):
+    V, t = heff_spaces(D, qmax, sigma)
+    t = dict(t)
+    t["x"] = dict(sym="U1", cod=(V, P_U1), dom=(V, dual(P_U1)))
+    return V, t
+
+
+def heff2_config(D: int, qmax: int, sigma: float, config_id: int):
+    """Two-site effective Hamiltonian  y = L . W . W . x2 . R  (Alg.
+    "Two-site Benchmark"; x2 : V x P <- V x P*) as four pairwise
+    contractions."""
+    V, t = heff2_spaces(D, qmax, sigma)
+    return dict(name=f"heff2_u1_D{D}", config=config_id, tensors=t, calls=HEFF2_CALLS,
+                inputs=("x", "L", "W", "R"), output="y")
+
+
 def config2():
     return heff_config(1024, 8, 3.0, 2)
 

@@ -180,6 +180,23 @@ def test_contract_plan_matches_oracle(sym):
         P.close()
 
 
+def test_heff2_plan_flops_match_oracle():
+    cfg = synth.heff2_config(1024, 8, 3.0, 6)
+    t = {k: lib_tensor(v) for k, v in cfg["tensors"].items()}
+    st = {k: ostruct(v) for k, v in cfg["tensors"].items()}
+    for out, a, b, call in cfg["calls"]:
+        Cn = tk.tensor_create_contracted(None, t[a], call["pA"], call["qA"], t[b], call["pB"], call["qB"],
+                                         call["pAB"], call["qAB"])
+        P = tk.Plan(None, t[a], call["pA"], call["qA"], t[b], call["pB"], call["qB"], call["pAB"], call["qAB"], Cn)
+        sC, _ = blockwise.contract(st[a], {}, call["pA"], call["qA"], st[b], {}, call["pB"], call["qB"],
+                                   call["pAB"], call["qAB"])
+        assert P.info()["flops"] == blockwise.useful_flops(st[a], call["pA"], call["qA"], st[b], call["pB"],
+                                                           call["qB"])
+        assert Cn.nelem == sC.size
+        t[out], st[out] = Cn, sC
+        P.close()
+
+
 def test_heff_plan_flops_match_survey_sizes():
     cfg = synth.config2()
     t = {k: lib_tensor(v) for k, v in cfg["tensors"].items()}

@@ -386,6 +386,29 @@ def test_heff_full_size_fp64(ctx, cfgfn, cid):
         assert_close(download(T[k]), v[k], vabs[k])
 
 
+def test_heff2_small_integer_bit_exact(ctx):
+    """Two-site H_eff chain (four contractions, two of them skinny) on
+    small-integer data: every intermediate equals the oracle's exactly."""
+    cfg = synth.heff2_config(64, 3, 1.2, 92)
+    rng = np.random.default_rng(92)
+    data = heff_data(cfg, 92, ints=True, rng=rng)
+    T = run_heff_gpu(ctx, cfg, data)
+    _, v = run_heff_oracle(cfg, data)
+    for k in ("T1", "T2", "T3", "y"):
+        assert np.array_equal(download(T[k]), v[k]), k
+
+
+def test_heff2_d1024_fp64(ctx):
+    cfg = synth.heff2_config(1024, 8, 3.0, 6)
+    data = heff_data(cfg, 6)
+    T = run_heff_gpu(ctx, cfg, data)
+    _, v = run_heff_oracle(cfg, data)
+    absdata = {k: np.abs(x) for k, x in data.items()}
+    _, vabs = run_heff_oracle(cfg, absdata)
+    for k in ("T1", "T2", "T3", "y"):
+        assert_close(download(T[k]), v[k], vabs[k])
+
+
 # ---------------------------------------------------------------------------
 # batches and graphs
 # ---------------------------------------------------------------------------

@@ -180,6 +180,30 @@ def test_heff_chain_equals_literal_einsum():
     assert np.allclose(cur_st["y"].to_dense(cur["y"]), expect, rtol=1e-12, atol=1e-12)
 
 
+def test_heff2_chain_equals_literal_einsum():
+    """Two-site H_eff apply: y[a,p1;b,p2] = L[a;a',w] W[w,p1;p1',w'] W[w',p2;p2',w'']
+    x2[a',p1';b',p2'] R[w'',b';b], with x2 : V x P <- V x P* (Alg. "Two-site
+    Benchmark")."""
+    from paper_2508_10076_amd import synth
+    from tests.helpers import ostruct
+    V, t = synth.heff2_spaces(24, 2, 1.0)
+    st = {k: ostruct(v) for k, v in t.items()}
+    rng = np.random.default_rng(6)
+    data = {k: rng.standard_normal(s.size) for k, s in st.items()}
+    dn = {k: st[k].to_dense(data[k]) for k in st}
+    expect = np.einsum("aAw,wpPW,WqQZ,APBQ,ZBb->apbq", dn["L"], dn["W"], dn["W"], dn["x"], dn["R"], optimize=True)
+    cur_st, cur = dict(st), dict(data)
+    for out, a, b, call in synth.HEFF2_CALLS:
+        s_out, v_out = blockwise.contract_storage(cur_st[a], cur[a], call["pA"], call["qA"],
+                                                  cur_st[b], cur[b], call["pB"], call["qB"],
+                                                  call["pAB"], call["qAB"])
+        cur_st[out], cur[out] = s_out, v_out
+    # the output has the type of x2
+    assert [(s.sectors, s.degs, s.dual) for s in cur_st["y"].cod + cur_st["y"].dom] == \
+        [(s.sectors, s.degs, s.dual) for s in st["x"].cod + st["x"].dom]
+    assert np.allclose(cur_st["y"].to_dense(cur["y"]), expect, rtol=1e-12, atol=1e-12)
+
+
 def test_block_diagonal_flop_count():
     """k equal blocks of size n/k cost 2 n^3 / k^2 instead of 2 n^3
     (section "What Is A Symmetry?")."""
