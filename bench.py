@@ -15,7 +15,9 @@ Other workloads (--workload): heff_d1024; heff2_d1024 and heff2_d4096
 Alg. "Two-site Benchmark"); batch64 (64 independent
 rank-3 x rank-4 contractions, one persistent grouped launch replayed from a
 HIP graph, fp64 and fp32); peps (fermionic U(1) x fZ2 double layer
-E = A^dagger o A interleaved to rank 8, D = 16).
+E = A^dagger o A interleaved to rank 8, D = 16); trace_d4096 (partial trace of
+a U(1) tensor V (x) Wm <- V (x) Wm over the Wm pair, Alg. "Abelian Tensor
+Trace", D = 4096).
 
 Prints ONE JSON line.  value = useful block flops (sum over coupled charges
 of 2 M N K) per second, whole job, with the whole application captured in
@@ -47,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024", "heff2_d1024", "heff2_d4096", "batch64", "peps"])
+    ap.add_argument("--workload", default="heff_d4096", choices=["heff_d4096", "heff_d1024", "heff2_d1024", "heff2_d4096", "batch64", "peps",
+                                                         "trace_d4096"])
     ap.add_argument("--precision", default="native", choices=["native", "f32", "bf16x3"])
     ap.add_argument("--no-variants", action="store_true", help="skip the fp32 / bf16x3 side runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -427,6 +430,53 @@ def bench_peps(args, tk, torch, np):
             "peps": res}
 
 
+def bench_trace(args, tk, torch, np):
+    from paper_2508_10076_amd import synth
+    from oracle.graded import Space, Structure
+    q, d = synth.gaussian_degeneracies(4096, 12, 4.5)
+    V = synth.u1_space(q, d)
+    t = dict(sym="U1", cod=[V, synth.WM_U1], dom=[V, synth.WM_U1])
+    ctx = tk.Context(0)
+    stream = torch.cuda.Stream()
+    A = tk.tensor_create(ctx, "U1", t["cod"], t["dom"])
+    A.storage[: A.nelem].copy_(torch.from_numpy(synth.normal(A.nelem, 8, 0)))
+    C = tk.tensor_create_traced(ctx, A, (0,), (2,), (1,), (3,))
+    # algorithmic work: every diagonal element of A (traced indices equal) read once, C written once
+    st = Structure("U1", [Space(s.sectors, s.degs, s.dual) for s in t["cod"]],
+                   [Space(s.sectors, s.degs, s.dual) for s in t["dom"]])
+    diag = 0
+    for _, ai, bi, _, _ in st.channels():
+        if ai[1] == bi[1]:
+            diag += st.cod[0].degs[ai[0]] * st.dom[0].degs[bi[0]] * st.cod[1].degs[ai[1]]
+    nbytes = 8.0 * (diag + C.nelem)
+
+    def step():
+        tk.tensor_trace(ctx, A, (0,), (2,), (1,), (3,), C_=C, stream=stream)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            step()
+    stream.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"metric": METRIC, "value": round(diag / (ms * 1e-3) / 1e12, 5), "unit": "TFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "trace_u1_D4096: tr over Wm of A : V x Wm <- V x Wm, U(1), D=4096, "
+                                   "charges -12..12", "A_entries": A.nelem, "C_entries": C.nelem,
+                       "diagonal_entries": diag, "parallelism": "1 GPU"},
+            "roofline": {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_PEAK, "unit": "GB/s",
+                         "frac": round(gbps / HBM_PEAK, 4), "traffic": None,
+                         "kernel": "trace_kernel (diagonal of A read once, C written once)"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -452,6 +502,8 @@ def main():
         out = bench_heff(args, tk, torch, np)
     elif args.workload == "batch64":
         out = bench_batch(args, tk, torch, np)
+    elif args.workload == "trace_d4096":
+        out = bench_trace(args, tk, torch, np)
     else:
         out = bench_peps(args, tk, torch, np)
     print(json.dumps(out), flush=True)

@@ -178,11 +178,37 @@ tk_status tk_tensor_create_contracted(tk_context* ctx, const tk_tensor* A, const
                                       void* device_buf, uint64_t buf_bytes, tk_tensor** out);
 tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* device_buf,
                                    uint64_t buf_bytes, tk_tensor** out);
+/* A tensor shaped as the partial trace of A (see tk_tensor_trace). */
+tk_status tk_tensor_create_traced(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                                  const int32_t* q, int32_t nq, const int32_t* t1, const int32_t* t2,
+                                  int32_t nt, void* device_buf, uint64_t buf_bytes, tk_tensor** out);
 
 /* ---- operations ------------------------------------------------------------
  * C = permute(A, (p, q)).  C must have the permuted spaces and A's dtype. */
 tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
                             const int32_t* q, int32_t nq, tk_tensor* C, void* stream);
+
+/* Partial trace, Alg. "Abelian Tensor Trace": C = alpha * tr(A) + beta * C,
+ * where legs t1[i] and t2[i] of A (nt pairs, 1..4) are closed with each
+ * other and the remaining legs form C's codomain (p) and domain (q), each
+ * indexing A's legs (0-based, codomain then domain); p, q, t1 and t2 list
+ * every leg of A exactly once.  A traced pair must carry the same sectors
+ * and degeneracies and be a vector / co-vector pair in A's bra-ket reading
+ * (a codomain leg over V with a domain leg over V, or two codomain legs over
+ * V and V*, ...); the trace is diagonal in the sector and in the index.
+ * C's spaces are those of tk_tensor_create_traced (the free legs placed as
+ * by tk_tensor_permute).  Fermionic symmetries use the graph semantics of
+ * the section on fermions (twist pushed into the right evaluation): a
+ * channel's sign is the Koszul sign of reordering A's legs so that every
+ * traced pair is adjacent with its dual leg first, followed by C's legs.
+ * Errors: TK_ERR_INVALID_ARG (bad lists, null or aliased tensors),
+ * TK_ERR_SPACE_MISMATCH (pair spaces, C's spaces), TK_ERR_DTYPE,
+ * TK_ERR_UNSUPPORTED (more than 4 pairs, strides beyond 32 bits). A and C
+ * are caller-owned; the plan is cached in the context; the launch is
+ * enqueued on `stream`. */
+tk_status tk_tensor_trace(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                          const int32_t* q, int32_t nq, const int32_t* t1, const int32_t* t2, int32_t nt,
+                          double alpha, double beta, tk_tensor* C, void* stream);
 
 /* C = alpha * permute(permute(A,(pA,qA)) o permute(B,(pB,qB)), (pAB,qAB)) + beta * C.
  * (pA, qA): free legs of A (codomain of A~) and contracted legs (domain of

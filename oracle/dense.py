@@ -165,6 +165,16 @@ def contract_dense(sym: str, A, Acod, Adom, pA, qA, B, Bcod, Bdom, pB, qB, pAB, 
     return graph_evaluate(sym, [(A, Acod, Adom), (B, Bcod, Bdom)], pairs, out_cod, out_dom)
 
 
+def trace_dense(sym: str, T: np.ndarray, cod, dom, p, q, t1, t2):
+    """Partial trace (Alg. "Abelian Tensor Trace") as a graph: legs t1[i] and
+    t2[i] of the one tensor are a contracted pair (closed with the dual leg
+    first, as every pair of the evaluator), the free legs are the output's
+    codomain p and domain q.  For a bosonic symmetry this is the einsum with
+    a repeated index per pair.  Returns (C, cod, dom)."""
+    pairs = [((0, a), (0, b)) for a, b in zip(t1, t2)]
+    return graph_evaluate(sym, [(T, cod, dom)], pairs, [(0, i) for i in p], [(0, j) for j in q])
+
+
 # ---------------------------------------------------------------------------
 # adjacent-swap decomposition (used by the tests to pin the exchange sign)
 # ---------------------------------------------------------------------------

@@ -740,13 +740,13 @@ constexpr int64_t kSkStrip = 16384;
 // leg order) as chunked tasks, merging dims contiguous in r, s and dst.
 // Pack consecutive tasks into workgroups of about kPermChunk elements.
 template <typename TL>
-void pack_workgroups(TL& tl) {
+void pack_workgroups(TL& tl, int64_t limit = tk::kPermChunk) {
   tl.wg_first.assign(1, 0);
   int64_t acc = 0;
   int ntask = 0;
   for (size_t i = 0; i < tl.tasks.size(); ++i) {
     const int c = tl.tasks[i].count;
-    if (ntask > 0 && (acc + c > tk::kPermChunk || ntask >= 64)) {
+    if (ntask > 0 && (acc + c > limit || ntask >= 64)) {
       tl.wg_first.push_back(static_cast<int32_t>(i));
       acc = 0;
       ntask = 0;
@@ -853,6 +853,128 @@ void plan_permute_tasks(const Structure& A, const std::vector<int>& p, const std
   });
 }
 
+// Partial trace (Alg. "Abelian Tensor Trace"): legs t1[i] and t2[i] of A are
+// closed with each other, the free legs form C's codomain p and domain q.
+bool lin_dual(const Structure& A, int l) { return A.leg(l).dual != (l >= A.N1()); }
+
+void check_trace_lists(const Structure& A, const std::vector<int>& p, const std::vector<int>& q,
+                       const std::vector<int>& t1, const std::vector<int>& t2) {
+  const int N = A.N();
+  if (t1.empty() || t1.size() != t2.size()) fail(TK_ERR_INVALID_ARG, "a trace needs matching, non-empty leg pair lists");
+  if (t1.size() > static_cast<size_t>(tk::kMaxTracePairs)) fail(TK_ERR_UNSUPPORTED, "more than 4 traced leg pairs");
+  std::vector<char> seen(N, 0);
+  for (const auto* v : {&p, &q, &t1, &t2})
+    for (int x : *v) {
+      if (x < 0 || x >= N || seen[x]) fail(TK_ERR_INVALID_ARG, "(p, q, t1, t2) must list every leg exactly once");
+      seen[x] = 1;
+    }
+  if (static_cast<int>(p.size() + q.size() + t1.size() + t2.size()) != N)
+    fail(TK_ERR_INVALID_ARG, "(p, q, t1, t2) must list every leg exactly once");
+  if (p.size() > TK_MAX_LEGS || q.size() > TK_MAX_LEGS) fail(TK_ERR_UNSUPPORTED, "too many legs on one side");
+  for (size_t i = 0; i < t1.size(); ++i) {
+    const Space &x = A.leg(t1[i]), &y = A.leg(t2[i]);
+    if (x.q != y.q || x.p != y.p || x.deg != y.deg) fail(TK_ERR_SPACE_MISMATCH, "traced legs carry different spaces");
+    if (lin_dual(A, t1[i]) == lin_dual(A, t2[i]))
+      fail(TK_ERR_SPACE_MISMATCH, "traced legs are not a vector / co-vector pair");
+  }
+}
+
+// Leg pairs whose order flips between A's bra-ket reading (codomain, then
+// domain reversed) and the order in which the graph closes the trace: each
+// traced pair adjacent with its dual (in that reading) leg first, then the
+// free legs in C's bra-ket reading.
+std::vector<std::pair<int, int>> trace_exchanged_pairs(const Structure& A, const std::vector<int>& p,
+                                                       const std::vector<int>& q, const std::vector<int>& t1,
+                                                       const std::vector<int>& t2) {
+  const int N1 = A.N1(), N = A.N();
+  std::vector<int> pos_in(N), pos_out(N), target;
+  for (int l = 0; l < N1; ++l) pos_in[l] = l;
+  for (int l = N1; l < N; ++l) pos_in[l] = N - 1 - (l - N1);
+  for (size_t i = 0; i < t1.size(); ++i) {
+    const bool xd = lin_dual(A, t1[i]);
+    target.push_back(xd ? t1[i] : t2[i]);
+    target.push_back(xd ? t2[i] : t1[i]);
+  }
+  target.insert(target.end(), p.begin(), p.end());
+  target.insert(target.end(), q.rbegin(), q.rend());
+  for (int k = 0; k < N; ++k) pos_out[target[k]] = k;
+  std::vector<std::pair<int, int>> r;
+  for (int x = 0; x < N; ++x)
+    for (int y = 0; y < N; ++y)
+      if (pos_in[x] < pos_in[y] && pos_out[x] > pos_out[y]) r.emplace_back(x, y);
+  return r;
+}
+
+// output elements per trace task: small, so that a trace with few large
+// output blocks still spreads over every CU (each element gathers several
+// diagonal entries, so the kernel is latency- rather than bandwidth-bound)
+constexpr int64_t kTraceChunk = 512;
+
+struct TracePlan {
+  std::shared_ptr<Structure> A, C;
+  TaskListT<tk::TraceTask> tl;
+  std::vector<tk::TraceContrib> contribs;
+  DevBuf d_contribs;
+};
+
+void plan_trace_tasks(const Structure& A, const std::vector<int>& p, const std::vector<int>& q,
+                      const std::vector<int>& t1, const std::vector<int>& t2, const Structure& C, TracePlan& tp) {
+  const bool ferm = A.si.fermionic;
+  const auto pairs = ferm ? trace_exchanged_pairs(A, p, q, t1, t2) : std::vector<std::pair<int, int>>{};
+  std::vector<int> src(p);
+  src.insert(src.end(), q.begin(), q.end());
+  const int n = static_cast<int>(src.size()), nt = static_cast<int>(t1.size());
+  std::vector<uint8_t> otup(std::max(n, 1));
+  int64_t idim[TK_MAX_RANK], istr[TK_MAX_RANK], odim[TK_MAX_RANK], ostr[TK_MAX_RANK];
+  std::unordered_map<int64_t, std::vector<tk::TraceContrib>> by_block;  // output block offset -> inputs
+  for_each_block(A, [&](int s, int32_t, int32_t, const uint8_t* tup, int64_t off) {
+    for (int k = 0; k < nt; ++k)
+      if (tup[t1[k]] != tup[t2[k]]) return;  // the pairing is diagonal in the sector
+    for (int m = 0; m < n; ++m) otup[m] = tup[src[m]];
+    const BlockLoc b = locate(C, otup.data());
+    if (b.sector < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: C lacks a channel of the trace");
+    block_strides(A, tup, A.R[s], idim, istr);
+    tk::TraceContrib c{};
+    c.src = off;
+    c.sign = (ferm && channel_parity(A, tup, pairs)) ? -1.0f : 1.0f;
+    c.nd = nt;
+    for (int m = 0; m < n; ++m) c.ss[m] = checked_i32(istr[src[m]], "stride");
+    for (int k = 0; k < nt; ++k) {
+      c.dd[k] = checked_i32(idim[t1[k]], "degeneracy");
+      c.dstr[k] = checked_i32(istr[t1[k]] + istr[t2[k]], "stride");
+    }
+    by_block[b.offset].push_back(c);
+  });
+  for_each_block(C, [&](int s, int32_t, int32_t, const uint8_t* ot, int64_t off) {
+    block_strides(C, ot, C.R[s], odim, ostr);
+    const int32_t c0 = checked_i32(static_cast<int64_t>(tp.contribs.size()), "trace contributions");
+    auto it = by_block.find(off);
+    if (it != by_block.end()) tp.contribs.insert(tp.contribs.end(), it->second.begin(), it->second.end());
+    const int32_t c1 = checked_i32(static_cast<int64_t>(tp.contribs.size()), "trace contributions");
+    int64_t total = 1;
+    for (int m = 0; m < n; ++m) total *= odim[m];
+    if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "trace output block larger than 2^31 elements");
+    for (int64_t s0 = 0; s0 < total; s0 += kTraceChunk) {
+      tk::TraceTask t{};
+      t.dst = off;
+      t.n = n;
+      t.start = static_cast<int32_t>(s0);
+      t.count = static_cast<int32_t>(std::min<int64_t>(kTraceChunk, total - s0));
+      t.c0 = c0;
+      t.c1 = c1;
+      t.src_buf = tk::kBufA;
+      t.dst_buf = tk::kBufC;
+      for (int m = 0; m < tk::kMaxDims; ++m) {
+        t.dim[m] = m < n ? checked_i32(odim[m], "dim") : 1;
+        t.ds[m] = m < n ? checked_i32(ostr[m], "stride") : 0;
+        division_magic(static_cast<uint32_t>(t.dim[m]), &t.mag[m], &t.shr[m]);
+      }
+      tp.tl.tasks.push_back(t);
+    }
+  });
+  pack_workgroups(tp.tl, kTraceChunk);
+}
+
 // Whether a block with these dims and strides fills one contiguous range
 // (its non-unit dims, ordered by stride, are densely packed from stride 1);
 // *span = number of elements.
@@ -885,6 +1007,7 @@ struct tk_context {
   std::mutex mu;
   std::unordered_map<std::string, std::shared_ptr<tk_plan>> plans;
   std::unordered_map<std::string, std::shared_ptr<struct PermPlan>> perm_plans;
+  std::unordered_map<std::string, std::shared_ptr<struct TracePlan>> trace_plans;
 };
 
 struct tk_tensor {
@@ -1868,6 +1991,19 @@ tk_status tk_tensor_create_permuted(tk_context* ctx, const tk_tensor* A, const i
   });
 }
 
+tk_status tk_tensor_create_traced(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                                  const int32_t* q, int32_t nq, const int32_t* t1, const int32_t* t2, int32_t nt,
+                                  void* device_buf, uint64_t buf_bytes, tk_tensor** out) {
+  return guarded([&] {
+    if (!A || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto pv = to_vec(p, np, "p"), qv = to_vec(q, nq, "q"), a = to_vec(t1, nt, "t1"), b = to_vec(t2, nt, "t2");
+    check_trace_lists(*A->st, pv, qv, a, b);
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    *out = new_tensor(ctx, get_structure(A->st->sym, c, d), A->dtype, device_buf, buf_bytes);
+  });
+}
+
 tk_status tk_tensor_create_contracted(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
                                       const int32_t* qA, int32_t nqA, const tk_tensor* B, const int32_t* pB,
                                       int32_t npB, const int32_t* qB, int32_t nqB, const int32_t* pAB, int32_t npAB,
@@ -1949,6 +2085,52 @@ tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* 
                                  static_cast<const int32_t*>(pp->tl.d_wg.p), pp->tl.nwg(), ptrs, 1.0, 0.0,
                                  static_cast<hipStream_t>(stream)),
               "permute launch");
+  });
+}
+
+tk_status tk_tensor_trace(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,
+                          int32_t nq, const int32_t* t1, const int32_t* t2, int32_t nt, double alpha, double beta,
+                          tk_tensor* C, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !C) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (A->dtype != C->dtype) fail(TK_ERR_DTYPE, "dtype mismatch");
+    if (!A->data && A->st->size) fail(TK_ERR_INVALID_ARG, "A has no data");
+    if (!C->data && C->st->size) fail(TK_ERR_INVALID_ARG, "C has no data");
+    if (A->data && A->data == C->data) fail(TK_ERR_INVALID_ARG, "C aliases A");
+    auto pv = to_vec(p, np, "p"), qv = to_vec(q, nq, "q"), a = to_vec(t1, nt, "t1"), b = to_vec(t2, nt, "t2");
+    check_trace_lists(*A->st, pv, qv, a, b);
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    if (c != C->st->cod || d != C->st->dom) fail(TK_ERR_SPACE_MISMATCH, "C does not have the traced spaces");
+    std::string key = "T#" + A->st->sig + "#" + C->st->sig + "#";
+    for (const auto* v : {&pv, &qv, &a, &b}) {
+      for (int x : *v) key += std::to_string(x) + ",";
+      key += "/";
+    }
+    std::shared_ptr<TracePlan> tp;
+    {
+      std::lock_guard<std::mutex> g(ctx->mu);
+      auto it = ctx->trace_plans.find(key);
+      if (it != ctx->trace_plans.end()) tp = it->second;
+    }
+    if (!tp) {
+      tp = std::make_shared<TracePlan>();
+      tp->A = A->st;
+      tp->C = C->st;
+      plan_trace_tasks(*A->st, pv, qv, a, b, *C->st, *tp);
+      tp->tl.upload();
+      tp->d_contribs.upload(tp->contribs);
+      std::lock_guard<std::mutex> g(ctx->mu);
+      ctx->trace_plans[key] = tp;
+    }
+    tk::Ptrs ptrs{};
+    ptrs.p[tk::kBufA] = A->data;
+    ptrs.p[tk::kBufC] = C->data;
+    hip_check(tk::launch_trace(A->dtype, static_cast<const tk::TraceTask*>(tp->tl.d_tasks.p),
+                               static_cast<const int32_t*>(tp->tl.d_wg.p), tp->tl.nwg(),
+                               static_cast<const tk::TraceContrib*>(tp->d_contribs.p), ptrs, alpha, beta,
+                               static_cast<hipStream_t>(stream)),
+              "trace launch");
   });
 }
 

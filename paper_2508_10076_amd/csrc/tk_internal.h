@@ -238,6 +238,36 @@ hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs
 // wstart[w] .. wstart[w+1]-1; first[w] is the range holding wstart[w].
 hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first,
                               const int64_t* wstart, int nwg, const Ptrs& ptrs, double beta, hipStream_t stream);
+// Partial trace (Alg. "Abelian Tensor Trace"): one chunk of one output block
+// of C, elements start .. start + count - 1 of its linear order over dim
+// (first fastest; destination offset sum i_d ds[d]).  Its value is the sum,
+// over contributions c0 .. c1 - 1 (the input channels whose free legs give
+// this block and whose traced pairs carry equal sectors), of the
+// contribution's sign times its sum along the traced diagonal.
+struct TraceTask {
+  int64_t dst;
+  int32_t n, count, start, c0, c1;
+  int16_t src_buf, dst_buf;
+  int32_t dim[kMaxDims];
+  int32_t ds[kMaxDims];
+  uint32_t mag[kMaxDims];
+  uint8_t shr[kMaxDims];
+};
+// One input channel feeding an output block: its first element in A, per
+// output dimension its stride in A, and per traced pair the degeneracy and
+// one diagonal step (the sum of the two legs' strides).
+constexpr int kMaxTracePairs = 4;
+struct TraceContrib {
+  int64_t src;
+  float sign;
+  int32_t nd;
+  int32_t ss[kMaxDims];
+  int32_t dd[kMaxTracePairs];
+  int32_t dstr[kMaxTracePairs];
+};
+hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_first, int nwg,
+                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta,
+                        hipStream_t stream);
 // Small-K sector GEMM tasks that all share the same K (1..8): one
 // workgroup per task.
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

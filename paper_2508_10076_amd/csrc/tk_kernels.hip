@@ -135,6 +135,78 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
   for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T>(tasks + t, P, alpha, beta, lane, 64);
 }
 
+// Partial trace: thread per output element; the element's index in the
+// block is split over the output dimensions once, then each contribution
+// adds sign * (sum along its traced diagonal), and the element is written
+// once (alpha times the trace plus beta times the old value).
+template <typename T>
+__device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, const TraceContrib* __restrict__ cs,
+                                           const Ptrs& P, double alpha, double beta, int lt, int nthr) {
+  const int n = tk->n, count = tk->count, c0 = tk->c0, c1 = tk->c1;
+  const uint32_t start = static_cast<uint32_t>(tk->start);
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, tk->src_buf);
+  for (int e = lt; e < count; e += nthr) {
+    uint32_t lin = start + static_cast<uint32_t>(e);
+    int32_t idx[kMaxDims];
+    int64_t dof = 0;
+#pragma unroll
+    for (int d = 0; d < kMaxDims; ++d) {
+      idx[d] = 0;
+      if (d < n) {
+        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
+        const uint32_t i = lin - q * static_cast<uint32_t>(tk->dim[d]);
+        lin = q;
+        idx[d] = static_cast<int32_t>(i);
+        dof += static_cast<int64_t>(i) * tk->ds[d];
+      }
+    }
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) {
+      const TraceContrib* cb = cs + c;
+      int64_t base = cb->src;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d)
+        if (d < n) base += static_cast<int64_t>(idx[d]) * cb->ss[d];
+      const int nd = cb->nd;
+      int32_t t[kMaxTracePairs] = {0, 0, 0, 0};
+      double sum = 0.0;
+      for (;;) {  // every diagonal index of the traced pairs, first pair fastest
+        int64_t o = base;
+#pragma unroll
+        for (int j = 0; j < kMaxTracePairs; ++j)
+          if (j < nd) o += static_cast<int64_t>(t[j]) * cb->dstr[j];
+        sum += static_cast<double>(src[o]);
+        int j = 0;
+        for (; j < nd; ++j) {
+          if (++t[j] < cb->dd[j]) break;
+          t[j] = 0;
+        }
+        if (j == nd) break;
+      }
+      acc += static_cast<double>(cb->sign) * sum;
+    }
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * static_cast<double>(dst[dof]);
+    dst[dof] = static_cast<T>(v);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __restrict__ tasks,
+                                                         const int32_t* __restrict__ wg_first,
+                                                         const TraceContrib* __restrict__ cs, Ptrs P, double alpha,
+                                                         double beta) {
+  const int t0 = wg_first[blockIdx.x];
+  const int t1 = wg_first[blockIdx.x + 1];
+  if (t1 - t0 == 1) {
+    trace_task<T>(tasks + t0, cs, P, alpha, beta, threadIdx.x, kThreads);
+    return;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) trace_task<T>(tasks + t, cs, P, alpha, beta, lane, 64);
+}
+
 // Buffer id -> base address with a per-lane id (a select chain over the
 // plan's buffers, or the batch's table).
 template <typename T>
@@ -1238,6 +1310,19 @@ hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, c
   else
     hipLaunchKernelGGL(zero_ranges_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, ranges, nranges, first,
                        wstart, ptrs, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_first, int nwg,
+                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta,
+                        hipStream_t stream) {
+  if (nwg <= 0) return hipSuccess;
+  if (dtype == 0)
+    hipLaunchKernelGGL(trace_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs,
+                       alpha, beta);
+  else
+    hipLaunchKernelGGL(trace_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs,
+                       alpha, beta);
   return hipGetLastError();
 }
 

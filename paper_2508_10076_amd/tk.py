@@ -63,6 +63,10 @@ _SIGS = {
                                     C.c_int32, _I32P, C.c_int32, _I32P, C.c_int32, _P, C.c_uint64, C.POINTER(_P)],
     "tk_tensor_create_adjoint": [_P, _P, _P, C.c_uint64, C.POINTER(_P)],
     "tk_tensor_permute": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _P],
+    "tk_tensor_create_traced": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _P,
+                                C.c_uint64, C.POINTER(_P)],
+    "tk_tensor_trace": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, C.c_double,
+                        C.c_double, _P, _P],
     "tk_tensor_contract": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I32P, C.c_int32, _I32P, C.c_int32,
                            _I32P, C.c_int32, _I32P, C.c_int32, C.c_double, C.c_double, C.c_int32, _P, _P],
     "tk_tensor_adjoint": [_P, _P, _P, _P],
@@ -311,6 +315,24 @@ def tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB):
     (a1, n1), (a2, n2), (b1, m1), (b2, m2), (c1, k1), (c2, k2) = lists
     return Tensor._derived(ctx, lambda c, *r: lib.tk_tensor_create_contracted(
         c, A.h, a1, n1, a2, n2, B.h, b1, m1, b2, m2, c1, k1, c2, k2, *r))
+
+
+def tensor_create_traced(ctx, A, p, q, t1, t2):
+    (pa, npa), (qa, nqa), (a, na), (b, nb) = [_ilist(v) for v in (p, q, t1, t2)]
+    if na != nb:
+        raise ValueError("t1 and t2 differ in length")
+    return Tensor._derived(ctx, lambda c, *r: lib.tk_tensor_create_traced(c, A.h, pa, npa, qa, nqa, a, b, na, *r))
+
+
+def tensor_trace(ctx, A, p, q, t1, t2, alpha=1.0, beta=0.0, C_=None, stream=None):
+    if C_ is None:
+        C_ = tensor_create_traced(ctx, A, p, q, t1, t2)
+    (pa, npa), (qa, nqa), (a, na), (b, nb) = [_ilist(v) for v in (p, q, t1, t2)]
+    if na != nb:
+        raise ValueError("t1 and t2 differ in length")
+    _check(lib.tk_tensor_trace(ctx.h, A.h, pa, npa, qa, nqa, a, b, na, float(alpha), float(beta), C_.h,
+                               _stream(stream)))
+    return C_
 
 
 def tensor_create_adjoint(ctx, A):

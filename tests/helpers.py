@@ -51,3 +51,57 @@ def brute_channels(sym_fuse, unit, spaces_cod, spaces_dom, label):
 
 def int_data(n, rng, lo=-3, hi=3):
     return rng.integers(lo, hi + 1, size=n).astype(np.float64)
+
+
+def trace_case(rng, sym: str, npairs: int = 1, max_free: int = 3):
+    """A random tensor with npairs traceable leg pairs (each a vector /
+    co-vector pair over one space: a codomain and a domain leg over X, or X
+    and X* on the same side) plus up to max_free free legs, and a random
+    arrangement of the free legs.  Returns (tensor dict, p, q, t1, t2)."""
+    from paper_2508_10076_amd import synth
+    while True:
+        cod, dom, pairs = [], [], []
+        for _ in range(npairs):
+            X = synth.random_space(rng, sym, max_deg=3)
+            kind = int(rng.integers(0, 3))
+            if kind == 0:
+                cod.append(("t", X)), dom.append(("t", X))
+            elif kind == 1:
+                cod.append(("t", X)), cod.append(("t", synth.dual(X)))
+            else:
+                dom.append(("t", X)), dom.append(("t", synth.dual(X)))
+            pairs.append(kind)
+        for _ in range(int(rng.integers(0, max_free + 1))):
+            (cod if rng.random() < 0.5 else dom).append(("f", synth.random_space(rng, sym, max_deg=3)))
+        if len(cod) > 4 or len(dom) > 4:
+            continue
+        cod = [cod[i] for i in rng.permutation(len(cod))] if cod else cod
+        dom = [dom[i] for i in rng.permutation(len(dom))] if dom else dom
+        legs = cod + dom
+        # pair the traced legs: an X leg with its partner (same space, opposite reading)
+        used, t1, t2 = set(), [], []
+        for a in range(len(legs)):
+            if legs[a][0] != "t" or a in used:
+                continue
+            for b in range(a + 1, len(legs)):
+                if legs[b][0] != "t" or b in used:
+                    continue
+                A, B = legs[a][1], legs[b][1]
+                if A.sectors != B.sectors or A.degs != B.degs:
+                    continue
+                da = A.dual != (a >= len(cod))
+                db = B.dual != (b >= len(cod))
+                if da != db:
+                    used |= {a, b}
+                    t1.append(a)
+                    t2.append(b)
+                    break
+        if len(t1) != npairs:
+            continue
+        free = [l for l in range(len(legs)) if l not in used]
+        free = [free[i] for i in rng.permutation(len(free))] if free else free
+        n1 = int(rng.integers(0, len(free) + 1))
+        t = dict(sym=sym, cod=[s for _, s in cod], dom=[s for _, s in dom])
+        if ostruct(t).size == 0:
+            continue
+        return t, tuple(free[:n1]), tuple(free[n1:]), tuple(t1), tuple(t2)

@@ -215,6 +215,48 @@ def test_heff_plan_flops_match_survey_sizes():
     assert 4.0e8 < total < 4.8e8
 
 
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_traced_spaces_match_oracle(sym):
+    """tk_tensor_create_traced gives the spaces of the dense trace oracle
+    (the free legs placed as by a permute)."""
+    from oracle import dense
+    from tests.helpers import trace_case
+    rng = np.random.default_rng(810 + len(sym))
+    for trial in range(12):
+        t, p, q, t1, t2 = trace_case(rng, sym, npairs=1 + trial % 2)
+        st = ostruct(t)
+        A = lib_tensor(t)
+        Cn = tk.tensor_create_traced(None, A, p, q, t1, t2)
+        _, ocod, odom = dense.trace_dense(sym, np.zeros([s.dim for s in st.cod + st.dom]), st.cod, st.dom,
+                                          p, q, t1, t2)
+        got = [Cn.space(l) for l in range(Cn.ncod + Cn.ndom)]
+        want = [(list(s.sectors), list(s.degs), bool(s.dual)) for s in ocod + odom]
+        assert [(list(map(tuple, g[0])), list(g[1]), g[2]) for g in got] == \
+            [(list(map(tuple, w[0])), w[1], w[2]) for w in want], (sym, trial)
+
+
+def test_trace_error_paths():
+    V = synth.u1_space([-1, 0, 1], [1, 2, 1])
+    P = synth.P_U1
+    A = tk.tensor_create(None, "U1", [V, P], [V, P])
+    with pytest.raises(tk.TkError) as e:     # a leg listed twice
+        tk.tensor_create_traced(None, A, [1, 1], [], [0], [2])
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:     # a leg missing
+        tk.tensor_create_traced(None, A, [1], [], [0], [2])
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:     # no pair
+        tk.tensor_create_traced(None, A, [0, 1], [2, 3], [], [])
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:     # V against P
+        tk.tensor_create_traced(None, A, [1], [2], [0], [3])
+    assert e.value.status == 2
+    B = tk.tensor_create(None, "U1", [V, V, P], [])
+    with pytest.raises(tk.TkError) as e:     # two codomain legs over V: not a vector / co-vector pair
+        tk.tensor_create_traced(None, B, [2], [], [0], [1])
+    assert e.value.status == 2
+
+
 def test_error_paths():
     V = synth.u1_space([-1, 0, 1], [1, 2, 1])
     P = synth.P_U1

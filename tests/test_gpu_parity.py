@@ -386,6 +386,64 @@ def test_heff_full_size_fp64(ctx, cfgfn, cid):
         assert_close(download(T[k]), v[k], vabs[k])
 
 
+# ---------------------------------------------------------------------------
+# partial trace (Alg. "Abelian Tensor Trace")
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_trace_against_dense_oracle(ctx, sym):
+    """GPU partial trace against the dense graph oracle: one and two traced
+    pairs in every orientation, random free-leg arrangements (including a
+    full trace to a scalar), small-integer data, alpha/beta, bit-exact."""
+    from tests.helpers import trace_case
+    rng = np.random.default_rng(8200 + len(sym))
+    for trial in range(10):
+        t, p, q, t1, t2 = trace_case(rng, sym, npairs=1 + trial % 2)
+        st = ostruct(t)
+        a = int_vec(rng, st.size)
+        A = make(ctx, t, a)
+        Cg = tk.tensor_create_traced(ctx, A, p, q, t1, t2)
+        D, ocod, odom = dense.trace_dense(sym, st.to_dense(a), st.cod, st.dom, p, q, t1, t2)
+        stC = Structure(sym, ocod, odom)
+        assert stC.size == Cg.nelem
+        c0 = int_vec(rng, Cg.nelem)
+        upload(Cg, c0)
+        tk.tensor_trace(ctx, A, p, q, t1, t2, alpha=2.0, beta=-1.0, C_=Cg)
+        want = 2.0 * stC.from_dense(D, check_zero=True) - c0
+        assert np.array_equal(download(Cg), want), (sym, trial, p, q, t1, t2)
+
+
+def test_trace_large_u1_fp64(ctx):
+    """A U(1) tensor V (x) Wm <- V (x) Wm (D=1024) traced over the Wm pair,
+    against the dense oracle's blocks, fp64 within 1e-12."""
+    q, d = synth.gaussian_degeneracies(1024, 8, 3.0)
+    V = synth.u1_space(q, d)
+    t = dict(sym="U1", cod=[V, synth.WM_U1], dom=[V, synth.WM_U1])
+    st = ostruct(t)
+    a = synth.normal(st.size, 9, 0)
+    A = make(ctx, t, a)
+    Cg = tk.tensor_trace(ctx, A, (0,), (2,), (1,), (3,))
+    # blockwise reference: C[a; b] = sum_w A[a, w; b, w], channel by channel
+    ref = np.zeros(Cg.nelem)
+    stA = st
+    stC = Structure("U1", [stA.cod[0]], [stA.dom[0]])
+    dense_idx = {}
+    for c, ai, bi, off, R in stA.channels():
+        if ai[1] != bi[1]:
+            continue
+        dw = stA.cod[1].degs[ai[1]]
+        da, db = stA.cod[0].degs[ai[0]], stA.dom[0].degs[bi[0]]
+        blk = a[off + np.arange(da)[:, None, None, None] + da * np.arange(dw)[None, :, None, None]
+                + R * (np.arange(db)[None, None, :, None] + db * np.arange(dw)[None, None, None, :])]
+        dense_idx.setdefault((ai[0], bi[0]), np.zeros((da, db)))
+        dense_idx[(ai[0], bi[0])] += np.einsum("awbw->ab", blk)
+    for c, ai, bi, off, R in stC.channels():
+        blk = dense_idx.get((ai[0], bi[0]))
+        if blk is not None:
+            da, db = blk.shape
+            ref[off + np.arange(da)[:, None] + R * np.arange(db)[None, :]] = blk
+    assert_close(download(Cg), ref, np.abs(ref) + 1.0)
+
+
 def test_heff2_small_integer_bit_exact(ctx):
     """Two-site H_eff chain (four contractions, two of them skinny) on
     small-integer data: every intermediate equals the oracle's exactly."""

@@ -406,6 +406,96 @@ def test_fermionic_associativity(seed):
     assert np.array_equal(stABC.to_dense(abc), T)
 
 
+# ---------------------------------------------------------------------------
+# partial trace (Alg. "Abelian Tensor Trace")
+# ---------------------------------------------------------------------------
+def test_trace_bosonic_equals_literal_einsum():
+    """U(1): a traced pair is a repeated einsum index, for a codomain leg
+    against a domain leg over V and for two codomain legs over V and V*."""
+    rng = np.random.default_rng(71)
+    V = Space([(-1,), (0,), (1,)], [2, 3, 1])
+    W = Space([(0,), (1,)], [2, 2])
+    X = Space([(-1,), (0,)], [1, 2])
+    st = Structure("U1", [V, W], [V, X])
+    T = st.to_dense(rng.standard_normal(st.size))
+    C, ccod, cdom = dense.trace_dense("U1", T, st.cod, st.dom, (1,), (3,), (0,), (2,))
+    assert np.allclose(C, np.einsum("abac->bc", T), rtol=1e-14, atol=1e-14)
+    assert ccod == (W,) and cdom == (X,)
+    Vd = Space(V.sectors, V.degs, True)
+    st2 = Structure("U1", [V, Vd, W], [])
+    T2 = st2.to_dense(rng.standard_normal(st2.size))
+    C2, _, _ = dense.trace_dense("U1", T2, st2.cod, st2.dom, (2,), (), (0,), (1,))
+    assert np.allclose(C2, np.einsum("aab->b", T2), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("sym", ["FZ2", "U1xFZ2"])
+def test_trace_fermionic_is_supertrace(sym):
+    """Closing an endomorphism A : V <- V on itself is the supertrace
+    sum_i (-1)^{|i|} A_ii under the pushed-twist pairing (the odd part picks
+    up the twist, as for the graded dimension d_J = -1); over V* the pair is
+    already in evaluation order and the trace is the plain one; a bosonic
+    symmetry gives the plain trace."""
+    rng = np.random.default_rng(72)
+    secs = [(0,), (1,)] if sym == "FZ2" else [(0, 0), (1, 1), (-1, 1), (2, 0)]
+    V = Space(secs, [2, 3] if sym == "FZ2" else [2, 1, 2, 1])
+    par = V.parity_of_index(sym)
+    for dual_, expect_sign in ((False, np.where(par % 2 == 1, -1.0, 1.0)), (True, np.ones(V.dim))):
+        Vx = Space(V.sectors, V.degs, dual_)
+        st = Structure(sym, [Vx], [Vx])
+        A = st.to_dense(rng.standard_normal(st.size))
+        C, _, _ = dense.trace_dense(sym, A, st.cod, st.dom, (), (), (0,), (1,))
+        assert C.shape == () and np.isclose(C, np.sum(expect_sign * np.diag(A)), rtol=1e-14, atol=1e-14)
+    bos = "Z2" if sym == "FZ2" else "U1"
+    Vb = Space([s[:1] for s in V.sectors] if bos == "U1" else V.sectors, V.degs)
+    if bos == "U1" and len(set(Vb.sectors)) != len(Vb.sectors):
+        return
+    st = Structure(bos, [Vb], [Vb])
+    A = st.to_dense(rng.standard_normal(st.size))
+    C, _, _ = dense.trace_dense(bos, A, st.cod, st.dom, (), (), (0,), (1,))
+    assert np.isclose(C, np.trace(A), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_trace_of_composition_equals_loop_contraction(seed):
+    """A graph has one value however it is evaluated: composing A and B over
+    Z (blockwise oracle O2) and then closing A's X against B's X with the
+    trace equals contracting A and B over Z and X in one step (O2, an
+    independent code path: per-sector matrix products with the composition
+    twist).  X normal or dual, fermionic and bosonic, integer data, exact."""
+    rng = np.random.default_rng(700 + seed)
+    from paper_2508_10076_amd import synth
+    from tests.helpers import ospace
+    checked = 0
+    for sym in ("U1xFZ2", "FZ2", "U1", "Z2"):
+        for _ in range(8):
+            X = ospace(synth.random_space(rng, sym, max_deg=2))
+            Z = ospace(synth.random_space(rng, sym, max_deg=2))
+            ea = [ospace(synth.random_space(rng, sym, max_deg=2)) for _ in range(int(rng.integers(0, 2)))]
+            eb = [ospace(synth.random_space(rng, sym, max_deg=2)) for _ in range(int(rng.integers(0, 2)))]
+            stA = Structure(sym, [X] + ea, [Z])          # A : X (x) ea <- Z
+            stB = Structure(sym, [Z], [X] + eb)          # B : Z <- X (x) eb
+            if stA.size == 0 or stB.size == 0:
+                continue
+            a, b = int_data(stA.size, rng), int_data(stB.size, rng)
+            na, nb = len(ea), len(eb)
+            # C = A o B : legs X, ea..., X, eb...  (codomain X, ea; domain X, eb)
+            pA = tuple(range(1 + na))
+            stC, c = blockwise.contract_storage(stA, a, pA, (1 + na,), stB, b, (0,), tuple(range(1, 2 + nb)),
+                                                tuple(range(1 + na)), tuple(range(1 + na, 2 + na + nb)))
+            if stC.size == 0:
+                continue
+            D, dcod, ddom = dense.trace_dense(sym, stC.to_dense(c), stC.cod, stC.dom,
+                                              tuple(range(1, 1 + na)), tuple(range(2 + na, 2 + na + nb)),
+                                              (0,), (1 + na,))
+            stL, l = blockwise.contract_storage(stA, a, tuple(range(1, 1 + na)), (1 + na, 0), stB, b, (0, 1),
+                                                tuple(range(2, 2 + nb)), tuple(range(na)),
+                                                tuple(range(na, na + nb)))
+            assert stL.cod == dcod and stL.dom == ddom
+            assert np.array_equal(stL.to_dense(l), D), (sym, seed)
+            checked += 1
+    assert checked >= 8
+
+
 def test_adjoint_inner_product():
     """<A, A> = tr(A^dagger A) = ||A||^2 through blockwise adjoint + compose."""
     rng = np.random.default_rng(9)
