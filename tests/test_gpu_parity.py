@@ -300,6 +300,62 @@ def test_contract_alpha_beta(ctx):
     assert np.array_equal(download(Cg), ref)
 
 
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_outer_product_bit_exact(ctx, sym):
+    """Contraction over no legs (K = 1 sector GEMMs through the small-K
+    path): GPU against the blockwise oracle, random output arrangements."""
+    rng = np.random.default_rng(9300 + len(sym))
+    done = 0
+    while done < 4:
+        tA = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=3) for _ in range(2)],
+                  dom=[synth.random_space(rng, sym, max_deg=3)])
+        tB = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=3)],
+                  dom=[synth.random_space(rng, sym, max_deg=3)])
+        stA, stB = ostruct(tA), ostruct(tB)
+        if stA.size == 0 or stB.size == 0:
+            continue
+        perm = [int(x) for x in rng.permutation(5)]
+        n1 = int(rng.integers(0, 5))
+        pAB, qAB = perm[:n1], perm[n1:]
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_contract(ctx, A, (0, 1, 2), (), B, (), (0, 1), pAB, qAB)
+        _, ref = blockwise.contract_storage(stA, a, (0, 1, 2), (), stB, b, (), (0, 1), pAB, qAB)
+        assert np.array_equal(download(Cg), ref), (sym, pAB, qAB)
+        done += 1
+
+
+def test_empty_operands(ctx):
+    """An operand without any channel: C = beta * C exactly (every coupled
+    charge of C has an empty K range), and operations on a zero-size tensor
+    launch nothing and succeed."""
+    V = synth.u1_space([-1, 0, 1], [2, 3, 2])
+    W = synth.u1_space([7], [2])
+    tE = dict(sym="U1", cod=[W], dom=[V])            # charge 7 never meets -1..1: no channel
+    tB = dict(sym="U1", cod=[V], dom=[V])
+    assert ostruct(tE).size == 0
+    rng = np.random.default_rng(77)
+    E = make(ctx, tE)
+    B = make(ctx, tB, int_vec(rng, ostruct(tB).size))
+    C0 = tk.tensor_create_contracted(ctx, E, (0,), (1,), B, (0,), (1,), (0,), (1,))
+    assert C0.nelem == 0
+    tk.tensor_contract(ctx, E, (0,), (1,), B, (0,), (1,), (0,), (1,), C_=C0)
+    tk.tensor_permute(ctx, E, (), (0, 1))
+    # a C with entries, fed by an operand whose sectors never couple
+    tA = dict(sym="U1", cod=[V], dom=[synth.u1_space([5], [3])])
+    tB2 = dict(sym="U1", cod=[synth.u1_space([5], [3])], dom=[V])
+    A = make(ctx, tA, int_vec(rng, ostruct(tA).size))
+    Cg = tk.tensor_create_contracted(ctx, A, (0,), (1,), make(ctx, tB2), (0,), (1,), (0,), (1,))
+    assert ostruct(tA).size == 0 and Cg.nelem > 0
+    c0 = int_vec(rng, Cg.nelem)
+    upload(Cg, c0)
+    tk.tensor_contract(ctx, A, (0,), (1,), make(ctx, tB2), (0,), (1,), (0,), (1,), alpha=3.0, beta=-2.0, C_=Cg)
+    assert np.array_equal(download(Cg), -2.0 * c0)
+    upload(Cg, c0)
+    tk.tensor_contract(ctx, A, (0,), (1,), make(ctx, tB2), (0,), (1,), (0,), (1,), alpha=3.0, beta=0.0, C_=Cg)
+    assert np.array_equal(download(Cg), np.zeros_like(c0))
+
+
 def test_empty_k_sectors_are_zero(ctx):
     """A coupled charge present in codomain(A~) and domain(B~) but not in the
     contracted space gives a zero block (remark after eq. abelian_compostion)."""

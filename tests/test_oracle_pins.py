@@ -406,6 +406,36 @@ def test_fermionic_associativity(seed):
     assert np.array_equal(stABC.to_dense(abc), T)
 
 
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_outer_product_matches_graph_evaluator(sym):
+    """The outer product (composition over no legs, section "Contractions")
+    through O2 equals the dense definition (the plain tensor product for
+    bosons; graph signs of the output arrangement for fermions)."""
+    from paper_2508_10076_amd import synth
+    from tests.helpers import ospace
+    rng = np.random.default_rng(90 + len(sym))
+    done = 0
+    while done < 5:
+        stA = Structure(sym, [ospace(synth.random_space(rng, sym, max_deg=2)) for _ in range(2)],
+                        [ospace(synth.random_space(rng, sym, max_deg=2))])
+        stB = Structure(sym, [ospace(synth.random_space(rng, sym, max_deg=2))],
+                        [ospace(synth.random_space(rng, sym, max_deg=2))])
+        if stA.size == 0 or stB.size == 0:
+            continue
+        a, b = int_data(stA.size, rng), int_data(stB.size, rng)
+        perm = [int(x) for x in rng.permutation(5)]
+        n1 = int(rng.integers(0, 6))
+        pAB, qAB = tuple(perm[:n1]), tuple(perm[n1:])
+        stC, c = blockwise.contract_storage(stA, a, (0, 1, 2), (), stB, b, (), (0, 1), pAB, qAB)
+        D, dc, dd = dense.contract_dense(sym, stA.to_dense(a), stA.cod, stA.dom, (0, 1, 2), (),
+                                         stB.to_dense(b), stB.cod, stB.dom, (), (0, 1), pAB, qAB)
+        assert stC.cod == dc and stC.dom == dd
+        assert np.array_equal(stC.to_dense(c), D)
+        if sym in ("Z1", "Z2", "U1") and pAB == (0, 1, 2, 3, 4) and qAB == ():
+            assert np.array_equal(D, np.multiply.outer(stA.to_dense(a), stB.to_dense(b)))
+        done += 1
+
+
 # ---------------------------------------------------------------------------
 # partial trace (Alg. "Abelian Tensor Trace")
 # ---------------------------------------------------------------------------
