@@ -197,7 +197,7 @@ def test_heff2_plan_flops_match_oracle():
         P.close()
 
 
-def test_heff_plan_flops_match_survey_sizes():
+def test_heff_plan_flops_match_expected_sizes():
     cfg = synth.config2()
     t = {k: lib_tensor(v) for k, v in cfg["tensors"].items()}
     st = {k: ostruct(v) for k, v in cfg["tensors"].items()}
