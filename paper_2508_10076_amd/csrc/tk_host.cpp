@@ -739,6 +739,10 @@ constexpr int64_t kSkStrip = 16384;
 // Add one output block of a small-K sector GEMM (dims and strides in output
 // leg order) as chunked tasks, merging dims contiguous in r, s and dst.
 // Pack consecutive tasks into workgroups of about kPermChunk elements.
+// Tasks of one workgroup at most: its waves take them in turn, so a few per
+// wave keep the dependent loads of small tasks short.
+constexpr int kTasksPerWg = 16;
+
 template <typename TL>
 void pack_workgroups(TL& tl, int64_t limit = tk::kPermChunk) {
   tl.wg_first.assign(1, 0);
@@ -746,7 +750,7 @@ void pack_workgroups(TL& tl, int64_t limit = tk::kPermChunk) {
   int ntask = 0;
   for (size_t i = 0; i < tl.tasks.size(); ++i) {
     const int c = tl.tasks[i].count;
-    if (ntask > 0 && (acc + c > limit || ntask >= 64)) {
+    if (ntask > 0 && (acc + c > limit || ntask >= kTasksPerWg)) {
       tl.wg_first.push_back(static_cast<int32_t>(i));
       acc = 0;
       ntask = 0;
