@@ -510,16 +510,27 @@ constexpr int64_t kRunLimit = int64_t(1) << 24;
 // pieces of at most kRunChunk elements touching at most kRunMax runs.
 struct RunSet {
   std::vector<tk::SkRun> runs;
-  std::vector<tk::SkRunDec> decs;
+  std::vector<tk::SkRunShape> shapes;
+  std::map<std::string, int32_t> shape_id;  // shape bytes -> index
   std::vector<int32_t> first;
   std::vector<int64_t> wstart;
   int64_t total = 0;
-  DevBuf d_runs, d_decs, d_first, d_wstart;
+  DevBuf d_runs, d_shapes, d_first, d_wstart;
+  int32_t add_shape(const tk::SkRunShape& sh) {
+    const std::string key(reinterpret_cast<const char*>(&sh), sizeof(sh));
+    auto it = shape_id.find(key);
+    if (it != shape_id.end()) return it->second;
+    if (shapes.size() >= static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many run shapes");
+    const int32_t id = static_cast<int32_t>(shapes.size());
+    shapes.push_back(sh);
+    shape_id.emplace(key, id);
+    return id;
+  }
   void finalize() {
     std::sort(runs.begin(), runs.end(), [](const tk::SkRun& x, const tk::SkRun& y) {
       return x.buf != y.buf ? x.buf < y.buf : x.off < y.off;
     });
-    if (runs.size() > static_cast<size_t>(INT32_MAX) || decs.size() > static_cast<size_t>(INT32_MAX))
+    if (runs.size() > static_cast<size_t>(INT32_MAX) || shapes.size() > static_cast<size_t>(INT32_MAX))
       fail(TK_ERR_UNSUPPORTED, "too many output runs");
     total = 0;
     for (auto& r : runs) {
@@ -546,7 +557,7 @@ struct RunSet {
   int nwg() const { return wstart.empty() ? 0 : static_cast<int>(wstart.size()) - 1; }
   void upload() {
     d_runs.upload(runs);
-    d_decs.upload(decs);
+    d_shapes.upload(shapes);
     d_first.upload(first);
     d_wstart.upload(wstart);
   }
@@ -639,32 +650,24 @@ bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Gro
       nelem += b.count;
     }
   if (nruns * 4 > nelem || M >= kRunLimit) return false;
-  const int32_t dbase = checked_i32(static_cast<int64_t>(rs.decs.size()), "decoder table");
   for (int32_t i = 0; i < rg.n(); ++i)
     for (int32_t j = 0; j < cg.n(); ++j) {
       const size_t bi = static_cast<size_t>(i) * cg.n() + j;
       const Blk& b = blks[bi];
       const PairDesc& pd = pairs[pbase + i * cg.n() + j];
-      tk::SkRunDec d{};
-      d.a = a0 + rg.off[i];
-      d.b = b0 + cg.off[j] * K;
-      d.lda = checked_i32(M, "M");
-      d.sign = pd.sign;
-      d.a_buf = abuf;
-      d.b_buf = bbuf;
-      d.nd = 0;
+      tk::SkRunShape sh{};
       for (int n = 0; n < 8; ++n) {
         if (b.dim[n] == 1) continue;  // its index is always 0
         uint32_t mag = 0;
         uint8_t shr = 0;
         division_magic(static_cast<uint32_t>(b.dim[n]), &mag, &shr);  // shr >= 32 for extents >= 2
-        tk::SkRunDim& o = d.dim[d.nd++];
+        tk::SkRunDim& o = sh.dim[sh.nd++];
         o.mag = mag;
         o.dimshr = static_cast<uint32_t>(b.dim[n]) | (static_cast<uint32_t>(shr - 32) << 24);
         o.sa = (b.bmask >> n) & 1u ? 0u : static_cast<uint32_t>(b.str[n]);
         o.sb = (b.bmask >> n) & 1u ? static_cast<uint32_t>(b.str[n]) : 0u;
       }
-      rs.decs.push_back(d);
+      const int32_t shape = rs.add_shape(sh);
       for (int64_t lin0 = 0; lin0 < b.count; lin0 += b.runlen) {
         tk::SkRun r{};
         int64_t rem = lin0, x = 0;
@@ -673,9 +676,15 @@ bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Gro
           rem /= b.dim[n];
         }
         r.off = pd.base + x;
-        r.dec = dbase + static_cast<int32_t>(bi);
+        r.a = a0 + rg.off[i];
+        r.b = b0 + cg.off[j] * K;
         r.lin0 = static_cast<int32_t>(lin0);
+        r.shape = shape;
+        r.lda = checked_i32(M, "M");
+        r.sign = pd.sign;
         r.buf = tk::kBufC;
+        r.a_buf = abuf;
+        r.b_buf = bbuf;
         r.len = static_cast<int32_t>(b.runlen);
         rs.runs.push_back(r);
       }
@@ -1769,7 +1778,7 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                          static_cast<int>(P.skruns[K].runs.size()),
                                          static_cast<const int32_t*>(P.skruns[K].d_first.p),
                                          static_cast<const int64_t*>(P.skruns[K].d_wstart.p), P.skruns[K].nwg(),
-                                         static_cast<const tk::SkRunDec*>(P.skruns[K].d_decs.p), ptrs,
+                                         static_cast<const tk::SkRunShape*>(P.skruns[K].d_shapes.p), ptrs,
                                          P.post ? 1.0 : alpha, P.post ? 0.0 : beta, stream),
                   "small-K run launch");
   if ((stages & TK_STAGE_ZERO) && P.zranges.nwg() > 0)
@@ -2412,7 +2421,7 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                        static_cast<int>(b.skruns[K].runs.size()),
                                        static_cast<const int32_t*>(b.skruns[K].d_first.p),
                                        static_cast<const int64_t*>(b.skruns[K].d_wstart.p), b.skruns[K].nwg(),
-                                       static_cast<const tk::SkRunDec*>(b.skruns[K].d_decs.p), ptrs, b.alpha, b.beta,
+                                       static_cast<const tk::SkRunShape*>(b.skruns[K].d_shapes.p), ptrs, b.alpha, b.beta,
                                        stream),
                 "small-K run launch");
   if (b.zranges.nwg() > 0)
@@ -2483,15 +2492,13 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
         }
         for (size_t w = 1; w < P.skblocks[K].wg_first.size(); ++w)
           b->skblocks[K].wg_first.push_back(base + P.skblocks[K].wg_first[w]);
-        const int32_t db = static_cast<int32_t>(b->skruns[K].decs.size());
-        for (tk::SkRunDec d : P.skruns[K].decs) {
-          d.a_buf = static_cast<int16_t>(d.a_buf + i * tk::kBufsPerPlan);
-          d.b_buf = static_cast<int16_t>(d.b_buf + i * tk::kBufsPerPlan);
-          b->skruns[K].decs.push_back(d);
-        }
+        const int32_t db = static_cast<int32_t>(b->skruns[K].shapes.size());
+        b->skruns[K].shapes.insert(b->skruns[K].shapes.end(), P.skruns[K].shapes.begin(), P.skruns[K].shapes.end());
         for (tk::SkRun r : P.skruns[K].runs) {
-          r.dec += db;
-          r.buf += i * tk::kBufsPerPlan;
+          r.shape += db;
+          r.buf = static_cast<int16_t>(r.buf + i * tk::kBufsPerPlan);
+          r.a_buf = static_cast<int16_t>(r.a_buf + i * tk::kBufsPerPlan);
+          r.b_buf = static_cast<int16_t>(r.b_buf + i * tk::kBufsPerPlan);
           b->skruns[K].runs.push_back(r);
         }
       }

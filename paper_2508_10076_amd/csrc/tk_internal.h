@@ -198,30 +198,29 @@ hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTa
 struct SkRun {
   int64_t off;     // first element in the destination buffer
   int64_t vstart;  // first element in the list's concatenation of runs
-  int32_t dec;     // decoder of the run's block
+  int64_t a, b;    // the block's rows in A~ and its first column in B~ (elements)
   int32_t lin0;    // linear index of the run's first element in its block
-  int32_t buf;     // destination buffer
+  int32_t shape;   // the block's dimension record
+  int32_t lda;     // A~ stride between consecutive k
+  float sign;
+  int16_t buf, a_buf, b_buf, pad_;  // destination and operand buffers
   int32_t len;     // elements (host side)
 };
 
-// One output block written through runs: its rows in A~, its first column
-// in B~, its sign, and its output dimensions of extent above 1 in the
-// output's leg order (first fastest): per dimension the division magic
+// Dimension record of an output block written through runs, shared by all
+// blocks with the same extents: its output dimensions of extent above 1 in
+// the output's leg order (first fastest), per dimension the division magic
 // (floor(x / d) = mulhi(x, mag) >> shift for x < 2^24), the extent, and the
 // strides of the leg in A~ and in B~ (one of them 0; the B~ stride counts
 // elements, ldb included).  Blocks hold fewer than 2^24 elements and every
-// operand offset inside a block is below 2^24.
+// operand offset inside a block, and lda, are below 2^24.
 struct SkRunDim {
   uint32_t mag;
   uint32_t dimshr;  // extent | (shift - 32) << 24
   uint32_t sa, sb;
 };
-struct SkRunDec {
-  int64_t a, b;
-  int32_t lda;
-  float sign;
-  int16_t a_buf, b_buf;
-  int32_t nd;
+struct SkRunShape {
+  int32_t nd, pad_[3];
   SkRunDim dim[8];
 };
 constexpr int kRunChunk = 4096;  // elements of one workgroup
@@ -231,7 +230,7 @@ constexpr int kRunMax = 128;     // runs one workgroup touches at most
 // elements wstart[w] .. wstart[w+1]-1 of the concatenation; first[w] is the
 // run holding element wstart[w].
 hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs, int nruns, const int32_t* first,
-                              const int64_t* wstart, int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha,
+                              const int64_t* wstart, int nwg, const SkRunShape* shapes, const Ptrs& ptrs, double alpha,
                               double beta, hipStream_t stream);
 
 // Zero (or beta-scale) the ranges: workgroup w covers virtual elements

@@ -1215,7 +1215,7 @@ template <typename T, int MODE, int KK>
 __global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __restrict__ runs, int nruns,
                                                                const int32_t* __restrict__ first,
                                                                const int64_t* __restrict__ wstart,
-                                                               const SkRunDec* __restrict__ decs, Ptrs P,
+                                                               const SkRunShape* __restrict__ shapes, Ptrs P,
                                                                double alpha, double beta) {
   static_assert(kRunMax < 255, "run index map is 8-bit");
   __shared__ TK_GLOBAL T* s_p[kRunMax + 1];
@@ -1233,18 +1233,17 @@ __global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __re
   const int nr = min(r1 - r0, kRunMax + 1);
   for (int i = threadIdx.x; i < nr; i += kThreads) {
     const SkRun rn = runs[r0 + i];
-    const SkRunDec* dc = decs + rn.dec;
     const int64_t rel = rn.vstart - c0;  // <= 0 for run 0, in (0, n] for the others
     s_r[i] = static_cast<int32_t>(max<int64_t>(rel, 0));
     s_p[i] = buf_ptr_lane<T>(P, rn.buf) + (rn.off - rel);
-    s_a[i] = buf_ptr_lane<const T>(P, dc->a_buf) + dc->a;
-    s_b[i] = buf_ptr_lane<const T>(P, dc->b_buf) + dc->b;
-    s_i[i] = make_int4(dc->nd, static_cast<int32_t>(rn.lin0 - rel), dc->lda, __float_as_int(dc->sign));
+    s_a[i] = buf_ptr_lane<const T>(P, rn.a_buf) + rn.a;
+    s_b[i] = buf_ptr_lane<const T>(P, rn.b_buf) + rn.b;
+    s_i[i] = make_int4(shapes[rn.shape].nd, static_cast<int32_t>(rn.lin0 - rel), rn.lda, __float_as_int(rn.sign));
   }
   // the dimensions: 8 records of 16 bytes per run, one per thread in turn
   for (int t = threadIdx.x; t < nr * 8; t += kThreads) {
     const int i = t >> 3;
-    s_dim[i][t & 7] = decs[runs[r0 + i].dec].dim[t & 7];
+    s_dim[i][t & 7] = shapes[runs[r0 + i].shape].dim[t & 7];
   }
   __syncthreads();
   if (nr > 1) chunk_range_map<kRunChunk, uint8_t>(s_idx, s_wmax, s_r, nr, n);
@@ -1395,13 +1394,13 @@ hipError_t launch_smallk_blocks(int dtype, int precision, int K, const SkBlockTa
 
 template <typename T, int MODE>
 static void launch_smallk_runs_k(int K, const SkRun* runs, int nruns, const int32_t* first, const int64_t* wstart,
-                                 int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha, double beta,
+                                 int nwg, const SkRunShape* shapes, const Ptrs& ptrs, double alpha, double beta,
                                  hipStream_t stream) {
   switch (K) {
 #define TK_SKR_CASE(KK_)                                                                                        \
   case KK_:                                                                                                     \
     hipLaunchKernelGGL((smallk_runs_kernel<T, MODE, KK_>), dim3(nwg), dim3(kThreads), 0, stream, runs, nruns,   \
-                       first, wstart, decs, ptrs, alpha, beta);                                                 \
+                       first, wstart, shapes, ptrs, alpha, beta);                                               \
     break;
     TK_SKR_CASE(1) TK_SKR_CASE(2) TK_SKR_CASE(3) TK_SKR_CASE(4) TK_SKR_CASE(5) TK_SKR_CASE(6) TK_SKR_CASE(7)
     TK_SKR_CASE(8)
@@ -1412,22 +1411,22 @@ static void launch_smallk_runs_k(int K, const SkRun* runs, int nruns, const int3
 }
 
 hipError_t launch_smallk_runs(int dtype, int precision, int K, const SkRun* runs, int nruns, const int32_t* first,
-                              const int64_t* wstart, int nwg, const SkRunDec* decs, const Ptrs& ptrs, double alpha,
+                              const int64_t* wstart, int nwg, const SkRunShape* shapes, const Ptrs& ptrs, double alpha,
                               double beta, hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
   if (K < 1 || K > 8) return hipErrorInvalidValue;
   if (dtype == 0) {
     if (precision == 0)
-      launch_smallk_runs_k<double, 0>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+      launch_smallk_runs_k<double, 0>(K, runs, nruns, first, wstart, nwg, shapes, ptrs, alpha, beta, stream);
     else if (precision == 1)
-      launch_smallk_runs_k<double, 1>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+      launch_smallk_runs_k<double, 1>(K, runs, nruns, first, wstart, nwg, shapes, ptrs, alpha, beta, stream);
     else
-      launch_smallk_runs_k<double, 2>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+      launch_smallk_runs_k<double, 2>(K, runs, nruns, first, wstart, nwg, shapes, ptrs, alpha, beta, stream);
   } else {
     if (precision == 2)
-      launch_smallk_runs_k<float, 2>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+      launch_smallk_runs_k<float, 2>(K, runs, nruns, first, wstart, nwg, shapes, ptrs, alpha, beta, stream);
     else
-      launch_smallk_runs_k<float, 1>(K, runs, nruns, first, wstart, nwg, decs, ptrs, alpha, beta, stream);
+      launch_smallk_runs_k<float, 1>(K, runs, nruns, first, wstart, nwg, shapes, ptrs, alpha, beta, stream);
   }
   return hipGetLastError();
 }
