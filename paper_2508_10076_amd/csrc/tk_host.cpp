@@ -748,9 +748,9 @@ constexpr int64_t kSkStrip = 16384;
 // Add one output block of a small-K sector GEMM (dims and strides in output
 // leg order) as chunked tasks, merging dims contiguous in r, s and dst.
 // Pack consecutive tasks into workgroups of about kPermChunk elements.
-// Tasks of one workgroup at most: its waves take them in turn, so a few per
-// wave keep the dependent loads of small tasks short.
-constexpr int kTasksPerWg = 16;
+// Tasks of one workgroup at most: one per wave, so small tasks (a handful
+// of elements each) run side by side instead of one after another.
+constexpr int kTasksPerWg = 4;
 
 template <typename TL>
 void pack_workgroups(TL& tl, int64_t limit = tk::kPermChunk) {
