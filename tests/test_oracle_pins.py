@@ -526,6 +526,83 @@ def test_trace_of_composition_equals_loop_contraction(seed):
     assert checked >= 8
 
 
+# ---------------------------------------------------------------------------
+# truncated SVD (Alg. "Abelian tensor decomposition")
+# ---------------------------------------------------------------------------
+def _svd_case(rng, sym):
+    from paper_2508_10076_amd import synth
+    from tests.helpers import ospace
+    while True:
+        st = Structure(sym, [ospace(synth.random_space(rng, sym, max_deg=3)) for _ in range(2)],
+                       [ospace(synth.random_space(rng, sym, max_deg=3)) for _ in range(2)])
+        if st.size:
+            return st
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_svd_blocks_give_the_dense_spectrum_and_reconstruct(sym):
+    """The singular values of all coupled-charge blocks together are those of
+    the dense matrix of A~ (the grouping isomorphism is unitary); U S Vh
+    rebuilds A~ through the blockwise contraction O2 (an independent code
+    path); U and Vh have orthonormal columns / rows (O2 with the adjoint)."""
+    from oracle import decomp
+    rng = np.random.default_rng(60 + len(sym))
+    for _ in range(4):
+        st = _svd_case(rng, sym)
+        a = rng.standard_normal(st.size)
+        perm = [int(x) for x in rng.permutation(4)]
+        n1 = int(rng.integers(1, 4))
+        p, q = tuple(perm[:n1]), tuple(perm[n1:])
+        (stU, u), (stS, sv), (stV, vh), err, kept = decomp.svd_trunc(st, a, p, q)
+        stT, t = blockwise.permute_storage(st, a, p, q)
+        D = stT.to_dense(t)
+        r = int(np.prod(D.shape[:stT.N1]))
+        dense_s = np.linalg.svd(D.reshape(r, -1, order="F"), compute_uv=False)
+        got = np.sort(np.concatenate([kept[c] for c in kept]))[::-1]
+        m = min(len(got), len(dense_s))
+        assert np.allclose(got[:m], dense_s[:m], rtol=1e-12, atol=1e-12)
+        assert np.allclose(dense_s[m:], 0.0, atol=1e-12) and err == 0.0
+        stUS, us = blockwise.contract_storage(stU, u, tuple(range(stU.N1)), (stU.N1,), stS, sv, (0,), (1,),
+                                              tuple(range(stU.N1)), (stU.N1,))
+        stR, rec = blockwise.contract_storage(stUS, us, tuple(range(stUS.N1)), (stUS.N1,), stV, vh, (0,),
+                                              tuple(range(1, 1 + stV.N2)), tuple(range(stUS.N1)),
+                                              tuple(range(stUS.N1, stUS.N1 + stV.N2)))
+        assert stR.cod == stT.cod and stR.dom == stT.dom
+        assert np.allclose(rec, t, rtol=1e-12, atol=1e-12)
+        for c in stU.sectors:              # orthonormal singular vectors, block by block
+            Uc, Vc = stU.sector_matrix(u, c), stV.sector_matrix(vh, c)
+            assert np.allclose(Uc.T @ Uc, np.eye(Uc.shape[1]), atol=1e-12)
+            assert np.allclose(Vc @ Vc.T, np.eye(Vc.shape[0]), atol=1e-12)
+
+
+def test_svd_truncation_is_eckart_young():
+    """Keeping the k largest singular values over all sectors leaves the
+    optimal rank-k error of the dense matrix (Eckart-Young), equal to the
+    norm of the discarded values; the cutoff drops values at or below it."""
+    from oracle import decomp
+    rng = np.random.default_rng(66)
+    st = _svd_case(rng, "U1")
+    a = rng.standard_normal(st.size)
+    (stU, u), (stS, sv), (stV, vh), err0, kept0 = decomp.svd_trunc(st, a, (0, 1), (2, 3))
+    allv = np.sort(np.concatenate([kept0[c] for c in kept0]))[::-1]
+    k = max(1, len(allv) // 3)
+    (stU, u), (stS, sv), (stV, vh), err, kept = decomp.svd_trunc(st, a, (0, 1), (2, 3), max_dim=k)
+    assert sum(len(x) for x in kept.values()) == k
+    assert np.isclose(err, np.sqrt(np.sum(allv[k:] ** 2)), rtol=1e-12)
+    stUS, us = blockwise.contract_storage(stU, u, (0, 1), (2,), stS, sv, (0,), (1,), (0, 1), (2,))
+    stR, rec = blockwise.contract_storage(stUS, us, (0, 1), (2,), stV, vh, (0,), (1, 2), (0, 1), (2, 3))
+    stT, t = blockwise.permute_storage(st, a, (0, 1), (2, 3))
+    full = stT.to_dense(t)
+    approx = stR.to_dense(rec)
+    assert np.isclose(np.linalg.norm(full - approx), err, rtol=1e-10, atol=1e-12)
+    r = int(np.prod(full.shape[:2]))
+    dense_s = np.linalg.svd(full.reshape(r, -1, order="F"), compute_uv=False)
+    assert np.isclose(err, np.sqrt(np.sum(dense_s[k:] ** 2)), rtol=1e-10)
+    cut = allv[k - 1]
+    _, _, _, _, kept2 = decomp.svd_trunc(st, a, (0, 1), (2, 3), cutoff=cut)
+    assert sum(len(x) for x in kept2.values()) == k - 1
+
+
 def test_adjoint_inner_product():
     """<A, A> = tr(A^dagger A) = ||A||^2 through blockwise adjoint + compose."""
     rng = np.random.default_rng(9)
