@@ -117,6 +117,7 @@ typedef struct tk_context tk_context;
 typedef struct tk_tensor tk_tensor;
 typedef struct tk_plan tk_plan;
 typedef struct tk_batch tk_batch;
+typedef struct tk_svd tk_svd;
 
 /* ---- context ------------------------------------------------------------
  * A context binds a HIP device and owns the plan cache used by
@@ -178,6 +179,33 @@ tk_status tk_tensor_create_contracted(tk_context* ctx, const tk_tensor* A, const
                                       void* device_buf, uint64_t buf_bytes, tk_tensor** out);
 tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* device_buf,
                                    uint64_t buf_bytes, tk_tensor** out);
+/* Truncated singular value decomposition, Alg. "Abelian tensor
+ * decomposition": A~ = permute(A, (p, q)) (both sides non-empty) is split
+ * as U o S o Vh with U : cod(A~) <- W, S : W <- W diagonal and non-negative
+ * (descending within each coupled charge), Vh : W <- dom(A~), where the
+ * bond space W has one sector per coupled charge of A~, of degeneracy the
+ * number of singular values kept there.  Each coupled-charge matrix is
+ * decomposed on the device by one-sided Jacobi rotations; the kept values
+ * are the largest over all charges, at most max_dim of them (max_dim < 0:
+ * no bound) and only those above cutoff.  Three steps:
+ *   tk_svd_create -- enqueues the decomposition on `stream`, waits for it,
+ *     and chooses the kept values (TK_ERR_DTYPE unless A is fp64;
+ *     TK_ERR_INVALID_ARG if nothing would be kept);
+ *   tk_svd_create_factor -- a tensor with the spaces of U (which = 0),
+ *     S (1) or Vh (2), on caller storage as tk_tensor_create;
+ *   tk_svd_finish -- fills U, S and Vh (waits for the copies) and returns
+ *     the truncation error (the norm of the discarded singular values).
+ * The handle owns device workspace until tk_svd_destroy; it allocates, so
+ * it is not for graph capture. */
+tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
+                        const int32_t* q, int32_t nq, int64_t max_dim, double cutoff, void* stream,
+                        tk_svd** out);
+tk_status tk_svd_create_factor(tk_context* ctx, const tk_svd* svd, int32_t which, void* device_buf,
+                               uint64_t buf_bytes, tk_tensor** out);
+tk_status tk_svd_finish(tk_svd* svd, tk_tensor* U, tk_tensor* S, tk_tensor* Vh, double* trunc_err,
+                        void* stream);
+tk_status tk_svd_destroy(tk_svd* svd);
+
 /* A tensor shaped as the partial trace of A (see tk_tensor_trace). */
 tk_status tk_tensor_create_traced(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
                                   const int32_t* q, int32_t nq, const int32_t* t1, const int32_t* t2,

@@ -2101,6 +2101,224 @@ tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* 
   });
 }
 
+}  // extern "C"
+
+// Truncated SVD in progress (Alg. "Abelian tensor decomposition"): the
+// working copies and singular values on the device, the kept singular
+// values per sector, and the structures of the factors.
+struct tk_svd {
+  tk_context* ctx = nullptr;
+  int dtype = TK_F64;
+  std::shared_ptr<Structure> T;  // A~ = permute(A, (p, q))
+  DevBuf at, ws, secs;           // A~ (when permuted), workspace, sector records
+  std::vector<tk::SvdSector> sec;
+  std::vector<std::vector<int32_t>> keep;  // per record: kept singular value indices, largest first
+  std::vector<int32_t> sec_sector;         // per record: its sector of A~
+  std::vector<double> sigma;
+  std::shared_ptr<Structure> U, S, V;
+  double err = 0.0;
+};
+
+namespace {
+// The bond space of the factors: one sector per coupled charge with kept
+// singular values, that charge as its label.
+Space bond_space(const Structure& T, const std::vector<int32_t>& sectors, const std::vector<int64_t>& degs) {
+  const SymInfo si = sym_info(T.sym);
+  std::vector<int32_t> ch;
+  for (int32_t s : sectors) {
+    const int64_t key = T.keys[s];
+    const int32_t q = static_cast<int32_t>(key >> 1), par = static_cast<int32_t>(key & 1);
+    if (T.sym == TK_SYM_U1) ch.push_back(q);
+    else if (T.sym == TK_SYM_Z2 || T.sym == TK_SYM_FZ2) ch.push_back(par);
+    else if (T.sym == TK_SYM_U1_FZ2) ch.push_back(q), ch.push_back(par);
+  }
+  tk_space sp{};
+  sp.nsect = static_cast<int32_t>(sectors.size());
+  sp.charges = si.ncomp ? ch.data() : nullptr;
+  sp.degeneracies = degs.data();
+  sp.isdual = 0;
+  return make_space(T.sym, sp);
+}
+}  // namespace
+
+extern "C" {
+
+tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,
+                        int32_t nq, int64_t max_dim, double cutoff, void* stream, tk_svd** out) {
+  return guarded([&] {
+    if (!ctx || !A || !out) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (A->dtype != TK_F64) fail(TK_ERR_DTYPE, "the SVD works on fp64 tensors");
+    if (!A->data && A->st->size) fail(TK_ERR_INVALID_ARG, "A has no data");
+    auto pv = to_vec(p, np, "p"), qv = to_vec(q, nq, "q");
+    check_perm(pv, qv, A->st->N());
+    if (pv.empty() || qv.empty()) fail(TK_ERR_INVALID_ARG, "both sides of the matrix form need a leg");
+    auto sv = std::make_unique<tk_svd>();
+    sv->ctx = ctx;
+    std::vector<Space> c, d;
+    permute_spaces(*A->st, pv, qv, c, d);
+    sv->T = get_structure(A->st->sym, c, d);
+    const Structure& T = *sv->T;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double* X = static_cast<const double*>(A->data);
+    if (!is_identity(pv, qv, A->st->N1())) {
+      sv->at.alloc(T.size * sizeof(double));
+      TaskList tl;
+      plan_permute_tasks(*A->st, pv, qv, T, tk::kBufA, tk::kBufC, false, tl);
+      pack_workgroups(tl);
+      tl.upload();
+      tk::Ptrs ptrs{};
+      ptrs.p[tk::kBufA] = A->data;
+      ptrs.p[tk::kBufC] = sv->at.p;
+      hip_check(tk::launch_permute(TK_F64, static_cast<const PermTask*>(tl.d_tasks.p),
+                                   static_cast<const int32_t*>(tl.d_wg.p), tl.nwg(), ptrs, 1.0, 0.0, st),
+                "permute launch");
+      hip_check(hipStreamSynchronize(st), "stream synchronize");  // tl is freed on return
+      X = static_cast<const double*>(sv->at.p);
+    }
+    int64_t wsz = 0;
+    for (size_t k = 0; k < T.keys.size(); ++k) {
+      const int64_t R = T.R[k], C = T.C[k];
+      if (R == 0 || C == 0) continue;
+      if (R >= (int64_t(1) << 31) || C >= (int64_t(1) << 31)) fail(TK_ERR_UNSUPPORTED, "sector matrix too large");
+      tk::SvdSector r{};
+      r.x = T.soff[k];
+      r.R = static_cast<int32_t>(R);
+      r.C = static_cast<int32_t>(C);
+      r.trans = R < C;
+      r.m = static_cast<int32_t>(std::max(R, C));
+      r.n = static_cast<int32_t>(std::min(R, C));
+      r.w = wsz;
+      wsz += int64_t(r.m) * r.n;
+      r.v = wsz;
+      wsz += int64_t(r.n) * r.n;
+      sv->sec.push_back(r);
+      sv->sec_sector.push_back(static_cast<int32_t>(k));
+    }
+    for (auto& r : sv->sec) {  // singular values after every matrix
+      r.s = wsz;
+      wsz += r.n;
+    }
+    sv->ws.alloc(std::max<int64_t>(wsz, 1) * sizeof(double));
+    sv->secs.upload(sv->sec);
+    const double tol = std::numeric_limits<double>::epsilon() * 4.0;
+    hip_check(tk::launch_jacobi_svd(static_cast<const tk::SvdSector*>(sv->secs.p), static_cast<int>(sv->sec.size()), X,
+                                    static_cast<double*>(sv->ws.p), 60, tol, st),
+              "Jacobi SVD launch");
+    hip_check(hipStreamSynchronize(st), "stream synchronize");
+    int64_t nsig = 0;
+    for (const auto& r : sv->sec) nsig += r.n;
+    sv->sigma.resize(nsig);
+    if (nsig)
+      hip_check(hipMemcpy(sv->sigma.data(), static_cast<double*>(sv->ws.p) + sv->sec.front().s,
+                          nsig * sizeof(double), hipMemcpyDeviceToHost),
+                "copy of the singular values");
+    // the largest values over all sectors (ties: sector order, then index)
+    struct Val {
+      double s;
+      int32_t r, j;
+    };
+    std::vector<Val> all;
+    int64_t base = 0;
+    for (size_t r = 0; r < sv->sec.size(); ++r) {
+      for (int j = 0; j < sv->sec[r].n; ++j) all.push_back({sv->sigma[base + j], static_cast<int32_t>(r), j});
+      base += sv->sec[r].n;
+    }
+    std::stable_sort(all.begin(), all.end(), [](const Val& a, const Val& b) {
+      return a.s != b.s ? a.s > b.s : (a.r != b.r ? a.r < b.r : a.j < b.j);
+    });
+    size_t nkeep = 0;
+    while (nkeep < all.size() && all[nkeep].s > cutoff && (max_dim < 0 || int64_t(nkeep) < max_dim)) ++nkeep;
+    double e2 = 0.0;
+    for (size_t i = nkeep; i < all.size(); ++i) e2 += all[i].s * all[i].s;
+    sv->err = std::sqrt(e2);
+    sv->keep.assign(sv->sec.size(), {});
+    for (size_t i = 0; i < nkeep; ++i) sv->keep[all[i].r].push_back(all[i].j);
+    std::vector<int32_t> ks;
+    std::vector<int64_t> kd;
+    for (size_t r = 0; r < sv->sec.size(); ++r)
+      if (!sv->keep[r].empty()) {
+        ks.push_back(sv->sec_sector[r]);
+        kd.push_back(static_cast<int64_t>(sv->keep[r].size()));
+      }
+    if (ks.empty()) fail(TK_ERR_INVALID_ARG, "the truncation keeps no singular value");
+    const Space W = bond_space(T, ks, kd);
+    sv->U = get_structure(T.sym, T.cod, {W});
+    sv->S = get_structure(T.sym, {W}, {W});
+    sv->V = get_structure(T.sym, {W}, T.dom);
+    *out = sv.release();
+  });
+}
+
+tk_status tk_svd_create_factor(tk_context* ctx, const tk_svd* svd, int32_t which, void* device_buf,
+                               uint64_t buf_bytes, tk_tensor** out) {
+  return guarded([&] {
+    if (!svd || !out || which < 0 || which > 2) fail(TK_ERR_INVALID_ARG, "bad factor request");
+    const auto& st = which == 0 ? svd->U : which == 1 ? svd->S : svd->V;
+    *out = new_tensor(ctx, st, TK_F64, device_buf, buf_bytes);
+  });
+}
+
+tk_status tk_svd_finish(tk_svd* svd, tk_tensor* U, tk_tensor* S, tk_tensor* Vh, double* trunc_err, void* stream) {
+  return guarded([&] {
+    if (!svd || !U || !S || !Vh) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto same = [](const tk_tensor* t, const std::shared_ptr<Structure>& st) {
+      return t->st == st || t->st->sig == st->sig;
+    };
+    if (!same(U, svd->U) || !same(S, svd->S) || !same(Vh, svd->V))
+      fail(TK_ERR_SPACE_MISMATCH, "factor tensors do not have the SVD's spaces");
+    if (U->dtype != TK_F64 || S->dtype != TK_F64 || Vh->dtype != TK_F64) fail(TK_ERR_DTYPE, "factors are fp64");
+    for (const tk_tensor* t : {U, S, Vh})
+      if (!t->data && t->st->size) fail(TK_ERR_INVALID_ARG, "factor without data");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hip_check(hipMemsetAsync(S->data, 0, S->st->size * sizeof(double), st), "clear of S");
+    // copies: U columns, rows of Vh, the diagonal of S (sources in the workspace, buffer 0)
+    TaskList tl;
+    const Structure &Us = *svd->U, &Ss = *svd->S, &Vs = *svd->V;
+    for (size_t r = 0; r < svd->sec.size(); ++r) {
+      const auto& kp = svd->keep[r];
+      if (kp.empty()) continue;
+      const tk::SvdSector& sc = svd->sec[r];
+      const int64_t key = svd->T->keys[svd->sec_sector[r]];
+      const int su = Us.sector_of_key(key), ss = Ss.sector_of_key(key), sv = Vs.sector_of_key(key);
+      if (su < 0 || ss < 0 || sv < 0) fail(TK_ERR_SPACE_MISMATCH, "internal: factor lacks a sector");
+      const int64_t k = static_cast<int64_t>(kp.size());
+      for (int64_t i = 0; i < k; ++i) {
+        const int j = kp[i];
+        int64_t dim[1], one[1] = {1}, ds[1];
+        // U(:, i) <- left vector j: a column of W, or of V for a transposed matrix
+        dim[0] = sc.R;
+        ds[0] = 1;
+        add_block_tasks(tl, 0, sc.trans ? sc.v + int64_t(j) * sc.n : sc.w + int64_t(j) * sc.m, 1,
+                        Us.soff[su] + i * sc.R, 1, dim, one, ds, 1.0f);
+        // Vh(i, :) <- right vector j: a column of V, or of W for a transposed matrix
+        dim[0] = sc.C;
+        ds[0] = k;
+        add_block_tasks(tl, 0, sc.trans ? sc.w + int64_t(j) * sc.m : sc.v + int64_t(j) * sc.n, 3,
+                        Vs.soff[sv] + i, 1, dim, one, ds, 1.0f);
+        dim[0] = 1;
+        ds[0] = 1;
+        add_block_tasks(tl, 0, sc.s + j, 2, Ss.soff[ss] + i * (k + 1), 1, dim, one, ds, 1.0f);
+      }
+    }
+    pack_workgroups(tl);
+    tl.upload();
+    tk::Ptrs ptrs{};
+    ptrs.p[0] = svd->ws.p;
+    ptrs.p[1] = U->data;
+    ptrs.p[2] = S->data;
+    ptrs.p[3] = Vh->data;
+    hip_check(tk::launch_permute(TK_F64, static_cast<const PermTask*>(tl.d_tasks.p),
+                                 static_cast<const int32_t*>(tl.d_wg.p), tl.nwg(), ptrs, 1.0, 0.0, st),
+              "factor copy launch");
+    hip_check(hipStreamSynchronize(st), "stream synchronize");  // tl is freed on return
+    if (trunc_err) *trunc_err = svd->err;
+  });
+}
+
+tk_status tk_svd_destroy(tk_svd* svd) {
+  return guarded([&] { delete svd; });
+}
+
 tk_status tk_tensor_trace(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,
                           int32_t nq, const int32_t* t1, const int32_t* t2, int32_t nt, double alpha, double beta,
                           tk_tensor* C, void* stream) {

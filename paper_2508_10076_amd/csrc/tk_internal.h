@@ -267,6 +267,20 @@ struct TraceContrib {
 hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_first, int nwg,
                         const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta,
                         hipStream_t stream);
+// Singular value decomposition of one coupled-sector matrix (R x C,
+// column-major) by one-sided Jacobi rotations on its m x n working copy W
+// (the matrix, or its transpose when R < C, so that m >= n), with the
+// rotations accumulated in V (n x n).  On exit sigma[j] = |W_j| and W_j is
+// normalised (the left singular vectors of the working matrix).
+struct SvdSector {
+  int64_t x;         // the matrix in its buffer
+  int64_t w, v, s;   // W, V and sigma in the workspace (elements)
+  int32_t R, C, m, n, trans, pad_;
+};
+constexpr int kSvdThreads = 1024;
+hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, double* ws, int max_sweeps,
+                             double tol, hipStream_t stream);
+
 // Small-K sector GEMM tasks that all share the same K (1..8): one
 // workgroup per task.
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

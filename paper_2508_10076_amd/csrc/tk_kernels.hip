@@ -207,6 +207,94 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __rest
   for (int t = t0 + wave; t < t1; t += kThreads / 64) trace_task<T>(tasks + t, cs, P, alpha, beta, lane, 64);
 }
 
+// One-sided (Hestenes) Jacobi SVD, one workgroup per coupled-sector
+// matrix.  A sweep pairs every two columns once, in n' - 1 rounds of n'/2
+// disjoint pairs (round-robin order, n' = n rounded up to even, the extra
+// column a dummy); a wave takes a pair, forms |W_p|^2, |W_q|^2 and W_p.W_q
+// over the rows, and, unless the pair is already orthogonal to tol, rotates
+// both columns of W and of V so that it becomes so.  Rounds are separated by
+// barriers (their pairs are disjoint); sweeps stop when one applies no
+// rotation or after max_sweeps.
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector* __restrict__ secs,
+                                                                 const double* __restrict__ X,
+                                                                 double* __restrict__ ws, int max_sweeps,
+                                                                 double tol) {
+  const SvdSector sc = secs[blockIdx.x];
+  const int m = sc.m, n = sc.n, R = sc.R;
+  double* W = ws + sc.w;
+  double* V = ws + sc.v;
+  const double* Xs = X + sc.x;
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(m) * n; e += kSvdThreads) {
+    const int i = static_cast<int>(e % m), j = static_cast<int>(e / m);
+    W[e] = sc.trans ? Xs[j + static_cast<int64_t>(R) * i] : Xs[i + static_cast<int64_t>(R) * j];
+  }
+  for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * n; e += kSvdThreads)
+    V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  __shared__ int s_rot;
+  __syncthreads();
+  const int nn = n + (n & 1), wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kSvdThreads / 64;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < nn - 1; ++r) {
+      for (int k = wave; k < nn / 2; k += nw) {
+        const int p = k == 0 ? 0 : 1 + (r + k) % (nn - 1);
+        const int q = k == 0 ? 1 + r : 1 + (r - k + nn - 1) % (nn - 1);
+        if (p >= n || q >= n) continue;  // the dummy column
+        double* Wp = W + static_cast<int64_t>(m) * p;
+        double* Wq = W + static_cast<int64_t>(m) * q;
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = lane; i < m; i += 64) {
+          const double x = Wp[i], y = Wq[i];
+          a += x * x;
+          b += y * y;
+          g += x * y;
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        g = wave_sum(g);
+        if (!(a > 0.0 && b > 0.0) || fabs(g) <= tol * sqrt(a * b)) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = lane; i < m; i += 64) {
+          const double x = Wp[i], y = Wq[i];
+          Wp[i] = c * x - s * y;
+          Wq[i] = s * x + c * y;
+        }
+        double* Vp = V + static_cast<int64_t>(n) * p;
+        double* Vq = V + static_cast<int64_t>(n) * q;
+        for (int i = lane; i < n; i += 64) {
+          const double x = Vp[i], y = Vq[i];
+          Vp[i] = c * x - s * y;
+          Vq[i] = s * x + c * y;
+        }
+        if (lane == 0) s_rot = 1;
+      }
+      __syncthreads();
+    }
+    const int rotated = s_rot;
+    __syncthreads();
+    if (!rotated) break;
+  }
+  double* S = ws + sc.s;
+  for (int j = wave; j < n; j += nw) {
+    double* Wj = W + static_cast<int64_t>(m) * j;
+    double a = 0.0;
+    for (int i = lane; i < m; i += 64) a += Wj[i] * Wj[i];
+    const double nrm = sqrt(wave_sum(a));
+    if (lane == 0) S[j] = nrm;
+    if (nrm > 0.0)
+      for (int i = lane; i < m; i += 64) Wj[i] /= nrm;
+  }
+}
+
 // Buffer id -> base address with a per-lane id (a select chain over the
 // plan's buffers, or the batch's table).
 template <typename T>
@@ -1322,6 +1410,13 @@ hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_fir
   else
     hipLaunchKernelGGL(trace_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs,
                        alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, double* ws, int max_sweeps,
+                             double tol, hipStream_t stream) {
+  if (nsec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nsec), dim3(kSvdThreads), 0, stream, secs, X, ws, max_sweeps, tol);
   return hipGetLastError();
 }
 

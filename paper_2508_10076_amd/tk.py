@@ -63,6 +63,10 @@ _SIGS = {
                                     C.c_int32, _I32P, C.c_int32, _I32P, C.c_int32, _P, C.c_uint64, C.POINTER(_P)],
     "tk_tensor_create_adjoint": [_P, _P, _P, C.c_uint64, C.POINTER(_P)],
     "tk_tensor_permute": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _P],
+    "tk_svd_create": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, C.c_int64, C.c_double, _P, C.POINTER(_P)],
+    "tk_svd_create_factor": [_P, _P, C.c_int32, _P, C.c_uint64, C.POINTER(_P)],
+    "tk_svd_finish": [_P, _P, _P, _P, C.POINTER(C.c_double), _P],
+    "tk_svd_destroy": [_P],
     "tk_tensor_create_traced": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _P,
                                 C.c_uint64, C.POINTER(_P)],
     "tk_tensor_trace": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, C.c_double,
@@ -333,6 +337,22 @@ def tensor_trace(ctx, A, p, q, t1, t2, alpha=1.0, beta=0.0, C_=None, stream=None
     _check(lib.tk_tensor_trace(ctx.h, A.h, pa, npa, qa, nqa, a, b, na, float(alpha), float(beta), C_.h,
                                _stream(stream)))
     return C_
+
+
+def tensor_svd(ctx, A, p, q, max_dim=-1, cutoff=0.0, stream=None):
+    """Truncated SVD A~ = U o S o Vh of A~ = permute(A, (p, q)); returns
+    (U, S, Vh, truncation error)."""
+    (pa, npa), (qa, nqa) = _ilist(p), _ilist(q)
+    h = C.c_void_p()
+    _check(lib.tk_svd_create(ctx.h, A.h, pa, npa, qa, nqa, int(max_dim), float(cutoff), _stream(stream),
+                             C.byref(h)))
+    try:
+        U, S, Vh = (Tensor._derived(ctx, lambda c, *r, w=w: lib.tk_svd_create_factor(c, h, w, *r)) for w in range(3))
+        err = C.c_double()
+        _check(lib.tk_svd_finish(h, U.h, S.h, Vh.h, C.byref(err), _stream(stream)))
+    finally:
+        lib.tk_svd_destroy(h)
+    return U, S, Vh, err.value
 
 
 def tensor_create_adjoint(ctx, A):

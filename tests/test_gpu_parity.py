@@ -500,6 +500,63 @@ def test_trace_large_u1_fp64(ctx):
     assert_close(download(Cg), ref, np.abs(ref) + 1.0)
 
 
+# ---------------------------------------------------------------------------
+# truncated SVD (Alg. "Abelian tensor decomposition")
+# ---------------------------------------------------------------------------
+def _svd_check(ctx, t, a, p, q, max_dim=-1, cutoff=0.0):
+    from oracle import decomp
+    st = ostruct(t)
+    A = make(ctx, t, a)
+    U, S, Vh, err = tk.tensor_svd(ctx, A, p, q, max_dim=max_dim, cutoff=cutoff)
+    (stU, u), (stS, sv), (stV, vh), err_o, kept = decomp.svd_trunc(st, a, p, q, None if max_dim < 0 else max_dim,
+                                                                  cutoff)
+    assert U.nelem == stU.size and S.nelem == stS.size and Vh.nelem == stV.size
+    gu, gs, gv = download(U), download(S), download(Vh)
+    scale = max(float(np.max(np.abs(kept[c]))) for c in kept)
+    assert abs(err - err_o) <= 1e-12 * scale
+    # same singular values per coupled charge (descending), within fp64 accuracy
+    assert np.allclose(gs, sv, rtol=0, atol=1e-12 * scale)
+    for c in stU.sectors:
+        Ug, Uo = stU.sector_matrix(gu, c), stU.sector_matrix(u, c)
+        Vg, Vo = stV.sector_matrix(gv, c), stV.sector_matrix(vh, c)
+        assert np.allclose(Ug.T @ Ug, np.eye(Ug.shape[1]), atol=1e-12)
+        assert np.allclose(Vg @ Vg.T, np.eye(Vg.shape[0]), atol=1e-12)
+        # vectors of distinct singular values agree up to a sign
+        sg = np.sign(np.sum(Ug * Uo, axis=0))
+        assert np.allclose(Ug * sg, Uo, atol=1e-10) and np.allclose(Vg * sg[:, None], Vo, atol=1e-10)
+    return err
+
+
+@pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
+def test_svd_against_oracle(ctx, sym):
+    """Blockwise Jacobi SVD against the oracle's per-sector library SVD:
+    singular values, orthonormal and (up to sign) equal singular vectors,
+    with the matrix form taken across every leg split."""
+    rng = np.random.default_rng(9600 + len(sym))
+    done = 0
+    while done < 4:
+        t = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=4) for _ in range(2)],
+                 dom=[synth.random_space(rng, sym, max_deg=4) for _ in range(2)])
+        st = ostruct(t)
+        if st.size == 0:
+            continue
+        perm = [int(x) for x in rng.permutation(4)]
+        n1 = int(rng.integers(1, 4))
+        _svd_check(ctx, t, rng.standard_normal(st.size), tuple(perm[:n1]), tuple(perm[n1:]))
+        done += 1
+
+
+def test_svd_truncated_two_site(ctx):
+    """The truncation of the two-site algorithm: x2 : V x P <- V x P* (D=256)
+    split between (a, p1) and (b, p2), keeping the 200 largest singular
+    values over all charges; error and factors against the oracle."""
+    cfg = synth.heff2_config(256, 6, 2.2, 94)
+    t = cfg["tensors"]["x"]
+    a = synth.normal(ostruct(t).size, 94, 0)
+    err = _svd_check(ctx, t, a, (0, 1), (2, 3), max_dim=200)
+    assert err > 0
+
+
 def test_heff2_small_integer_bit_exact(ctx):
     """Two-site H_eff chain (four contractions, two of them skinny) on
     small-integer data: every intermediate equals the oracle's exactly."""
