@@ -215,6 +215,8 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __rest
 // both columns of W and of V so that it becomes so.  Rounds are separated by
 // barriers (their pairs are disjoint); sweeps stop when one applies no
 // rotation or after max_sweeps.
+constexpr int kSvdCache = 8;  // elements per lane held in registers (columns up to 512 rows)
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -249,7 +251,49 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
         if (p >= n || q >= n) continue;  // the dummy column
         double* Wp = W + static_cast<int64_t>(m) * p;
         double* Wq = W + static_cast<int64_t>(m) * q;
+        double* Vp = V + static_cast<int64_t>(n) * p;
+        double* Vq = V + static_cast<int64_t>(n) * q;
         double a = 0.0, b = 0.0, g = 0.0;
+        if (m <= kSvdCache * 64) {
+          // columns of up to kSvdCache * 64 rows: every element this lane
+          // needs (of W and of V) is loaded once, before any arithmetic
+          double xw[kSvdCache], yw[kSvdCache], xv[kSvdCache], yv[kSvdCache];
+#pragma unroll
+          for (int u = 0; u < kSvdCache; ++u) {
+            const int i = lane + 64 * u;
+            xw[u] = i < m ? Wp[i] : 0.0;
+            yw[u] = i < m ? Wq[i] : 0.0;
+            xv[u] = i < n ? Vp[i] : 0.0;
+            yv[u] = i < n ? Vq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kSvdCache; ++u) {
+            a += xw[u] * xw[u];
+            b += yw[u] * yw[u];
+            g += xw[u] * yw[u];
+          }
+          a = wave_sum(a);
+          b = wave_sum(b);
+          g = wave_sum(g);
+          if (!(a > 0.0 && b > 0.0) || fabs(g) <= tol * sqrt(a * b)) continue;
+          const double zeta = (b - a) / (2.0 * g);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+          for (int u = 0; u < kSvdCache; ++u) {
+            const int i = lane + 64 * u;
+            if (i < m) {
+              Wp[i] = c * xw[u] - s * yw[u];
+              Wq[i] = s * xw[u] + c * yw[u];
+            }
+            if (i < n) {
+              Vp[i] = c * xv[u] - s * yv[u];
+              Vq[i] = s * xv[u] + c * yv[u];
+            }
+          }
+          if (lane == 0) s_rot = 1;
+          continue;
+        }
         for (int i = lane; i < m; i += 64) {
           const double x = Wp[i], y = Wq[i];
           a += x * x;
@@ -268,8 +312,6 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
           Wp[i] = c * x - s * y;
           Wq[i] = s * x + c * y;
         }
-        double* Vp = V + static_cast<int64_t>(n) * p;
-        double* Vq = V + static_cast<int64_t>(n) * q;
         for (int i = lane; i < n; i += 64) {
           const double x = Vp[i], y = Vq[i];
           Vp[i] = c * x - s * y;
