@@ -331,6 +331,60 @@ tk_status tk_tile_shapes(int32_t* count, int32_t* tile_mnk /* 3 * count, may be 
 tk_status tk_plan_set_tile(tk_plan* plan, int32_t tile_m, int32_t tile_n, int32_t tile_k);
 tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int32_t tile_k);
 
+/* ---- SU(2): leg permutations by recoupling ---------------------------------
+ * Section "Non-abelian symmetries" (fusion trees, the canonical expansion of
+ * a tensor map over fusion-splitting tree pairs) and Alg. "Non-abelian
+ * Tensor Transformation": each reduced array of the output is a sum of
+ * coefficient * permuted input reduced arrays; the coefficients are
+ * products of F-moves (6j symbols) and R-moves (exchange phases) of the
+ * Section "Fusion Tree Manipulations", computed on the host when the plan
+ * is made.
+ *
+ * Legs: n1 codomain legs then n2 domain legs (n1, n2 >= 1, n1 + n2 <= 8).
+ * Leg l has nsec[l] sectors (1..64); twoj and deg list all sectors of all
+ * legs in leg order: twice the spin (0..64, strictly ascending within a leg)
+ * and the degeneracy (>= 1).  A splitting tree of legs a_1..a_N is the
+ * canonical left-to-right tree: e_1 = a_1, e_k in e_{k-1} x a_k, e_N = c
+ * (Condon-Shortley Clebsch-Gordan vertices); domain trees are adjoints of
+ * splitting trees of the domain legs.
+ *
+ * Storage (input and output alike): one column-major matrix per coupled
+ * spin c, ascending c, only spins with both rows and columns, laid end to
+ * end.  Rows are the codomain trees of c, columns the domain trees of c;
+ * a tree takes prod(deg) consecutive rows (columns), its first leg fastest.
+ * The trees of one c are ordered by outer sectors (colex, first leg
+ * fastest), then by intermediates e_2..e_{N-1} (colex, e_2 fastest).
+ *
+ * permute(A, (p, q)): output codomain leg k is input leg p[k] (p permutes
+ * 0..n1-1), output domain leg k is input leg q[k] (q permutes
+ * n1..n1+n2-1).  Moving legs between codomain and domain is not supported
+ * (TK_ERR_INVALID_ARG).
+ *
+ * tk_su2_plan_create: builds both structures and the coefficient table on
+ *   the host (no GPU call); the caller owns *out (tk_su2_plan_destroy).
+ *   Errors: TK_ERR_INVALID_ARG (null pointers, leg counts, bad p or q,
+ *   degeneracies), TK_ERR_CHARGE (spins), TK_ERR_UNSUPPORTED (more than 8
+ *   legs, a reduced array beyond 2^31 elements, strides beyond 32 bits).
+ * tk_su2_plan_info: element counts of the input and output storage and the
+ *   number of (output pair, input pair) contributions (any may be null).
+ * tk_su2_plan_contribs: copies the host table, one entry per contribution:
+ *   first element of the output reduced array, first element of the input
+ *   reduced array, coefficient; cap >= the contribution count.
+ * tk_su2_permute: C = alpha * permute(A, (p, q)) + beta * C on `stream`;
+ *   A and C are device arrays of dtype (TK_F64 or TK_F32) with the plan's
+ *   input and output sizes, caller-owned, not aliased; beta == 0 never
+ *   reads C.  The plan's tables go to the current device on the first call
+ *   and the plan stays bound to that device.  One launch; the plan must
+ *   outlive the work enqueued with it. */
+typedef struct tk_su2_plan tk_su2_plan;
+tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
+                             const int32_t* p, const int32_t* q, tk_su2_plan** out);
+tk_status tk_su2_plan_info(const tk_su2_plan* plan, int64_t* in_size, int64_t* out_size, int64_t* ncontrib);
+tk_status tk_su2_plan_contribs(const tk_su2_plan* plan, int64_t cap, int64_t* dst, int64_t* src, double* coef);
+tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* C, double alpha, double beta,
+                         void* stream);
+tk_status tk_su2_plan_destroy(tk_su2_plan* plan);
+
 /* ---- misc ------------------------------------------------------------------ */
 const char* tk_last_error(void);
 const char* tk_version(void);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <array>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -949,7 +951,7 @@ void plan_trace_tasks(const Structure& A, const std::vector<int>& p, const std::
     block_strides(A, tup, A.R[s], idim, istr);
     tk::TraceContrib c{};
     c.src = off;
-    c.sign = (ferm && channel_parity(A, tup, pairs)) ? -1.0f : 1.0f;
+    c.coef = (ferm && channel_parity(A, tup, pairs)) ? -1.0 : 1.0;
     c.nd = nt;
     for (int m = 0; m < n; ++m) c.ss[m] = checked_i32(istr[src[m]], "stride");
     for (int k = 0; k < nt; ++k) {
@@ -987,6 +989,322 @@ void plan_trace_tasks(const Structure& A, const std::vector<int>& p, const std::
   });
   pack_workgroups(tp.tl, kTraceChunk);
 }
+
+// ---------------------------------------------------------------------------
+// SU(2) recoupling (Section "Non-abelian symmetries": canonical fusion and
+// splitting trees; Section "Fusion Tree Manipulations": F- and R-moves;
+// Alg. "Non-abelian Tensor Transformation").  Spins are twice their value.
+// A permutation of legs within one side acts on a canonical splitting tree
+// as a product of adjacent swaps; each swap is a local move built from the
+// 6j symbols (F) and the exchange phases (R), so no dense Clebsch-Gordan
+// tensors are formed.
+// ---------------------------------------------------------------------------
+namespace su2 {
+
+long double fact_half(int n2) {  // (n2 / 2)!
+  static const std::vector<long double> table = [] {
+    std::vector<long double> t(171);
+    t[0] = 1.0L;
+    for (size_t i = 1; i < t.size(); ++i) t[i] = t[i - 1] * static_cast<long double>(i);
+    return t;
+  }();
+  const int n = n2 / 2;
+  if (n2 < 0 || (n2 & 1) || n >= static_cast<int>(table.size())) fail(TK_ERR_UNSUPPORTED, "spin too large");
+  return table[n];
+}
+
+bool triangle(int a, int b, int c) { return std::abs(a - b) <= c && c <= a + b && ((a + b + c) & 1) == 0; }
+
+long double delta(int a, int b, int c) {
+  return std::sqrt(fact_half(a + b - c) * fact_half(a - b + c) * fact_half(-a + b + c) / fact_half(a + b + c + 2));
+}
+
+// Wigner 6j symbol {j1 j2 j3; j4 j5 j6} by Racah's single-sum formula.
+double sixj(int j1, int j2, int j3, int j4, int j5, int j6) {
+  if (!triangle(j1, j2, j3) || !triangle(j1, j5, j6) || !triangle(j4, j2, j6) || !triangle(j4, j5, j3)) return 0.0;
+  const int a1 = j1 + j2 + j3, a2 = j1 + j5 + j6, a3 = j4 + j2 + j6, a4 = j4 + j5 + j3;
+  const int b1 = j1 + j2 + j4 + j5, b2 = j2 + j3 + j5 + j6, b3 = j3 + j1 + j6 + j4;
+  const int tmin = std::max(std::max(a1, a2), std::max(a3, a4)), tmax = std::min(b1, std::min(b2, b3));
+  long double sum = 0.0L;
+  for (int t = tmin; t <= tmax; t += 2) {
+    const long double term = fact_half(t + 2) / (fact_half(t - a1) * fact_half(t - a2) * fact_half(t - a3) *
+                                                 fact_half(t - a4) * fact_half(b1 - t) * fact_half(b2 - t) *
+                                                 fact_half(b3 - t));
+    sum += ((t / 2) & 1) ? -term : term;
+  }
+  return static_cast<double>(delta(j1, j2, j3) * delta(j1, j5, j6) * delta(j4, j2, j6) * delta(j4, j5, j3) * sum);
+}
+
+// F-move of splitting trees: the coefficient of the tree (e (a b)h) g in the
+// tree ((e a)f b) g, with Condon-Shortley Clebsch-Gordan vertices.
+double fmove(int e, int a, int b, int g, int f, int h) {
+  const int ph = (e + a + b + g) / 2;
+  return ((ph & 1) ? -1.0 : 1.0) * std::sqrt(static_cast<double>((f + 1) * (h + 1))) * sixj(e, a, f, b, g, h);
+}
+
+// R-move: exchanging the two outgoing legs of the vertex c -> a x b.
+double rmove(int a, int b, int c) { return (((a + b - c) / 2) & 1) ? -1.0 : 1.0; }
+
+// Swap of adjacent legs k, k+1 (k >= 1) with e = e_{k-1}, a = leg k,
+// b = leg k+1, g = e_{k+1}: the tree with intermediate f becomes a sum over
+// trees with intermediate f2, coefficient sum_h F(e,a,b,g;f,h) R(a,b;h)
+// F(e,b,a,g;f2,h).
+double swap_coeff(int e, int a, int b, int g, int f, int f2) {
+  double v = 0.0;
+  for (int h = std::abs(a - b); h <= a + b; h += 2) {
+    if (!triangle(e, h, g)) continue;
+    v += fmove(e, a, b, g, f, h) * rmove(a, b, h) * fmove(e, b, a, g, f2, h);
+  }
+  return v;
+}
+
+struct Leg {
+  std::vector<int> tj;
+  std::vector<int64_t> deg;
+};
+
+struct Tree {
+  std::vector<int> sec;  // sector index per leg
+  std::vector<int> e;    // e_1 .. e_N (e_1 = first spin, e_N = coupled)
+  int64_t r0 = 0, n = 1;
+};
+
+// One side: trees grouped by coupled spin, in storage order.
+struct Side {
+  std::map<int, std::vector<Tree>> by_c;
+  std::map<std::pair<std::vector<int>, std::vector<int>>, std::pair<int, int>> index;  // (sec, e) -> (c, position)
+};
+
+void enumerate_trees(const std::vector<Leg>& legs, Side& side) {
+  const int N = static_cast<int>(legs.size());
+  std::vector<int> sec(N, 0);
+  for (;;) {
+    std::vector<int> outer(N);
+    int64_t n = 1;
+    for (int k = 0; k < N; ++k) {
+      outer[k] = legs[k].tj[sec[k]];
+      n *= legs[k].deg[sec[k]];
+    }
+    std::vector<std::vector<int>> found;
+    std::vector<int> e{outer[0]};
+    std::function<void(int)> rec = [&](int k) {
+      if (k == N) {
+        found.push_back(e);
+        return;
+      }
+      const int prev = e.back();
+      for (int f = std::abs(prev - outer[k]); f <= prev + outer[k]; f += 2) {
+        e.push_back(f);
+        rec(k + 1);
+        e.pop_back();
+      }
+    };
+    rec(1);
+    // intermediates e_2..e_{N-1} colex: compare from the last one
+    std::sort(found.begin(), found.end(), [&](const std::vector<int>& x, const std::vector<int>& y) {
+      for (int k = N - 2; k >= 1; --k)
+        if (x[k] != y[k]) return x[k] < y[k];
+      return false;
+    });
+    for (auto& ee : found) {
+      auto& lst = side.by_c[ee.back()];
+      Tree t;
+      t.sec = sec;
+      t.e = ee;
+      t.n = n;
+      t.r0 = lst.empty() ? 0 : lst.back().r0 + lst.back().n;
+      side.index[{sec, ee}] = {ee.back(), static_cast<int>(lst.size())};
+      lst.push_back(std::move(t));
+    }
+    int k = 0;  // next outer tuple, colex (first leg fastest)
+    for (; k < N; ++k) {
+      if (++sec[k] < static_cast<int>(legs[k].tj.size())) break;
+      sec[k] = 0;
+    }
+    if (k == N) break;
+  }
+}
+
+struct Map {
+  std::vector<Leg> cod, dom;
+  Side rows, cols;
+  std::map<int, std::array<int64_t, 3>> blocks;  // c -> offset, R, C
+  int64_t size = 0;
+  void build() {
+    enumerate_trees(cod, rows);
+    enumerate_trees(dom, cols);
+    for (auto& [c, rl] : rows.by_c) {
+      auto it = cols.by_c.find(c);
+      if (it == cols.by_c.end()) continue;
+      const int64_t R = rl.back().r0 + rl.back().n, C = it->second.back().r0 + it->second.back().n;
+      blocks[c] = {size, R, C};
+      size += R * C;
+    }
+  }
+};
+
+// The permuted tree (new leg k = old leg perm[k]) in canonical trees of the
+// new outer spins: (new e sequence) -> coefficient.
+std::map<std::vector<int>, double> permute_tree(const std::vector<int>& outer0, const std::vector<int>& e0,
+                                                const std::vector<int>& perm) {
+  const int N = static_cast<int>(outer0.size());
+  std::vector<int> pos(N), cur(N);  // cur[k] = old leg now at position k
+  for (int k = 0; k < N; ++k) {
+    pos[perm[k]] = k;
+    cur[k] = k;
+  }
+  std::map<std::vector<int>, double> v{{e0, 1.0}};
+  bool moved = true;
+  while (moved) {  // bubble sort by target position, one adjacent swap at a time
+    moved = false;
+    for (int k = 0; k + 1 < N; ++k) {
+      if (pos[cur[k]] < pos[cur[k + 1]]) continue;
+      const int a = outer0[cur[k]], b = outer0[cur[k + 1]];
+      std::map<std::vector<int>, double> w;
+      for (const auto& [e, x] : v) {
+        if (k == 0) {
+          std::vector<int> e2 = e;
+          e2[0] = b;
+          w[e2] += x * rmove(a, b, e[1]);
+        } else {
+          const int el = e[k - 1], g = e[k + 1];
+          for (int f2 = std::abs(el - b); f2 <= el + b; f2 += 2) {
+            if (!triangle(f2, a, g)) continue;
+            const double cf = swap_coeff(el, a, b, g, e[k], f2);
+            if (cf == 0.0) continue;
+            std::vector<int> e2 = e;
+            e2[k] = f2;
+            w[e2] += x * cf;
+          }
+        }
+      }
+      v.swap(w);
+      std::swap(cur[k], cur[k + 1]);
+      moved = true;
+    }
+  }
+  for (auto it = v.begin(); it != v.end();) it = std::fabs(it->second) < 1e-14 ? v.erase(it) : std::next(it);
+  return v;
+}
+
+
+// Alg. "Non-abelian Tensor Transformation" as a gather: every output tree
+// pair (s', f') collects, from each input pair (s, f) whose transform
+// reaches it, the coefficient c_s c_f and the strides of the permuted input
+// array; one trace-kernel task (no traced pairs) per chunk of an output pair
+// sums them and writes each element once.
+struct Plan {
+  Map A, C;
+  TaskListT<tk::TraceTask> tl;
+  std::vector<tk::TraceContrib> contribs;
+  std::vector<int64_t> tab_dst, tab_src;
+  DevBuf d_contribs;
+  int device = -1;
+};
+
+void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q) {
+  const Map& A = P.A;
+  const Map& C = P.C;
+  const int N1 = static_cast<int>(A.cod.size()), N2 = static_cast<int>(A.dom.size()), n = N1 + N2;
+  std::vector<int> qd(N2);
+  for (int k = 0; k < N2; ++k) qd[k] = q[k] - N1;
+  // per side: coupled spin -> per input tree the (output position, coefficient) list
+  auto side_map = [](const std::vector<Leg>& legs, const Side& in, const Side& out, const std::vector<int>& perm) {
+    std::map<int, std::vector<std::vector<std::pair<int, double>>>> res;
+    const int N = static_cast<int>(legs.size());
+    for (const auto& [c, trees] : in.by_c) {
+      auto& lst = res[c];
+      for (const Tree& t : trees) {
+        std::vector<int> outer(N), nsec(N);
+        for (int k = 0; k < N; ++k) outer[k] = legs[k].tj[t.sec[k]];
+        for (int k = 0; k < N; ++k) nsec[k] = t.sec[perm[k]];
+        std::vector<std::pair<int, double>> row;
+        for (const auto& [e2, cf] : permute_tree(outer, t.e, perm)) {
+          auto it = out.index.find({nsec, e2});
+          if (it == out.index.end() || it->second.first != c) fail(TK_ERR_INVALID_ARG, "internal: SU(2) tree lost");
+          row.emplace_back(it->second.second, cf);
+        }
+        lst.push_back(std::move(row));
+      }
+    }
+    return res;
+  };
+  const auto rmap = side_map(A.cod, A.rows, C.rows, p);
+  const auto cmap = side_map(A.dom, A.cols, C.cols, qd);
+  auto strides = [](const std::vector<Leg>& legs, const Tree& t, int64_t base, int64_t* out) {
+    int64_t st = base;
+    for (size_t k = 0; k < legs.size(); ++k) {
+      out[k] = st;
+      st *= legs[k].deg[t.sec[k]];
+    }
+  };
+  std::map<std::tuple<int, int, int>, std::vector<std::pair<tk::TraceContrib, int64_t>>> by_out;
+  for (const auto& [c, blk] : A.blocks) {
+    const int64_t off = blk[0], R = blk[1];
+    const auto& rows = A.rows.by_c.at(c);
+    const auto& cols = A.cols.by_c.at(c);
+    for (size_t i = 0; i < rows.size(); ++i)
+      for (size_t j = 0; j < cols.size(); ++j) {
+        int64_t is[TK_MAX_RANK], js[TK_MAX_RANK];
+        strides(A.cod, rows[i], 1, is);
+        strides(A.dom, cols[j], R, js);
+        tk::TraceContrib cb{};
+        cb.src = off + rows[i].r0 + cols[j].r0 * R;
+        cb.nd = 0;
+        for (int m = 0; m < n; ++m) cb.ss[m] = checked_i32(m < N1 ? is[p[m]] : js[qd[m - N1]], "stride");
+        for (const auto& [si, cs] : rmap.at(c)[i])
+          for (const auto& [fj, cf] : cmap.at(c)[j]) {
+            cb.coef = cs * cf;
+            by_out[{c, si, fj}].emplace_back(cb, cb.src);
+          }
+      }
+  }
+  for (const auto& [c, blk] : C.blocks) {
+    const int64_t off = blk[0], R = blk[1];
+    const auto& rows = C.rows.by_c.at(c);
+    const auto& cols = C.cols.by_c.at(c);
+    for (size_t i = 0; i < rows.size(); ++i)
+      for (size_t j = 0; j < cols.size(); ++j) {
+        int64_t os[TK_MAX_RANK], od[TK_MAX_RANK];
+        strides(C.cod, rows[i], 1, os);
+        strides(C.dom, cols[j], R, os + N1);
+        for (int m = 0; m < N1; ++m) od[m] = C.cod[m].deg[rows[i].sec[m]];
+        for (int m = 0; m < N2; ++m) od[N1 + m] = C.dom[m].deg[cols[j].sec[m]];
+        const int64_t dst = off + rows[i].r0 + cols[j].r0 * R;
+        const int32_t c0 = checked_i32(static_cast<int64_t>(P.contribs.size()), "contributions");
+        auto it = by_out.find({c, static_cast<int>(i), static_cast<int>(j)});
+        if (it != by_out.end())
+          for (const auto& [cb, src] : it->second) {
+            P.contribs.push_back(cb);
+            P.tab_dst.push_back(dst);
+            P.tab_src.push_back(src);
+          }
+        const int32_t c1 = checked_i32(static_cast<int64_t>(P.contribs.size()), "contributions");
+        const int64_t total = rows[i].n * cols[j].n;
+        if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "SU(2) reduced array larger than 2^31 elements");
+        for (int64_t s0 = 0; s0 < total; s0 += kTraceChunk) {
+          tk::TraceTask t{};
+          t.dst = dst;
+          t.n = n;
+          t.start = static_cast<int32_t>(s0);
+          t.count = static_cast<int32_t>(std::min<int64_t>(kTraceChunk, total - s0));
+          t.c0 = c0;
+          t.c1 = c1;
+          t.src_buf = tk::kBufA;
+          t.dst_buf = tk::kBufC;
+          for (int m = 0; m < tk::kMaxDims; ++m) {
+            t.dim[m] = m < n ? checked_i32(od[m], "dim") : 1;
+            t.ds[m] = m < n ? checked_i32(os[m], "stride") : 0;
+            division_magic(static_cast<uint32_t>(t.dim[m]), &t.mag[m], &t.shr[m]);
+          }
+          P.tl.tasks.push_back(t);
+        }
+      }
+  }
+  pack_workgroups(P.tl, kTraceChunk);
+}
+
+}  // namespace su2
 
 // Whether a block with these dims and strides fills one contiguous range
 // (its non-unit dims, ordered by stride, are densely packed from stride 1);
@@ -2839,3 +3157,100 @@ tk_status tk_batch_destroy(tk_batch* batch) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// SU(2) leg permutation
+// ---------------------------------------------------------------------------
+struct tk_su2_plan {
+  su2::Plan P;
+};
+
+tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
+                             const int32_t* p, const int32_t* q, tk_su2_plan** out) {
+  return guarded([&] {
+    if (!out || !nsec || !twoj || !deg || !p || !q) fail(TK_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (n1 < 1 || n2 < 1) fail(TK_ERR_INVALID_ARG, "codomain and domain need at least one leg each");
+    if (n1 + n2 > tk::kMaxDims) fail(TK_ERR_UNSUPPORTED, "more than 8 legs");
+    auto plan = std::make_unique<tk_su2_plan>();
+    int64_t k = 0;
+    for (int l = 0; l < n1 + n2; ++l) {
+      if (nsec[l] < 1 || nsec[l] > 64) fail(TK_ERR_INVALID_ARG, "a leg needs 1..64 sectors");
+      su2::Leg leg;
+      for (int i = 0; i < nsec[l]; ++i, ++k) {
+        if (twoj[k] < 0 || twoj[k] > 64) fail(TK_ERR_CHARGE, "spin (twice its value) outside 0..64");
+        if (i > 0 && twoj[k] <= leg.tj.back()) fail(TK_ERR_CHARGE, "spins of a leg must be strictly ascending");
+        if (deg[k] < 1 || deg[k] > INT32_MAX) fail(TK_ERR_INVALID_ARG, "degeneracy outside 1..2^31-1");
+        leg.tj.push_back(twoj[k]);
+        leg.deg.push_back(deg[k]);
+      }
+      (l < n1 ? plan->P.A.cod : plan->P.A.dom).push_back(std::move(leg));
+    }
+    std::vector<int> pv(p, p + n1), qv(q, q + n2), seen(n1 + n2, 0);
+    for (int x : pv)
+      if (x < 0 || x >= n1 || seen[x]++) fail(TK_ERR_INVALID_ARG, "p must permute the codomain legs 0..n1-1");
+    for (int x : qv)
+      if (x < n1 || x >= n1 + n2 || seen[x]++) fail(TK_ERR_INVALID_ARG, "q must permute the domain legs n1..n1+n2-1");
+    for (int x : pv) plan->P.C.cod.push_back(plan->P.A.cod[x]);
+    for (int x : qv) plan->P.C.dom.push_back(plan->P.A.dom[x - n1]);
+    plan->P.A.build();
+    plan->P.C.build();
+    su2::plan_permute(plan->P, pv, qv);
+    *out = plan.release();
+  });
+}
+
+tk_status tk_su2_plan_info(const tk_su2_plan* plan, int64_t* in_size, int64_t* out_size, int64_t* ncontrib) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    if (in_size) *in_size = plan->P.A.size;
+    if (out_size) *out_size = plan->P.C.size;
+    if (ncontrib) *ncontrib = static_cast<int64_t>(plan->P.contribs.size());
+  });
+}
+
+tk_status tk_su2_plan_contribs(const tk_su2_plan* plan, int64_t cap, int64_t* dst, int64_t* src, double* coef) {
+  return guarded([&] {
+    if (!plan || !dst || !src || !coef) fail(TK_ERR_INVALID_ARG, "null argument");
+    const auto& P = plan->P;
+    if (cap < static_cast<int64_t>(P.contribs.size())) fail(TK_ERR_INVALID_ARG, "cap below the contribution count");
+    for (size_t i = 0; i < P.contribs.size(); ++i) {
+      dst[i] = P.tab_dst[i];
+      src[i] = P.tab_src[i];
+      coef[i] = P.contribs[i].coef;
+    }
+  });
+}
+
+tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* C, double alpha, double beta,
+                         void* stream) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    if (dtype != TK_F64 && dtype != TK_F32) fail(TK_ERR_DTYPE, "dtype must be TK_F64 or TK_F32");
+    auto& P = plan->P;
+    if (!A && P.A.size) fail(TK_ERR_INVALID_ARG, "A is null");
+    if (!C && P.C.size) fail(TK_ERR_INVALID_ARG, "C is null");
+    if (A && A == C) fail(TK_ERR_INVALID_ARG, "C aliases A");
+    int dev = 0;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (P.device < 0) {
+      P.tl.upload();
+      P.d_contribs.upload(P.contribs);
+      P.device = dev;
+    } else if (P.device != dev) {
+      fail(TK_ERR_INVALID_ARG, "the plan was first launched on another device");
+    }
+    tk::Ptrs ptrs{};
+    ptrs.p[tk::kBufA] = const_cast<void*>(A);
+    ptrs.p[tk::kBufC] = C;
+    hip_check(tk::launch_trace(dtype, static_cast<const tk::TraceTask*>(P.tl.d_tasks.p),
+                               static_cast<const int32_t*>(P.tl.d_wg.p), P.tl.nwg(),
+                               static_cast<const tk::TraceContrib*>(P.d_contribs.p), ptrs, alpha, beta,
+                               static_cast<hipStream_t>(stream)),
+              "SU(2) permute launch");
+  });
+}
+
+tk_status tk_su2_plan_destroy(tk_su2_plan* plan) {
+  return guarded([&] { delete plan; });
+}

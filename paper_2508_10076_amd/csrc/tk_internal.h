@@ -258,7 +258,7 @@ struct TraceTask {
 constexpr int kMaxTracePairs = 4;
 struct TraceContrib {
   int64_t src;
-  float sign;
+  double coef;  // the sign of a fermionic trace, a recoupling coefficient
   int32_t nd;
   int32_t ss[kMaxDims];
   int32_t dd[kMaxTracePairs];

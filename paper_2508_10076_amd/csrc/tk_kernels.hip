@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
 
 // Partial trace: thread per output element; the element's index in the
 // block is split over the output dimensions once, then each contribution
-// adds sign * (sum along its traced diagonal), and the element is written
+// adds coef * (sum along its traced diagonal), and the element is written
 // once (alpha times the trace plus beta times the old value).
 template <typename T>
 __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, const TraceContrib* __restrict__ cs,
@@ -184,7 +184,7 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
         }
         if (j == nd) break;
       }
-      acc += static_cast<double>(cb->sign) * sum;
+      acc += cb->coef * sum;
     }
     double v = alpha * acc;
     if (beta != 0.0) v += beta * static_cast<double>(dst[dof]);

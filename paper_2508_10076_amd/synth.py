@@ -220,3 +220,32 @@ def random_space(g: np.random.Generator, sym: str, max_sect: int = 3, max_deg: i
     secs = [cands[i] for i in pick]
     degs = [int(g.integers(1, max_deg + 1)) for _ in secs]
     return space(secs, degs, bool(g.random() < dual_prob))
+
+
+# ---- SU(2) spin-1 chain -------------------------------------------------------
+# The SU(2) benchmark of the paper is the spin-1 Heisenberg chain: physical
+# leg spin 1, virtual legs with integer spins.  Synthetic virtual leg: spins
+# j = 0..jmax with multiplicities ~ exp(-j^2 / 2 sigma^2) summing to Dred
+# (the number of multiplets); the dense dimension is sum deg(j) (2j + 1).
+SU2_PHYS = [(2, 1)]  # (twice the spin, degeneracy): spin 1
+
+
+def su2_virtual(Dred: int, jmax: int, sigma: float):
+    """Virtual leg as [(2j, deg)], j = 0..jmax (largest-remainder rounding of
+    the Gaussian shares; every spin keeps at least one multiplet)."""
+    js = np.arange(0, jmax + 1)
+    w = np.exp(-js.astype(float) ** 2 / (2.0 * sigma * sigma))
+    share = w / w.sum() * Dred
+    d = np.maximum(np.floor(share).astype(np.int64), 1)
+    left = Dred - int(d.sum())
+    order = sorted(range(len(js)), key=lambda i: (-(share[i] - np.floor(share[i])), i))
+    for i in order[:max(0, left)]:
+        d[i] += 1
+    return [(2 * int(j), int(x)) for j, x in zip(js, d)]
+
+
+def su2_two_site(Dred: int, jmax: int, sigma: float):
+    """x2 : V (x) P (x) P <- V and the swap of its two physical legs
+    (codomain (0, 2, 1), domain (3)): the braid of a two-site gate."""
+    V = su2_virtual(Dred, jmax, sigma)
+    return dict(cod=[V, SU2_PHYS, SU2_PHYS], dom=[V], p=[0, 2, 1], q=[3])

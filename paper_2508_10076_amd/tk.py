@@ -92,6 +92,11 @@ _SIGS = {
     "tk_batch_destroy": [_P],
     "tk_tile_shapes": [_I32P, _I32P],
     "tk_plan_set_tile": [_P, C.c_int32, C.c_int32, C.c_int32],
+    "tk_su2_plan_create": [C.c_int32, C.c_int32, _I32P, _I32P, _I64P, _I32P, _I32P, C.POINTER(_P)],
+    "tk_su2_plan_info": [_P, _I64P, _I64P, _I64P],
+    "tk_su2_plan_contribs": [_P, C.c_int64, _I64P, _I64P, C.POINTER(C.c_double)],
+    "tk_su2_permute": [_P, C.c_int32, _P, _P, C.c_double, C.c_double, _P],
+    "tk_su2_plan_destroy": [_P],
     "tk_batch_set_tile": [_P, C.c_int32, C.c_int32, C.c_int32],
 }
 for _name, _args in _SIGS.items():
@@ -353,6 +358,49 @@ def tensor_svd(ctx, A, p, q, max_dim=-1, cutoff=0.0, stream=None):
     finally:
         lib.tk_svd_destroy(h)
     return U, S, Vh, err.value
+
+
+class SU2Plan:
+    """permute(A, (p, q)) of an SU(2) tensor map cod <- dom whose legs are
+    lists of (twice the spin, degeneracy); p and q permute the codomain and
+    the domain legs (numbered as in tk_su2_plan_create)."""
+
+    def __init__(self, cod, dom, p, q):
+        legs = [sorted(l) for l in list(cod) + list(dom)]
+        nsec, nl = _ilist([len(l) for l in legs])
+        tj, _ = _ilist([x for l in legs for x, _ in l])
+        deg = (C.c_int64 * max(1, sum(len(l) for l in legs)))(*[d for l in legs for _, d in l])
+        (pa, npa), (qa, nqa) = _ilist(p), _ilist(q)
+        self.h = C.c_void_p()
+        _check(lib.tk_su2_plan_create(len(cod), len(dom), nsec, tj, deg, pa, qa, C.byref(self.h)))
+        a, b, n = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib.tk_su2_plan_info(self.h, C.byref(a), C.byref(b), C.byref(n)))
+        self.in_size, self.out_size, self.ncontrib = a.value, b.value, n.value
+
+    def contribs(self):
+        """Host table: (output array start, input array start, coefficient)."""
+        n = max(1, self.ncontrib)
+        d, s_, c = (C.c_int64 * n)(), (C.c_int64 * n)(), (C.c_double * n)()
+        _check(lib.tk_su2_plan_contribs(self.h, self.ncontrib, d, s_, c))
+        return [(d[i], s_[i], c[i]) for i in range(self.ncontrib)]
+
+    def permute(self, A, C_=None, alpha=1.0, beta=0.0, stream=None):
+        """C = alpha * permute(A) + beta * C on device tensors (fp64 or fp32)."""
+        dt = {torch.float64: 0, torch.float32: 1}[A.dtype]
+        if A.numel() != self.in_size:
+            raise ValueError("A has %d elements, the plan needs %d" % (A.numel(), self.in_size))
+        if C_ is None:
+            C_ = torch.zeros(self.out_size, dtype=A.dtype, device=A.device)
+        if C_.numel() != self.out_size or C_.dtype != A.dtype or not (A.is_contiguous() and C_.is_contiguous()):
+            raise ValueError("C must be a contiguous tensor of the output size and A's dtype")
+        _check(lib.tk_su2_permute(self.h, dt, C.c_void_p(A.data_ptr()), C.c_void_p(C_.data_ptr()), float(alpha),
+                                  float(beta), _stream(stream)))
+        return C_
+
+    def __del__(self, _destroy=lib.tk_su2_plan_destroy):
+        if getattr(self, "h", None):
+            _destroy(self.h)
+            self.h = None
 
 
 def tensor_create_adjoint(ctx, A):

@@ -289,3 +289,67 @@ def test_error_paths():
         pl = tk.Plan(None, A, [0, 1], [2], B, [0], [1, 2], [0, 1], [2, 3], Cn)
         pl.execute(A, B, Cn, stream=0)
     assert e.value.status == 1
+
+
+# ---- SU(2) recoupling tables (host only: the plan makes no GPU call) ----------
+
+def _su2_oracle_table(st, p, q):
+    """(output array start, input array start) -> coefficient, from the
+    oracle's permute of unit inputs at each input array's first element."""
+    from oracle import su2
+    res = {}
+    for tc, s, f in st.pairs():
+        off, R, _ = st.blocks[tc]
+        src = off + s[2] + f[2] * R
+        e = np.zeros(st.size)
+        e[src] = 1.0
+        _, y = su2.permute(st, e, p, q)
+        for i in np.nonzero(np.abs(y) > 1e-14)[0]:
+            res[(int(i), src)] = y[i]
+    return res
+
+
+SU2_HOST_CASES = [
+    ([[(0, 1), (1, 1)]] * 2, [[(0, 1), (1, 1)]] * 2, [1, 0], [3, 2]),
+    ([[(0, 1), (1, 2)], [(1, 1), (2, 2)], [(1, 2), (3, 1)]],
+     [[(1, 2), (2, 1)], [(0, 1), (1, 2), (2, 1)], [(1, 1), (3, 1)]], [2, 0, 1], [4, 5, 3]),
+    ([[(2, 2), (4, 1)], [(2, 1)], [(2, 1)]], [[(0, 1), (2, 2), (4, 1)]], [0, 2, 1], [3]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SU2_HOST_CASES)))
+def test_su2_coefficients_match_oracle(case):
+    """The library's F/R-move coefficients (6j symbols) against the oracle's
+    projections of dense Clebsch-Gordan trees."""
+    from oracle import su2
+    cod, dom, p, q = SU2_HOST_CASES[case]
+    st = su2.SU2Map(cod, dom)
+    plan = tk.SU2Plan(cod, dom, p, q)
+    assert plan.in_size == st.size and plan.out_size == su2.permute_legs(st, p, q).size
+    got = {}
+    for d, s, c in plan.contribs():
+        got[(d, s)] = got.get((d, s), 0.0) + c
+    want = _su2_oracle_table(st, p, q)
+    assert set(got) == set(want)
+    assert max(abs(got[k] - want[k]) for k in want) < 1e-13
+
+
+def test_su2_error_paths():
+    V = [(0, 1), (1, 1)]
+    with pytest.raises(tk.TkError) as e:
+        tk.SU2Plan([V, V], [V, V], [0, 2], [1, 3])  # a leg would change sides
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:
+        tk.SU2Plan([V, V], [V, V], [0, 0], [2, 3])
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:
+        tk.SU2Plan([[(1, 1), (1, 2)]], [V], [0], [1])  # repeated spin
+    assert e.value.status == 3
+    with pytest.raises(tk.TkError) as e:
+        tk.SU2Plan([[(0, 0)]], [V], [0], [1])  # empty degeneracy
+    assert e.value.status == 1
+    with pytest.raises(tk.TkError) as e:
+        tk.SU2Plan([V] * 5, [V] * 4, list(range(5)), list(range(5, 9)))
+    assert e.value.status == 5
+    plan = tk.SU2Plan([[(1, 1)]], [[(0, 1)]], [0], [1])  # no common coupled spin
+    assert plan.in_size == 0 and plan.out_size == 0 and plan.ncontrib == 0
