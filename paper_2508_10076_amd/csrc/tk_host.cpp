@@ -1202,6 +1202,11 @@ struct Plan {
   int device = -1;
 };
 
+// Elements per recoupling task: one pass of the gather kernel's 256-thread
+// workgroup at 8 elements per thread (1024 and 4096 measured slower on the
+// spin-1 two-site swap).
+constexpr int64_t kSu2Chunk = 2048;
+
 void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q) {
   const Map& A = P.A;
   const Map& C = P.C;
@@ -1275,6 +1280,11 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
         auto it = by_out.find({c, static_cast<int>(i), static_cast<int>(j)});
         if (it != by_out.end())
           for (const auto& [cb, src] : it->second) {
+            // the gather kernel forms one source offset per element: every input
+            // of this output array (same outer sectors, same coupled spin) has
+            // the same strides
+            if (std::memcmp(cb.ss, it->second.front().first.ss, sizeof(cb.ss)) != 0)
+              fail(TK_ERR_INVALID_ARG, "internal: SU(2) inputs of one output differ in strides");
             P.contribs.push_back(cb);
             P.tab_dst.push_back(dst);
             P.tab_src.push_back(src);
@@ -1282,12 +1292,12 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
         const int32_t c1 = checked_i32(static_cast<int64_t>(P.contribs.size()), "contributions");
         const int64_t total = rows[i].n * cols[j].n;
         if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "SU(2) reduced array larger than 2^31 elements");
-        for (int64_t s0 = 0; s0 < total; s0 += kTraceChunk) {
+        for (int64_t s0 = 0; s0 < total; s0 += kSu2Chunk) {
           tk::TraceTask t{};
           t.dst = dst;
           t.n = n;
           t.start = static_cast<int32_t>(s0);
-          t.count = static_cast<int32_t>(std::min<int64_t>(kTraceChunk, total - s0));
+          t.count = static_cast<int32_t>(std::min<int64_t>(kSu2Chunk, total - s0));
           t.c0 = c0;
           t.c1 = c1;
           t.src_buf = tk::kBufA;
@@ -1301,7 +1311,7 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
         }
       }
   }
-  pack_workgroups(P.tl, kTraceChunk);
+  pack_workgroups(P.tl, kSu2Chunk);
 }
 
 }  // namespace su2
@@ -2677,7 +2687,7 @@ tk_status tk_tensor_trace(tk_context* ctx, const tk_tensor* A, const int32_t* p,
     ptrs.p[tk::kBufC] = C->data;
     hip_check(tk::launch_trace(A->dtype, static_cast<const tk::TraceTask*>(tp->tl.d_tasks.p),
                                static_cast<const int32_t*>(tp->tl.d_wg.p), tp->tl.nwg(),
-                               static_cast<const tk::TraceContrib*>(tp->d_contribs.p), ptrs, alpha, beta,
+                               static_cast<const tk::TraceContrib*>(tp->d_contribs.p), ptrs, alpha, beta, false,
                                static_cast<hipStream_t>(stream)),
               "trace launch");
   });
@@ -3245,7 +3255,7 @@ tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* 
     ptrs.p[tk::kBufC] = C;
     hip_check(tk::launch_trace(dtype, static_cast<const tk::TraceTask*>(P.tl.d_tasks.p),
                                static_cast<const int32_t*>(P.tl.d_wg.p), P.tl.nwg(),
-                               static_cast<const tk::TraceContrib*>(P.d_contribs.p), ptrs, alpha, beta,
+                               static_cast<const tk::TraceContrib*>(P.d_contribs.p), ptrs, alpha, beta, true,
                                static_cast<hipStream_t>(stream)),
               "SU(2) permute launch");
   });

@@ -264,8 +264,11 @@ struct TraceContrib {
   int32_t dd[kMaxTracePairs];
   int32_t dstr[kMaxTracePairs];
 };
+// gather: no contribution has a traced pair (nd == 0 throughout) and the
+// contributions of each task share their strides ss, which selects the
+// unrolled plain-gather variant.
 hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_first, int nwg,
-                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta,
+                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta, bool gather,
                         hipStream_t stream);
 // Singular value decomposition of one coupled-sector matrix (R x C,
 // column-major) by one-sided Jacobi rotations on its m x n working copy W

@@ -192,7 +192,68 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
   }
 }
 
+// The same task when no contribution has a traced pair and all of a task's
+// contributions share their strides (the inputs of one output array differ
+// only in where they start, as in a recoupling): per element the source
+// offset is formed once, and each thread takes kGatherUnroll elements at
+// once so that all of their loads (every element times every term) are in
+// flight together.
+constexpr int kGatherUnroll = 8;
+
 template <typename T>
+__device__ __forceinline__ void gather_task(const TraceTask* __restrict__ tk, const TraceContrib* __restrict__ cs,
+                                            const Ptrs& P, double alpha, double beta, int lt, int nthr) {
+  const int n = tk->n, count = tk->count, c0 = tk->c0, c1 = tk->c1;
+  const uint32_t start = static_cast<uint32_t>(tk->start);
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, tk->src_buf);
+  int32_t ss[kMaxDims] = {0, 0, 0, 0, 0, 0, 0, 0};  // the shared source strides (none without terms)
+  if (c1 > c0) {
+#pragma unroll
+    for (int d = 0; d < kMaxDims; ++d) ss[d] = cs[c0].ss[d];
+  }
+  for (int e0 = lt; e0 < count; e0 += kGatherUnroll * nthr) {
+    int64_t dof[kGatherUnroll], rel[kGatherUnroll];
+    double acc[kGatherUnroll];
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      const int e = e0 + u * nthr;
+      uint32_t lin = start + static_cast<uint32_t>(e < count ? e : 0);
+      dof[u] = 0;
+      rel[u] = 0;
+      acc[u] = 0.0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        if (d < n) {
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
+          const int64_t i = static_cast<int64_t>(lin - q * static_cast<uint32_t>(tk->dim[d]));
+          lin = q;
+          dof[u] += i * tk->ds[d];
+          rel[u] += i * ss[d];
+        }
+      }
+    }
+    for (int c = c0; c < c1; ++c) {
+      const int64_t base = cs[c].src;
+      const double coef = cs[c].coef;
+      double v[kGatherUnroll];
+#pragma unroll
+      for (int u = 0; u < kGatherUnroll; ++u)
+        v[u] = e0 + u * nthr < count ? static_cast<double>(src[base + rel[u]]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < kGatherUnroll; ++u) acc[u] += coef * v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kGatherUnroll; ++u) {
+      if (e0 + u * nthr >= count) break;
+      double r = alpha * acc[u];
+      if (beta != 0.0) r += beta * static_cast<double>(dst[dof[u]]);
+      dst[dof[u]] = static_cast<T>(r);
+    }
+  }
+}
+
+template <typename T, bool GATHER>
 __global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __restrict__ tasks,
                                                          const int32_t* __restrict__ wg_first,
                                                          const TraceContrib* __restrict__ cs, Ptrs P, double alpha,
@@ -200,11 +261,19 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __rest
   const int t0 = wg_first[blockIdx.x];
   const int t1 = wg_first[blockIdx.x + 1];
   if (t1 - t0 == 1) {
-    trace_task<T>(tasks + t0, cs, P, alpha, beta, threadIdx.x, kThreads);
+    if (GATHER)
+      gather_task<T>(tasks + t0, cs, P, alpha, beta, threadIdx.x, kThreads);
+    else
+      trace_task<T>(tasks + t0, cs, P, alpha, beta, threadIdx.x, kThreads);
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = t0 + wave; t < t1; t += kThreads / 64) trace_task<T>(tasks + t, cs, P, alpha, beta, lane, 64);
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) {
+    if (GATHER)
+      gather_task<T>(tasks + t, cs, P, alpha, beta, lane, 64);
+    else
+      trace_task<T>(tasks + t, cs, P, alpha, beta, lane, 64);
+  }
 }
 
 // One-sided (Hestenes) Jacobi SVD, one workgroup per coupled-sector
@@ -1443,15 +1512,12 @@ hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, c
 }
 
 hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_first, int nwg,
-                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta,
+                        const TraceContrib* contribs, const Ptrs& ptrs, double alpha, double beta, bool gather,
                         hipStream_t stream) {
   if (nwg <= 0) return hipSuccess;
-  if (dtype == 0)
-    hipLaunchKernelGGL(trace_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs,
-                       alpha, beta);
-  else
-    hipLaunchKernelGGL(trace_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs,
-                       alpha, beta);
+  const auto kernel = dtype == 0 ? (gather ? trace_kernel<double, true> : trace_kernel<double, false>)
+                                 : (gather ? trace_kernel<float, true> : trace_kernel<float, false>);
+  hipLaunchKernelGGL(kernel, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first, contribs, ptrs, alpha, beta);
   return hipGetLastError();
 }
 
