@@ -1264,12 +1264,28 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
           }
       }
   }
+  // Output pairs with the same outer sectors (they differ only in
+  // intermediate spins) read the same input arrays at the same relative
+  // offsets; their tasks are interleaved in runs of 8 chunks so that chunk k
+  // of every such sibling lands on the same XCD (workgroups are dealt to the
+  // 8 XCDs round-robin) at about the same time, and the shared inputs are
+  // served from that XCD's L2.
+  std::map<std::tuple<int, std::vector<int>, std::vector<int>>, size_t> group_of;
+  std::vector<std::vector<std::vector<tk::TraceTask>>> groups;
   for (const auto& [c, blk] : C.blocks) {
     const int64_t off = blk[0], R = blk[1];
     const auto& rows = C.rows.by_c.at(c);
     const auto& cols = C.cols.by_c.at(c);
     for (size_t i = 0; i < rows.size(); ++i)
       for (size_t j = 0; j < cols.size(); ++j) {
+        auto key = std::make_tuple(c, rows[i].sec, cols[j].sec);
+        auto g = group_of.find(key);
+        if (g == group_of.end()) {
+          g = group_of.emplace(key, groups.size()).first;
+          groups.emplace_back();
+        }
+        groups[g->second].emplace_back();
+        auto& mine = groups[g->second].back();
         int64_t os[TK_MAX_RANK], od[TK_MAX_RANK];
         strides(C.cod, rows[i], 1, os);
         strides(C.dom, cols[j], R, os + N1);
@@ -1307,9 +1323,17 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
             t.ds[m] = m < n ? checked_i32(os[m], "stride") : 0;
             division_magic(static_cast<uint32_t>(t.dim[m]), &t.mag[m], &t.shr[m]);
           }
-          P.tl.tasks.push_back(t);
+          mine.push_back(t);
         }
       }
+  }
+  constexpr size_t kRun = 8;  // one chunk per XCD
+  for (const auto& sib : groups) {
+    size_t nchunk = 0;
+    for (const auto& tl : sib) nchunk = std::max(nchunk, tl.size());
+    for (size_t b = 0; b < nchunk; b += kRun)
+      for (const auto& tl : sib)
+        for (size_t k = b; k < std::min(b + kRun, tl.size()); ++k) P.tl.tasks.push_back(tl[k]);
   }
   pack_workgroups(P.tl, kSu2Chunk);
 }
