@@ -308,10 +308,25 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
   for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * n; e += kSvdThreads)
     V[e] = (e % n == e / n) ? 1.0 : 0.0;
   __shared__ int s_rot;
+  // squared column norms of W (columns of up to kSvdCache * 64 rows, so
+  // n <= m <= 512): formed at the start of every sweep and carried through
+  // each rotation (a' = a - t g, b' = b + t g), so a rotation reduces only
+  // the inner product g across the wave
+  __shared__ double s_nrm[kSvdCache * 64];
+  const bool cached = m <= kSvdCache * 64;
   __syncthreads();
   const int nn = n + (n & 1), wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kSvdThreads / 64;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;
+    if (cached) {
+      for (int j = wave; j < n; j += nw) {
+        const double* Wj = W + static_cast<int64_t>(m) * j;
+        double a = 0.0;
+        for (int i = lane; i < m; i += 64) a += Wj[i] * Wj[i];
+        a = wave_sum(a);
+        if (lane == 0) s_nrm[j] = a;
+      }
+    }
     __syncthreads();
     for (int r = 0; r < nn - 1; ++r) {
       for (int k = wave; k < nn / 2; k += nw) {
@@ -323,7 +338,7 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
         double* Vp = V + static_cast<int64_t>(n) * p;
         double* Vq = V + static_cast<int64_t>(n) * q;
         double a = 0.0, b = 0.0, g = 0.0;
-        if (m <= kSvdCache * 64) {
+        if (cached) {
           // columns of up to kSvdCache * 64 rows: every element this lane
           // needs (of W and of V) is loaded once, before any arithmetic
           double xw[kSvdCache], yw[kSvdCache], xv[kSvdCache], yv[kSvdCache];
@@ -336,13 +351,9 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
             yv[u] = i < n ? Vq[i] : 0.0;
           }
 #pragma unroll
-          for (int u = 0; u < kSvdCache; ++u) {
-            a += xw[u] * xw[u];
-            b += yw[u] * yw[u];
-            g += xw[u] * yw[u];
-          }
-          a = wave_sum(a);
-          b = wave_sum(b);
+          for (int u = 0; u < kSvdCache; ++u) g += xw[u] * yw[u];
+          a = s_nrm[p];
+          b = s_nrm[q];
           g = wave_sum(g);
           if (!(a > 0.0 && b > 0.0) || fabs(g) <= tol * sqrt(a * b)) continue;
           const double zeta = (b - a) / (2.0 * g);
@@ -360,7 +371,11 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
               Vq[i] = s * xv[u] + c * yv[u];
             }
           }
-          if (lane == 0) s_rot = 1;
+          if (lane == 0) {
+            s_rot = 1;
+            s_nrm[p] = a - t * g;
+            s_nrm[q] = b + t * g;
+          }
           continue;
         }
         for (int i = lane; i < m; i += 64) {
