@@ -84,3 +84,18 @@ def test_su2_identity_is_a_copy_and_empty_is_a_no_op():
     assert plan.out_size == 0
     plan.permute(torch.zeros(0, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
+
+
+def test_su2_full_size_two_site_swap():
+    """The bench workload itself (spin-1 two-site swap, 4096 multiplets over
+    spins 0..10, 15.6M entries), in the launch configuration the bench times,
+    compared with the oracle on every entry."""
+    w = synth.su2_two_site(4096, 10, 4.0)
+    st = su2.SU2Map(w["cod"], w["dom"])
+    x = synth.normal(st.size, 9, 0)
+    print(f"case su2_two_site_D4096: {st.size} elements", flush=True)
+    _, want = su2.permute(st, x, w["p"], w["q"])
+    got = _run(w["cod"], w["dom"], w["p"], w["q"], x)
+    assert np.all(np.isfinite(got)), "an output element was never written"
+    assert np.linalg.norm(got - want) <= 1e-12 * np.linalg.norm(want)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
