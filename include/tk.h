@@ -374,8 +374,9 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int
  *   A and C are device arrays of dtype (TK_F64 or TK_F32) with the plan's
  *   input and output sizes, caller-owned, not aliased; beta == 0 never
  *   reads C.  The plan's tables go to the current device on the first call
- *   and the plan stays bound to that device.  One launch; the plan must
- *   outlive the work enqueued with it. */
+ *   and the plan stays bound to that device; that first call must not
+ *   overlap another call with the same plan from a second host thread.
+ *   One launch; the plan must outlive the work enqueued with it. */
 typedef struct tk_su2_plan tk_su2_plan;
 tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
                              const int32_t* p, const int32_t* q, tk_su2_plan** out);
