@@ -300,6 +300,25 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* counts /* 14 values */);
 /* (M, N, K) of sector GEMMs first..first+count-1 (3 * count values). */
 tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64_t* mnk);
 
+/* Host copies of a plan's work lists for the kernels that stage a
+ * workgroup's items in LDS: kind = 0 the zero ranges (empty-K blocks that
+ * are contiguous ranges of C), kind = K (1..8) the output runs of the
+ * small-K sectors with that K.  The items of a list are laid end to end;
+ * counts receives 3 values: items, workgroups, dimension records (0 for
+ * zero ranges).  Every other pointer may be NULL; otherwise it receives, per
+ * item, vstart (its first element in the concatenation) and len (elements),
+ * and for runs lin0 (linear index of the run's first element in its output
+ * block) and shape (its dimension record); first and wstart (workgroups + 1
+ * values each): workgroup w covers elements wstart[w] .. wstart[w+1]-1 and
+ * item first[w] holds element wstart[w]; dimrec (25 values per record): the
+ * number of dimensions nd (<= 8), then per dimension its extent and the
+ * magic and shift of the multiply-high division the kernel splits linear
+ * indices with (floor(x / extent) = (x * magic) >> shift for x < 2^24).
+ * Call once with NULL arrays to size them.  Host only; lets a CPU test
+ * replay every LDS index the kernels form. */
+tk_status tk_plan_worklist(const tk_plan* plan, int32_t kind, int64_t* counts, int64_t* vstart, int64_t* len,
+                           int32_t* lin0, int32_t* shape, int32_t* first, int64_t* wstart, int32_t* dimrec);
+
 /* Channel map of a permute: for every channel i of A (storage order) the
  * channel index of C it lands in and its sign (+1 / -1).  Host only. */
 tk_status tk_permute_map(const tk_tensor* A, const int32_t* p, int32_t np, const int32_t* q,

@@ -444,6 +444,37 @@ struct TaskListT {
 using TaskList = TaskListT<PermTask>;
 using SkBlockList = TaskListT<tk::SkBlockTask>;
 
+// Limits of the workgroup tables of the zero-range and output-run kernels,
+// which stage a workgroup's items in LDS arrays of max_items + 1 entries and
+// index its elements (at most chunk) through an LDS map: every item holds at
+// least one element, workgroup w covers elements wstart[w] .. wstart[w+1]-1
+// (1..chunk of them), item first[w] holds its first element, first[] never
+// decreases, and the items from first[w] to first[w+1] (the last one may
+// start exactly at the workgroup's end) number at most max_items + 1.  A
+// violation is a planner bug; it fails the plan instead of reaching a kernel.
+void check_chunks(const std::vector<int64_t>& vstart, int64_t total, const std::vector<int32_t>& first,
+                  const std::vector<int64_t>& wstart, int chunk, int max_items, const char* what) {
+  const int64_t n = static_cast<int64_t>(vstart.size());
+  auto bad = [&](const char* why) { fail(TK_ERR_UNSUPPORTED, std::string(what) + " work list: " + why); };
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t end = i + 1 < n ? vstart[i + 1] : total;
+    if (end - vstart[i] < 1) bad("an item without elements");
+  }
+  if (n == 0) return;
+  if (first.size() != wstart.size() || wstart.size() < 2 || wstart.front() != 0 || wstart.back() != total)
+    bad("workgroup bounds");
+  for (size_t w = 0; w + 1 < wstart.size(); ++w) {
+    const int64_t len = wstart[w + 1] - wstart[w];
+    if (len < 1 || len > chunk) bad("workgroup size");
+    const int32_t f = first[w], f1 = first[w + 1];
+    if (f < 0 || f1 < f || f1 >= n) bad("item order");
+    const int64_t fend = f + 1 < n ? vstart[f + 1] : total;
+    if (vstart[f] > wstart[w] || fend <= wstart[w]) bad("first item does not hold the first element");
+    if (static_cast<int64_t>(std::min<int64_t>(n, static_cast<int64_t>(f1) + 1)) - f > max_items + 1)
+      bad("too many items in one workgroup");
+  }
+}
+
 // Ranges of elements to zero: collected as (buffer, offset, length), then
 // sorted, merged where adjacent, and laid end to end as one virtual array
 // cut into workgroups of at most kZeroChunk elements in at most kZeroMax
@@ -495,6 +526,9 @@ struct ZeroSet {
       first.push_back(static_cast<int32_t>(r));
     }
     if (wstart.size() - 1 > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "zero fill too large");
+    std::vector<int64_t> vs(ranges.size());
+    for (size_t i = 0; i < ranges.size(); ++i) vs[i] = ranges[i].vstart;
+    check_chunks(vs, total, first, wstart, tk::kZeroChunk, tk::kZeroMax, "zero-range");
   }
   int nwg() const { return wstart.empty() ? 0 : static_cast<int>(wstart.size()) - 1; }
   void upload() {
@@ -555,6 +589,20 @@ struct RunSet {
       first.push_back(static_cast<int32_t>(r));
     }
     if (wstart.size() - 1 > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many output-run workgroups");
+    std::vector<int64_t> vs(runs.size());
+    for (size_t i = 0; i < runs.size(); ++i) {
+      const tk::SkRun& rn = runs[i];
+      vs[i] = rn.vstart;
+      if (rn.shape < 0 || rn.shape >= static_cast<int32_t>(shapes.size()))
+        fail(TK_ERR_UNSUPPORTED, "output run with a bad dimension record");
+      const tk::SkRunShape& sh = shapes[rn.shape];
+      if (sh.nd < 0 || sh.nd > 8) fail(TK_ERR_UNSUPPORTED, "output-run record with more than 8 dimensions");
+      int64_t cap = 1;
+      for (int o = 0; o < sh.nd; ++o) cap *= sh.dim[o].dimshr & 0xffffff;
+      if (rn.lin0 < 0 || rn.lin0 + static_cast<int64_t>(rn.len) > cap)
+        fail(TK_ERR_UNSUPPORTED, "output run reaches past its block");
+    }
+    check_chunks(vs, total, first, wstart, tk::kRunChunk, tk::kRunMax, "output-run");
   }
   int nwg() const { return wstart.empty() ? 0 : static_cast<int>(wstart.size()) - 1; }
   void upload() {
@@ -2841,6 +2889,59 @@ tk_status tk_plan_gemms(const tk_plan* plan, int64_t first, int64_t count, int64
     if (first < 0 || count < 0 || first + count > static_cast<int64_t>(plan->mnk.size() / 3))
       fail(TK_ERR_INVALID_ARG, "range out of bounds");
     std::copy(plan->mnk.begin() + 3 * first, plan->mnk.begin() + 3 * (first + count), mnk);
+  });
+}
+
+tk_status tk_plan_worklist(const tk_plan* plan, int32_t kind, int64_t* counts, int64_t* vstart, int64_t* len,
+                           int32_t* lin0, int32_t* shape, int32_t* first, int64_t* wstart, int32_t* dimrec) {
+  return guarded([&] {
+    if (!plan || !counts) fail(TK_ERR_INVALID_ARG, "null argument");
+    if (kind < 0 || kind > 8) fail(TK_ERR_INVALID_ARG, "kind must be 0 (zero ranges) or a K value 1..8");
+    const std::vector<int32_t>* fi;
+    const std::vector<int64_t>* ws;
+    int64_t total, n, nrec = 0;
+    if (kind == 0) {
+      const ZeroSet& z = plan->zranges;
+      fi = &z.first;
+      ws = &z.wstart;
+      total = z.total;
+      n = static_cast<int64_t>(z.ranges.size());
+      for (int64_t i = 0; i < n; ++i) {
+        if (vstart) vstart[i] = z.ranges[i].vstart;
+        if (len) len[i] = (i + 1 < n ? z.ranges[i + 1].vstart : total) - z.ranges[i].vstart;
+      }
+    } else {
+      const RunSet& r = plan->skruns[kind];
+      fi = &r.first;
+      ws = &r.wstart;
+      total = r.total;
+      n = static_cast<int64_t>(r.runs.size());
+      nrec = static_cast<int64_t>(r.shapes.size());
+      for (int64_t i = 0; i < n; ++i) {
+        if (vstart) vstart[i] = r.runs[i].vstart;
+        if (len) len[i] = r.runs[i].len;
+        if (lin0) lin0[i] = r.runs[i].lin0;
+        if (shape) shape[i] = r.runs[i].shape;
+      }
+      if (dimrec)
+        for (int64_t i = 0; i < nrec; ++i) {
+          const tk::SkRunShape& sh = r.shapes[i];
+          int32_t* o = dimrec + 25 * i;
+          o[0] = sh.nd;
+          for (int d = 0; d < 8; ++d) {
+            const bool used = d < sh.nd;
+            o[1 + 3 * d] = used ? static_cast<int32_t>(sh.dim[d].dimshr & 0xffffff) : 0;
+            o[2 + 3 * d] = used ? static_cast<int32_t>(sh.dim[d].mag) : 0;
+            o[3 + 3 * d] = used ? static_cast<int32_t>(32 + (sh.dim[d].dimshr >> 24)) : 0;
+          }
+        }
+    }
+    const int64_t nwg = fi->empty() ? 0 : static_cast<int64_t>(fi->size()) - 1;
+    if (first) std::copy(fi->begin(), fi->end(), first);
+    if (wstart) std::copy(ws->begin(), ws->end(), wstart);
+    counts[0] = n;
+    counts[1] = nwg;
+    counts[2] = nrec;
   });
 }
 

@@ -82,6 +82,7 @@ _SIGS = {
     "tk_plan_info": [_P, _I64P, C.POINTER(C.c_double), _I64P, _I64P, _I32P, _I32P, _I32P],
     "tk_plan_gemms": [_P, C.c_int64, C.c_int64, _I64P],
     "tk_plan_counts": [_P, _I64P],
+    "tk_plan_worklist": [_P, C.c_int32, _I64P, _I64P, _I64P, _I32P, _I32P, _I32P, _I64P, _I32P],
     "tk_permute_map": [_P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I64P, _I32P],
     "tk_batch_create": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.POINTER(_P), C.c_int32, C.c_double,
                         C.c_double, C.POINTER(_P)],
@@ -475,6 +476,23 @@ class Plan:
         keys = ("pre_tasks", "pre_wgs", "zero_tasks", "zero_wgs", "smallk_tasks", "smallk_wgs", "gemm_descs",
                 "tiles", "gemm_wgs", "split_groups", "split_slots", "makespan_stages", "smallk_runs", "run_wgs")
         return dict(zip(keys, out.tolist()))
+
+    def worklist(self, kind):
+        """Host copy of the zero-range (kind 0) or K-output-run (kind K) work
+        list: dict of numpy arrays (see tk_plan_worklist)."""
+        cnt = np.zeros(3, np.int64)
+        _check(lib.tk_plan_worklist(self.h, int(kind), cnt.ctypes.data_as(_I64P), None, None, None, None, None,
+                                    None, None))
+        n, nwg, nrec = (int(x) for x in cnt)
+        out = dict(vstart=np.zeros(n, np.int64), len=np.zeros(n, np.int64), lin0=np.zeros(n, np.int32),
+                   shape=np.zeros(n, np.int32), first=np.zeros(nwg + 1 if nwg else 0, np.int32),
+                   wstart=np.zeros(nwg + 1 if nwg else 0, np.int64), dimrec=np.zeros((nrec, 25), np.int32))
+        _check(lib.tk_plan_worklist(self.h, int(kind), cnt.ctypes.data_as(_I64P),
+                                    out["vstart"].ctypes.data_as(_I64P), out["len"].ctypes.data_as(_I64P),
+                                    out["lin0"].ctypes.data_as(_I32P), out["shape"].ctypes.data_as(_I32P),
+                                    out["first"].ctypes.data_as(_I32P), out["wstart"].ctypes.data_as(_I64P),
+                                    out["dimrec"].ctypes.data_as(_I32P)))
+        return out
 
     def gemms(self):
         n = self.info()["ngemm"]

@@ -6,6 +6,7 @@ import itertools
 import numpy as np
 
 from oracle.graded import Space, Structure
+from paper_2508_10076_amd import synth
 
 
 def ospace(spec) -> Space:
@@ -105,3 +106,19 @@ def trace_case(rng, sym: str, npairs: int = 1, max_free: int = 3):
         if ostruct(t).size == 0:
             continue
         return t, tuple(free[:n1]), tuple(free[n1:]), tuple(t1), tuple(t2)
+
+
+def wide_n_case(rng, sym):
+    """Small K (<= 8 per sector) against free legs of B wide enough that the
+    sectors have well over 64 columns (output-stationary small-K path)."""
+    while True:
+        kl = synth.random_space(rng, sym, max_deg=2)
+        tA = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=3) for _ in range(2)], dom=[kl])
+        wide = [synth.random_space(rng, sym, max_sect=3, max_deg=4) for _ in range(2)]
+        wide = [synth.space(w.sectors, [d + 8 for d in w.degs], w.dual) for w in wide]
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(kl.sectors, kl.degs, kl.dual)], dom=wide)
+        if not (ostruct(tA).size and ostruct(tB).size):
+            continue
+        oc = [int(x) for x in rng.permutation(4)]
+        n1 = int(rng.integers(0, 5))
+        return tA, (0, 1), (2,), tB, (0,), (1, 2), oc[:n1], oc[n1:]

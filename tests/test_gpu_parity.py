@@ -12,7 +12,7 @@ import pytest
 from oracle import blockwise, dense
 from oracle.graded import Structure, permute_spaces
 from paper_2508_10076_amd import synth
-from tests.helpers import ospace, ostruct
+from tests.helpers import ospace, ostruct, wide_n_case as _wide_n_case
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -164,22 +164,6 @@ def test_contract_wide_output_permuted_after(ctx, sym, kdeg):
         tk.tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
         _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
         assert np.array_equal(download(Cg), ref), (sym, kdeg, trial)
-
-
-def _wide_n_case(rng, sym):
-    """Small K (<= 8 per sector) against free legs of B wide enough that the
-    sectors have well over 64 columns (output-stationary small-K path)."""
-    while True:
-        kl = synth.random_space(rng, sym, max_deg=2)
-        tA = dict(sym=sym, cod=[synth.random_space(rng, sym, max_deg=3) for _ in range(2)], dom=[kl])
-        wide = [synth.random_space(rng, sym, max_sect=3, max_deg=4) for _ in range(2)]
-        wide = [synth.space(w.sectors, [d + 8 for d in w.degs], w.dual) for w in wide]
-        tB = dict(sym=sym, cod=[synth.SpaceSpec(kl.sectors, kl.degs, kl.dual)], dom=wide)
-        if not (ostruct(tA).size and ostruct(tB).size):
-            continue
-        oc = [int(x) for x in rng.permutation(4)]
-        n1 = int(rng.integers(0, 5))
-        return tA, (0, 1), (2,), tB, (0,), (1, 2), oc[:n1], oc[n1:]
 
 
 @pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
