@@ -195,6 +195,12 @@ tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* de
  *     S (1) or Vh (2), on caller storage as tk_tensor_create;
  *   tk_svd_finish -- fills U, S and Vh (waits for the copies) and returns
  *     the truncation error (the norm of the discarded singular values).
+ * Sweeps stop when one rotates no pair (a pair counts as orthogonal when
+ * |w_p . w_q| <= 4 eps |w_p| |w_q|); a sector still rotating after 60
+ * sweeps fails tk_svd_create with TK_ERR_UNSUPPORTED (its values would not
+ * be converged).  tk_svd_info reports the number of decomposed sector
+ * matrices, of kept values, and the largest sweep count (any pointer may be
+ * NULL).
  * The handle owns device workspace until tk_svd_destroy; it allocates, so
  * it is not for graph capture. */
 tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, int32_t np,
@@ -204,6 +210,7 @@ tk_status tk_svd_create_factor(tk_context* ctx, const tk_svd* svd, int32_t which
                                uint64_t buf_bytes, tk_tensor** out);
 tk_status tk_svd_finish(tk_svd* svd, tk_tensor* U, tk_tensor* S, tk_tensor* Vh, double* trunc_err,
                         void* stream);
+tk_status tk_svd_info(const tk_svd* svd, int64_t* nsectors, int64_t* nkept, int32_t* max_sweeps);
 tk_status tk_svd_destroy(tk_svd* svd);
 
 /* A tensor shaped as the partial trace of A (see tk_tensor_trace). */
@@ -380,7 +387,10 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int
  * (TK_ERR_INVALID_ARG).
  *
  * tk_su2_plan_create: builds both structures and the coefficient table on
- *   the host (no GPU call); the caller owns *out (tk_su2_plan_destroy).
+ *   the host and copies the device tables to the current HIP device (the
+ *   plan is bound to it; with no device present the plan is host only:
+ *   its queries work, tk_su2_permute refuses it); the caller owns *out
+ *   (tk_su2_plan_destroy).
  *   Errors: TK_ERR_INVALID_ARG (null pointers, leg counts, bad p or q,
  *   degeneracies), TK_ERR_CHARGE (spins), TK_ERR_UNSUPPORTED (more than 8
  *   legs, a reduced array beyond 2^31 elements, strides beyond 32 bits).
@@ -392,10 +402,10 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int
  * tk_su2_permute: C = alpha * permute(A, (p, q)) + beta * C on `stream`;
  *   A and C are device arrays of dtype (TK_F64 or TK_F32) with the plan's
  *   input and output sizes, caller-owned, not aliased; beta == 0 never
- *   reads C.  The plan's tables go to the current device on the first call
- *   and the plan stays bound to that device; that first call must not
- *   overlap another call with the same plan from a second host thread.
- *   One launch; the plan must outlive the work enqueued with it. */
+ *   reads C.  The current device must be the plan's (TK_ERR_INVALID_ARG
+ *   otherwise).  One launch that allocates nothing, so it may be captured
+ *   in a HIP graph; calls with one plan may overlap (the plan is only
+ *   read).  The plan must outlive the work enqueued with it. */
 typedef struct tk_su2_plan tk_su2_plan;
 tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
                              const int32_t* p, const int32_t* q, tk_su2_plan** out);

@@ -60,6 +60,13 @@ def _time_ms(run, stream, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def lookup(mnk, tag=("f64", "native"), cache_path=DEFAULT_CACHE):
+    """The cached winner for this shape class, or None (never times, never
+    writes the cache)."""
+    ent = _load(cache_path).get(shape_class(mnk, *tag))
+    return tuple(ent["tile"]) if ent else None
+
+
 def tune(target, run, mnk, stream, cache_path=DEFAULT_CACHE, reps=5, force=False, tag=("f64", "native")):
     """target: a tk.Plan or tk.Batch; run(): enqueues its GEMM work on
     `stream`.  Returns (best_config, {config: ms})."""

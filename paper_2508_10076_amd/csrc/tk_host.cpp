@@ -2517,7 +2517,12 @@ struct tk_svd {
   std::vector<double> sigma;
   std::shared_ptr<Structure> U, S, V;
   double err = 0.0;
+  int max_sweeps = 0;  // largest sweep count over the sectors
 };
+
+namespace {
+constexpr int kSvdMaxSweeps = 60;
+}
 
 namespace {
 // The bond space of the factors: one sector per coupled charge with kept
@@ -2594,24 +2599,36 @@ tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, i
       sv->sec.push_back(r);
       sv->sec_sector.push_back(static_cast<int32_t>(k));
     }
-    for (auto& r : sv->sec) {  // singular values after every matrix
+    for (auto& r : sv->sec) {  // singular values (and the sweep count) after every matrix
       r.s = wsz;
-      wsz += r.n;
+      wsz += r.n + 1;
     }
     sv->ws.alloc(std::max<int64_t>(wsz, 1) * sizeof(double));
     sv->secs.upload(sv->sec);
     const double tol = std::numeric_limits<double>::epsilon() * 4.0;
     hip_check(tk::launch_jacobi_svd(static_cast<const tk::SvdSector*>(sv->secs.p), static_cast<int>(sv->sec.size()), X,
-                                    static_cast<double*>(sv->ws.p), 60, tol, st),
+                                    static_cast<double*>(sv->ws.p), kSvdMaxSweeps, tol, st),
               "Jacobi SVD launch");
     hip_check(hipStreamSynchronize(st), "stream synchronize");
     int64_t nsig = 0;
-    for (const auto& r : sv->sec) nsig += r.n;
-    sv->sigma.resize(nsig);
+    for (const auto& r : sv->sec) nsig += r.n + 1;
+    std::vector<double> sig(nsig);
     if (nsig)
-      hip_check(hipMemcpy(sv->sigma.data(), static_cast<double*>(sv->ws.p) + sv->sec.front().s,
-                          nsig * sizeof(double), hipMemcpyDeviceToHost),
+      hip_check(hipMemcpy(sig.data(), static_cast<double*>(sv->ws.p) + sv->sec.front().s, nsig * sizeof(double),
+                          hipMemcpyDeviceToHost),
                 "copy of the singular values");
+    // per sector: n singular values, then the sweep count (negative: the
+    // iteration reached the sweep limit while still rotating)
+    sv->sigma.clear();
+    for (size_t r = 0, o = 0; r < sv->sec.size(); o += sv->sec[r].n + 1, ++r) {
+      sv->sigma.insert(sv->sigma.end(), sig.begin() + o, sig.begin() + o + sv->sec[r].n);
+      const int sweeps = static_cast<int>(sig[o + sv->sec[r].n]);
+      sv->max_sweeps = std::max(sv->max_sweeps, std::abs(sweeps));
+      if (sweeps <= 0)
+        fail(TK_ERR_UNSUPPORTED, "the Jacobi iteration of a " + std::to_string(sv->sec[r].m) + " x " +
+                                     std::to_string(sv->sec[r].n) + " sector did not converge in " +
+                                     std::to_string(kSvdMaxSweeps) + " sweeps");
+    }
     // the largest values over all sectors (ties: sector order, then index)
     struct Val {
       double s;
@@ -2712,6 +2729,17 @@ tk_status tk_svd_finish(tk_svd* svd, tk_tensor* U, tk_tensor* S, tk_tensor* Vh, 
               "factor copy launch");
     hip_check(hipStreamSynchronize(st), "stream synchronize");  // tl is freed on return
     if (trunc_err) *trunc_err = svd->err;
+  });
+}
+
+tk_status tk_svd_info(const tk_svd* svd, int64_t* nsectors, int64_t* nkept, int32_t* max_sweeps) {
+  return guarded([&] {
+    if (!svd) fail(TK_ERR_INVALID_ARG, "null argument");
+    int64_t k = 0;
+    for (const auto& v : svd->keep) k += static_cast<int64_t>(v.size());
+    if (nsectors) *nsectors = static_cast<int64_t>(svd->sec.size());
+    if (nkept) *nkept = k;
+    if (max_sweeps) *max_sweeps = svd->max_sweeps;
   });
 }
 
@@ -3331,6 +3359,18 @@ tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const 
     plan->P.A.build();
     plan->P.C.build();
     su2::plan_permute(plan->P, pv, qv);
+    // device tables go to the current device now, so launches allocate
+    // nothing (and may be captured); without a device the plan is host only
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+      int dev = 0;
+      hip_check(hipGetDevice(&dev), "hipGetDevice");
+      plan->P.tl.upload();
+      plan->P.d_contribs.upload(plan->P.contribs);
+      plan->P.device = dev;
+    } else {
+      (void)hipGetLastError();
+    }
     *out = plan.release();
   });
 }
@@ -3366,15 +3406,10 @@ tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* 
     if (!A && P.A.size) fail(TK_ERR_INVALID_ARG, "A is null");
     if (!C && P.C.size) fail(TK_ERR_INVALID_ARG, "C is null");
     if (A && A == C) fail(TK_ERR_INVALID_ARG, "C aliases A");
+    if (P.device < 0) fail(TK_ERR_INVALID_ARG, "the plan was created without a HIP device (host only)");
     int dev = 0;
     hip_check(hipGetDevice(&dev), "hipGetDevice");
-    if (P.device < 0) {
-      P.tl.upload();
-      P.d_contribs.upload(P.contribs);
-      P.device = dev;
-    } else if (P.device != dev) {
-      fail(TK_ERR_INVALID_ARG, "the plan was first launched on another device");
-    }
+    if (P.device != dev) fail(TK_ERR_INVALID_ARG, "the plan's tables live on another device");
     tk::Ptrs ptrs{};
     ptrs.p[tk::kBufA] = const_cast<void*>(A);
     ptrs.p[tk::kBufC] = C;

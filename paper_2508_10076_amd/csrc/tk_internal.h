@@ -274,7 +274,9 @@ hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_fir
 // column-major) by one-sided Jacobi rotations on its m x n working copy W
 // (the matrix, or its transpose when R < C, so that m >= n), with the
 // rotations accumulated in V (n x n).  On exit sigma[j] = |W_j| and W_j is
-// normalised (the left singular vectors of the working matrix).
+// normalised (the left singular vectors of the working matrix), and
+// sigma[n] holds the number of sweeps used, negated when the last sweep still
+// rotated a pair (the iteration stopped at max_sweeps without converging).
 struct SvdSector {
   int64_t x;         // the matrix in its buffer
   int64_t w, v, s;   // W, V and sigma in the workspace (elements)

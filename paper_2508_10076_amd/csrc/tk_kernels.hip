@@ -316,6 +316,8 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
   const bool cached = m <= kSvdCache * 64;
   __syncthreads();
   const int nn = n + (n & 1), wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kSvdThreads / 64;
+  int done = 0;
+  bool converged = false;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) s_rot = 0;
     if (cached) {
@@ -407,8 +409,14 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
     }
     const int rotated = s_rot;
     __syncthreads();
-    if (!rotated) break;
+    done = sweep + 1;
+    if (!rotated) {
+      converged = true;
+      break;
+    }
   }
+  // sweeps used, negative when the last one still rotated (not converged)
+  if (threadIdx.x == 0) ws[sc.s + n] = converged ? done : -done;
   double* S = ws + sc.s;
   for (int j = wave; j < n; j += nw) {
     double* Wj = W + static_cast<int64_t>(m) * j;

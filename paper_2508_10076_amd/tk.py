@@ -66,6 +66,7 @@ _SIGS = {
     "tk_svd_create": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, C.c_int64, C.c_double, _P, C.POINTER(_P)],
     "tk_svd_create_factor": [_P, _P, C.c_int32, _P, C.c_uint64, C.POINTER(_P)],
     "tk_svd_finish": [_P, _P, _P, _P, C.POINTER(C.c_double), _P],
+    "tk_svd_info": [_P, _I64P, _I64P, _I32P],
     "tk_svd_destroy": [_P],
     "tk_tensor_create_traced": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _I32P, _I32P, C.c_int32, _P,
                                 C.c_uint64, C.POINTER(_P)],
@@ -345,19 +346,24 @@ def tensor_trace(ctx, A, p, q, t1, t2, alpha=1.0, beta=0.0, C_=None, stream=None
     return C_
 
 
-def tensor_svd(ctx, A, p, q, max_dim=-1, cutoff=0.0, stream=None):
+def tensor_svd(ctx, A, p, q, max_dim=-1, cutoff=0.0, stream=None, info=False):
     """Truncated SVD A~ = U o S o Vh of A~ = permute(A, (p, q)); returns
-    (U, S, Vh, truncation error)."""
+    (U, S, Vh, truncation error), and with info=True also a dict with the
+    number of sector matrices, of kept values and the largest sweep count."""
     (pa, npa), (qa, nqa) = _ilist(p), _ilist(q)
     h = C.c_void_p()
     _check(lib.tk_svd_create(ctx.h, A.h, pa, npa, qa, nqa, int(max_dim), float(cutoff), _stream(stream),
                              C.byref(h)))
     try:
+        ns, nk, sw = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(lib.tk_svd_info(h, C.byref(ns), C.byref(nk), C.byref(sw)))
         U, S, Vh = (Tensor._derived(ctx, lambda c, *r, w=w: lib.tk_svd_create_factor(c, h, w, *r)) for w in range(3))
         err = C.c_double()
         _check(lib.tk_svd_finish(h, U.h, S.h, Vh.h, C.byref(err), _stream(stream)))
     finally:
         lib.tk_svd_destroy(h)
+    if info:
+        return U, S, Vh, err.value, dict(nsectors=ns.value, nkept=nk.value, max_sweeps=sw.value)
     return U, S, Vh, err.value
 
 
