@@ -260,6 +260,34 @@ tk_status tk_tensor_contract(tk_context* ctx, const tk_tensor* A, const int32_t*
                              double alpha, double beta, int32_t precision, tk_tensor* C,
                              void* stream);
 
+/* The same contraction as tk_tensor_contract, for callers that cannot
+ * allocate device memory (code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It calls no hipMalloc or hipFree and no
+ * allocating library routine: the plan is rebuilt on the host each call and
+ * its device tables and workspaces (the permuted operands A~ and B~, C~ when
+ * the output permute runs after the GEMM, split-K partial tiles) are laid
+ * into one per-device scratch array of TK_SCRATCH_BYTES, which the library's
+ * code object holds on every device it runs on until the process ends (its
+ * address is looked up once per device, when the first context on that
+ * device is created).  The tables reach the array by one asynchronous copy
+ * on `stream`, then the kernels of tk_tensor_contract run on `stream` with
+ * the same schedule, so the result is bitwise the same.  Contractions whose
+ * tables and workspaces exceed TK_SCRATCH_BYTES fail with
+ * TK_ERR_UNSUPPORTED (nothing is enqueued).  Every call on one device uses
+ * the same array and leaves its contents behind: calls on one stream are
+ * ordered, but calls that overlap on one device (two streams, or two host
+ * threads with different streams) race on the array and give wrong results.
+ * The host side of calls on one device is serialised internally. */
+#define TK_SCRATCH_BYTES (64ull << 20)
+tk_status tk_tensor_contract_noalloc(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
+                                     const int32_t* qA, int32_t nqA, const tk_tensor* B, const int32_t* pB,
+                                     int32_t npB, const int32_t* qB, int32_t nqB, const int32_t* pAB, int32_t npAB,
+                                     const int32_t* qAB, int32_t nqAB, double alpha, double beta, int32_t precision,
+                                     tk_tensor* C, void* stream);
+/* Number of device allocations the library has made in this process
+ * (tensors created without a buffer, plan and batch tables, workspaces). */
+uint64_t tk_device_alloc_count(void);
+
 /* C = A^dagger: codomain and domain exchange, every coupled-charge matrix is
  * transposed (conjugation is the identity on real data). */
 tk_status tk_tensor_adjoint(tk_context* ctx, const tk_tensor* A, tk_tensor* C, void* stream);

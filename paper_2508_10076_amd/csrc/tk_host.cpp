@@ -5,6 +5,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <functional>
 #include <cmath>
@@ -397,34 +398,99 @@ std::vector<std::pair<int, int>> exchanged_pairs(int N1, int N2, const std::vect
 // ---------------------------------------------------------------------------
 // device memory
 // ---------------------------------------------------------------------------
+static_assert(TK_SCRATCH_BYTES == tk::kScratchBytes, "scratch size of tk.h and the kernels differ");
+
+struct DevBuf;
+
+// Device allocations the library has made (tk_device_alloc_count).
+std::atomic<uint64_t> g_device_allocs{0};
+
+// Placement of one allocation-free call's device memory.  While an arena is
+// active on the calling thread, DevBuf::alloc and DevBuf::upload record
+// requests instead of allocating: uploaded tables are staged back to back
+// (256-byte aligned) in host memory, workspaces only reserve their size.
+// place() then gives every request an address inside the caller's region
+// (tables first, then workspaces) and copies the staged tables in with one
+// asynchronous host-to-device copy.
+struct Arena {
+  struct Req {
+    DevBuf* buf;
+    size_t off, bytes;
+    bool table;
+  };
+  std::vector<Req> reqs;
+  std::vector<char>* staging = nullptr;  // table bytes (owned by the caller)
+  size_t work = 0;                       // workspace bytes reserved so far
+  static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
+  void reserve(DevBuf* b, size_t n) {
+    reqs.push_back({b, work, n, false});
+    work += align(n);
+  }
+  void stage(DevBuf* b, const void* src, size_t n) {
+    const size_t off = staging->size();
+    staging->resize(align(off + n));
+    std::memcpy(staging->data() + off, src, n);
+    reqs.push_back({b, off, n, true});
+  }
+  size_t total() const { return staging->size() + work; }
+  void place(char* base, size_t cap, hipStream_t stream);
+};
+thread_local Arena* t_arena = nullptr;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool borrowed = false;  // p lies in an arena's region (never freed here)
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    borrowed = false;
   }
   void alloc(size_t n) {
     release();
     if (n == 0) return;
+    if (t_arena) {
+      t_arena->reserve(this, n);
+      return;
+    }
     if (hipMalloc(&p, n) != hipSuccess) {
       (void)hipGetLastError();
       p = nullptr;
       fail(TK_ERR_OOM, "device allocation of " + std::to_string(n) + " bytes failed");
     }
+    g_device_allocs.fetch_add(1, std::memory_order_relaxed);
     bytes = n;
   }
   template <typename T>
   void upload(const std::vector<T>& v) {
+    if (t_arena) {
+      release();
+      if (!v.empty()) t_arena->stage(this, v.data(), v.size() * sizeof(T));
+      return;
+    }
     alloc(v.size() * sizeof(T));
     if (!v.empty()) hip_check(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
   }
 };
+
+void Arena::place(char* base, size_t cap, hipStream_t stream) {
+  const size_t tab = staging->size();
+  if (total() > cap)
+    fail(TK_ERR_UNSUPPORTED, "the contraction needs " + std::to_string(total()) +
+                                 " bytes of scratch (tables and workspaces); the allocation-free entry point has " +
+                                 std::to_string(cap));
+  for (const Req& r : reqs) {
+    r.buf->p = base + (r.table ? r.off : tab + r.off);
+    r.buf->bytes = r.bytes;
+    r.buf->borrowed = true;
+  }
+  if (tab) hip_check(hipMemcpyAsync(base, staging->data(), tab, hipMemcpyHostToDevice, stream), "scratch table copy");
+}
 
 // ---------------------------------------------------------------------------
 // permute task lists
@@ -2237,6 +2303,7 @@ tk_tensor* new_tensor(tk_context* ctx, std::shared_ptr<Structure> st, int dtype,
       t->data = nullptr;
       fail(TK_ERR_OOM, "device allocation failed");
     }
+    g_device_allocs.fetch_add(1, std::memory_order_relaxed);
     t->bytes = need;
     t->owns = true;
   }
@@ -2260,6 +2327,40 @@ tk_status guarded(F&& f) {
   }
 }
 
+// Per-device state of the allocation-free entry point: the address of the
+// device's scratch array (looked up once, when the first context on that
+// device is created, with the device current), the host staging of the
+// tables of the last call, and an event marking that their copy has left
+// host memory.  Calls on one device serialise their host side on `mu`; their
+// device work shares the one scratch array (see tk.h).
+struct Scratch {
+  std::mutex mu;
+  void* base = nullptr;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+  std::vector<char> staging;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+std::array<std::unique_ptr<Scratch>, kMaxDevices> g_scratch;
+
+void scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(TK_ERR_UNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[device]) return;
+  auto S = std::make_unique<Scratch>();
+  hip_check(tk::scratch_address(&S->base), "hipGetSymbolAddress of the scratch array");
+  hip_check(hipEventCreateWithFlags(&S->copied, hipEventDisableTiming), "hipEventCreate");
+  g_scratch[device] = std::move(S);
+}
+
+Scratch& scratch_of(int device) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices || !g_scratch[device])
+    fail(TK_ERR_INVALID_ARG, "no scratch for this device (create a context first)");
+  return *g_scratch[device];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -2277,6 +2378,7 @@ tk_status tk_context_create(int32_t device, tk_context** out) {
     hip_check(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n) fail(TK_ERR_INVALID_ARG, "no such device");
     hip_check(hipSetDevice(device), "hipSetDevice");
+    scratch_setup(device);
     hipDeviceProp_t prop;
     hip_check(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     auto c = std::make_unique<tk_context>();
@@ -2991,6 +3093,42 @@ tk_status tk_permute_map(const tk_tensor* A, const int32_t* p, int32_t np, const
     std::copy(sg.begin(), sg.end(), sign);
   });
 }
+
+tk_status tk_tensor_contract_noalloc(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA,
+                                     const int32_t* qA, int32_t nqA, const tk_tensor* B, const int32_t* pB,
+                                     int32_t npB, const int32_t* qB, int32_t nqB, const int32_t* pAB, int32_t npAB,
+                                     const int32_t* qAB, int32_t nqAB, double alpha, double beta, int32_t precision,
+                                     tk_tensor* C, void* stream) {
+  return guarded([&] {
+    if (!ctx || !A || !B || !C) fail(TK_ERR_INVALID_ARG, "null argument");
+    auto pa = to_vec(pA, npA, "pA"), qa = to_vec(qA, nqA, "qA"), pb = to_vec(pB, npB, "pB"), qb = to_vec(qB, nqB, "qB");
+    auto pab = to_vec(pAB, npAB, "pAB"), qab = to_vec(qAB, nqAB, "qAB");
+    Scratch& S = scratch_of(ctx->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> g(S.mu);
+    // the staging copy of the previous call must have left host memory
+    // before the staging buffer is refilled
+    if (S.pending) hip_check(hipEventSynchronize(S.copied), "hipEventSynchronize");
+    S.pending = false;
+    S.staging.clear();
+    Arena arena;
+    arena.staging = &S.staging;
+    std::unique_ptr<tk_plan> P;
+    {
+      struct Active {
+        explicit Active(Arena* a) { t_arena = a; }
+        ~Active() { t_arena = nullptr; }
+      } active(&arena);
+      P = build_contract_plan(ctx, A, pa, qa, B, pb, qb, pab, qab, precision, C);
+    }
+    arena.place(static_cast<char*>(S.base), tk::kScratchBytes, st);
+    hip_check(hipEventRecord(S.copied, st), "hipEventRecord");
+    S.pending = true;
+    execute_plan(*P, A, B, C, alpha, beta, st);
+  });
+}
+
+uint64_t tk_device_alloc_count(void) { return g_device_allocs.load(std::memory_order_relaxed); }
 
 tk_status tk_tensor_contract(tk_context* ctx, const tk_tensor* A, const int32_t* pA, int32_t npA, const int32_t* qA,
                              int32_t nqA, const tk_tensor* B, const int32_t* pB, int32_t npB, const int32_t* qB,

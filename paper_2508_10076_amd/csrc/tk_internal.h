@@ -286,6 +286,13 @@ constexpr int kSvdThreads = 1024;
 hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, double* ws, int max_sweeps,
                              double tol, hipStream_t stream);
 
+// Bytes of the per-device scratch array that the allocation-free
+// contraction lays its tables and workspaces into (TK_SCRATCH_BYTES).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+// Device address of that array on the current device (hipGetSymbolAddress;
+// call once per device, with the device current).
+hipError_t scratch_address(void** out);
+
 // Small-K sector GEMM tasks that all share the same K (1..8): one
 // workgroup per task.
 hipError_t launch_smallk(int dtype, int precision, int K, const SmallKTask* tasks, int ntasks, const SkChan* chans,

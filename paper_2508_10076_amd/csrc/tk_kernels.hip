@@ -1520,6 +1520,16 @@ __global__ __launch_bounds__(kThreads) void smallk_runs_kernel(const SkRun* __re
 }
 
 // ---------------------------------------------------------------------------
+// scratch memory of the allocation-free contraction entry point: one array
+// per device, held from the code object's load until the process ends.  In
+// host code its name stands for a host-side shadow, never a device address:
+// host code uses only the address scratch_address returns.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** out) { return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)); }
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_zero_ranges(int dtype, const ZeroRange* ranges, int nranges, const int32_t* first,

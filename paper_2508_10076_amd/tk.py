@@ -74,6 +74,9 @@ _SIGS = {
                         C.c_double, _P, _P],
     "tk_tensor_contract": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I32P, C.c_int32, _I32P, C.c_int32,
                            _I32P, C.c_int32, _I32P, C.c_int32, C.c_double, C.c_double, C.c_int32, _P, _P],
+    "tk_tensor_contract_noalloc": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I32P, C.c_int32, _I32P,
+                                   C.c_int32, _I32P, C.c_int32, _I32P, C.c_int32, C.c_double, C.c_double, C.c_int32,
+                                   _P, _P],
     "tk_tensor_adjoint": [_P, _P, _P, _P],
     "tk_plan_contract": [_P, _P, _I32P, C.c_int32, _I32P, C.c_int32, _P, _I32P, C.c_int32, _I32P, C.c_int32,
                          _I32P, C.c_int32, _I32P, C.c_int32, C.c_int32, _P, C.POINTER(_P)],
@@ -109,6 +112,9 @@ lib.tk_last_error.restype = C.c_char_p
 lib.tk_last_error.argtypes = []
 lib.tk_version.restype = C.c_char_p
 lib.tk_version.argtypes = []
+lib.tk_device_alloc_count.restype = C.c_uint64
+lib.tk_device_alloc_count.argtypes = []
+SCRATCH_BYTES = 64 << 20   # TK_SCRATCH_BYTES
 
 
 def _check(st):
@@ -432,6 +438,22 @@ def tensor_contract(ctx, A, pA, qA, B, pB, qB, pAB, qAB, alpha=1.0, beta=0.0, pr
     _check(lib.tk_tensor_contract(ctx.h, A.h, a1, n1, a2, n2, B.h, b1, m1, b2, m2, c1, k1, c2, k2, float(alpha),
                                   float(beta), prec, C_.h, _stream(stream)))
     return C_
+
+
+def tensor_contract_noalloc(ctx, A, pA, qA, B, pB, qB, pAB, qAB, C_, alpha=1.0, beta=0.0, precision="native",
+                            stream=None):
+    """tk_tensor_contract_noalloc: the contraction into the existing tensor
+    C_, with the library's tables and workspaces in its per-device scratch
+    array (no device allocation)."""
+    (a1, n1), (a2, n2), (b1, m1), (b2, m2), (c1, k1), (c2, k2) = [_ilist(v) for v in (pA, qA, pB, qB, pAB, qAB)]
+    prec = PREC[precision] if isinstance(precision, str) else int(precision)
+    _check(lib.tk_tensor_contract_noalloc(ctx.h, A.h, a1, n1, a2, n2, B.h, b1, m1, b2, m2, c1, k1, c2, k2,
+                                          float(alpha), float(beta), prec, C_.h, _stream(stream)))
+    return C_
+
+
+def device_alloc_count():
+    return int(lib.tk_device_alloc_count())
 
 
 def tensor_adjoint(ctx, A, C_=None, stream=None):
