@@ -102,6 +102,39 @@ def blas_threads():
         return os.cpu_count()
 
 
+def np_abs(v):
+    import numpy as np
+    return np.abs(v)
+
+
+def errors(np, got, ref, scale=None):
+    """normwise |C - C*| / |C*|; entrywise max |C - C*|_ij / scale_ij (scale:
+    the same computation on absolute values, |A||B|) and max |C - C*| / max |C*|."""
+    d = np.abs(got - ref)
+    out = {"normwise_rel_err": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+           "max_entry_err_rel_to_max": float(d.max() / np.abs(ref).max())}
+    if scale is not None:
+        nz = scale > 0
+        out["max_rel_err"] = float(np.max(d[nz] / scale[nz])) if nz.any() else 0.0
+    return out
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def one_thread():
+    """Context limiting the BLAS pool to one thread (the paper's setting)."""
+    from threadpoolctl import threadpool_limits
+    return threadpool_limits(limits=1, user_api="blas")
+
+
 def ostruct(t):
     from oracle.graded import Space, Structure
     osp = lambda s: Space(s.sectors, s.degs, s.dual)
@@ -211,12 +244,15 @@ class Heff:
         return y.storage[: y.nelem].double().cpu().numpy()
 
 
-def oracle_heff(cfg, cid, seconds):
-    """The CPU oracle on the same inputs: (y, reps, seconds spent)."""
+def oracle_heff(cfg, cid, seconds, absolute=False):
+    """The CPU oracle on the same inputs: (y, reps, seconds spent); with
+    absolute=True on |inputs| (the entrywise error scale |L||W||x||R|)."""
     from oracle import blockwise
     from paper_2508_10076_amd import synth
     st = {k: ostruct(cfg["tensors"][k]) for k in cfg["inputs"]}
     v0 = {k: synth.normal(st[k].size, cid, i) for i, k in enumerate(cfg["inputs"])}
+    if absolute:
+        v0 = {k: np_abs(v) for k, v in v0.items()}
     reps, spent, y = 0, 0.0, None
     while (spent < seconds or reps == 0) and reps < 50:
         s2, v = dict(st), dict(v0)
@@ -288,15 +324,19 @@ def bench_heff(args, tk, torch, np):
             del Hv
     if not args.no_cpu_baseline:
         y_ref, reps, spent = oracle_heff(cfg, cid, args.cpu_seconds)
-        nrm = np.linalg.norm(y_ref)
+        with one_thread():
+            _, reps1, spent1 = oracle_heff(cfg, cid, args.cpu_seconds / 2)
+        y_abs, _, _ = oracle_heff(cfg, cid, 0.0, absolute=True)
         out["cpu_baseline"] = {"value": round(H.flops * reps / spent / 1e12, 6), "unit": "TFLOP/s",
                                "cores": blas_threads(), "kind": "oracle",
                                "sample": f"{reps} full H_eff applications of the same workload (numpy blockwise "
-                                         f"fp64, OpenBLAS), {spent:.1f} s"}
-        out["max_rel_err"] = float(np.linalg.norm(y_gpu - y_ref) / nrm)
-        out["max_entry_err_rel_to_max"] = float(np.max(np.abs(y_gpu - y_ref)) / np.max(np.abs(y_ref)))
+                                         f"fp64, OpenBLAS), {spent:.1f} s",
+                               "single_thread": {"value": round(H.flops * reps1 / spent1 / 1e12, 6),
+                                                 "cores": 1, "sample": f"{reps1} applications, {spent1:.1f} s"},
+                               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        out.update(errors(np, y_gpu, y_ref, y_abs))
         for prec, v in variants.items():
-            v["max_rel_err"] = float(np.linalg.norm(v.pop("y") - y_ref) / nrm)
+            v.update(errors(np, v.pop("y"), y_ref, y_abs))
     for v in variants.values():
         v.pop("y", None)
     if variants:
@@ -313,14 +353,14 @@ def bench_batch(args, tk, torch, np):
     call = cfg["call"]
     ctx = tk.Context(0)
     stream = torch.cuda.Stream()
-    res = {}
+    res, outs = {}, {}
     for dtype in ("f64", "f32"):
         plans, As, Bs, Cs, flops = [], [], [], [], 0.0
         for i, it in enumerate(cfg["items"]):
             A = tk.tensor_create(ctx, "U1", it["A"]["cod"], it["A"]["dom"], dtype=dtype)
             B = tk.tensor_create(ctx, "U1", it["B"]["cod"], it["B"]["dom"], dtype=dtype)
-            A.storage.copy_(torch.from_numpy(synth.normal(A.storage.numel(), 4, 2 * i)))
-            B.storage.copy_(torch.from_numpy(synth.normal(B.storage.numel(), 4, 2 * i + 1)))
+            A.storage[: A.nelem].copy_(torch.from_numpy(synth.normal(A.nelem, 4, 2 * i)))
+            B.storage[: B.nelem].copy_(torch.from_numpy(synth.normal(B.nelem, 4, 2 * i + 1)))
             C = tk.tensor_create_contracted(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"],
                                             call["qAB"])
             P = tk.Plan(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"], call["qAB"], C)
@@ -358,8 +398,42 @@ def bench_batch(args, tk, torch, np):
                       "sequential_ms": round(ms_seq, 4), "speedup_vs_sequential": round(ms_seq / ms_graph, 3),
                       "ngemm": info["ngemm"], "ntiles": info["ntiles"], "tile": list(info["tile"]),
                       "block_flops": flops}
+        batch.replay(stream)
+        stream.synchronize()
+        outs[dtype] = np.concatenate([C.storage[: C.nelem].double().cpu().numpy() for C in Cs])
         del batch, plans
     f64 = res["f64"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import blockwise
+
+        def oracle_pass(absolute):
+            ys = []
+            for i, it in enumerate(cfg["items"]):
+                stA, stB = ostruct(it["A"]), ostruct(it["B"])
+                a, b = synth.normal(stA.size, 4, 2 * i), synth.normal(stB.size, 4, 2 * i + 1)
+                if absolute:
+                    a, b = np.abs(a), np.abs(b)
+                ys.append(blockwise.contract_storage(stA, a, call["pA"], call["qA"], stB, b, call["pB"], call["qB"],
+                                                     call["pAB"], call["qAB"])[1])
+            return np.concatenate(ys)
+        t0 = time.perf_counter()
+        y_ref = oracle_pass(False)
+        spent = time.perf_counter() - t0
+        y_abs = oracle_pass(True)
+        for dtype in res:
+            res[dtype].update(errors(np, outs[dtype], y_ref, y_abs))
+        cpu = {"value": round(f64["block_flops"] / spent / 1e12, 6), "unit": "TFLOP/s", "cores": blas_threads(),
+               "kind": "oracle", "sample": f"one pass over the 64 contractions (numpy blockwise fp64, OpenBLAS), "
+                                           f"{spent:.1f} s", "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    out = _batch_line(args, cfg, res, f64)
+    if cpu:
+        out["cpu_baseline"] = cpu
+        out.update({k: f64[k] for k in ("normwise_rel_err", "max_rel_err", "max_entry_err_rel_to_max")})
+    return out
+
+
+def _batch_line(args, cfg, res, f64):
     return {"metric": METRIC, "value": f64["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": f64["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -387,7 +461,9 @@ def bench_peps(args, tk, torch, np):
     Ad = tk.tensor_adjoint(ctx, A)
     E = tk.tensor_create_contracted(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"],
                                     call["qAB"])
-    res = {}
+    res, samples = {}, {}
+    pos = np.random.default_rng(51602).integers(0, E.nelem, size=200_000)
+    pos_dev = torch.from_numpy(pos).cuda()
     for prec in ("native", "bf16x3"):
         P = tk.Plan(ctx, Ad, call["pA"], call["qA"], A, call["pB"], call["qB"], call["pAB"], call["qAB"], E,
                     precision=prec)
@@ -409,7 +485,47 @@ def bench_peps(args, tk, torch, np):
         ms = e0.elapsed_time(e1) / args.steps
         res[prec] = {"ms_per_step": round(ms, 5), "value": round(flops / ms / 1e9, 5),
                      "gbps_output": round(8 * E.nelem / ms / 1e6, 1), "counts": P.counts()}
+        samples[prec] = E.storage[pos_dev].double().cpu().numpy()
     nat = res["native"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle: the graph value of the network evaluated at the sampled
+        # entries of E (pointwise definition, fp64), and the same sum of
+        # |terms| as the entrywise error scale
+        from oracle import blockwise, sampled
+        stA = ostruct(tA)
+        a = synth.normal(stA.size, 5, 0)
+        t0 = time.perf_counter()
+        sAd, bAd = blockwise.adjoint(stA, stA.to_blocks(a))
+        Adn, Ax = sAd.to_dense(sAd.from_blocks(bAd)), stA.to_dense(a)
+        free = [(0, i) for i in call["pA"]] + [(1, j) for j in call["qB"]]
+        out_cod = [free[i] for i in call["pAB"]]
+        pairs = [((0, x), (1, y)) for x, y in zip(call["qA"], call["pB"])]
+        ocod, _ = sampled.graph_output_spaces([(sAd.cod, sAd.dom), (stA.cod, stA.dom)], out_cod, [])
+        idx, size, off = sampled.codomain_channels("U1xFZ2", ocod)
+        di = sampled.positions_to_dense(ocod, idx, size, off, pos)
+        ref = sampled.graph_entries("U1xFZ2", [(Adn, sAd.cod, sAd.dom), (Ax, stA.cod, stA.dom)], pairs, out_cod,
+                                    [], di)
+        spent = time.perf_counter() - t0
+        scale = np.zeros(pos.shape[0])
+        for p in range(Ax.shape[0]):
+            scale += np.abs(Adn[di[:, 0], di[:, 2], di[:, 4], di[:, 6], p]) * np.abs(Ax[p, di[:, 1], di[:, 3],
+                                                                                      di[:, 5], di[:, 7]])
+        for prec in res:
+            res[prec].update(errors(np, samples[prec], ref, scale))
+        cpu = {"value": round(pos.shape[0] / spent / 1e6, 4), "unit": "M entries/s", "cores": 1,
+               "kind": "oracle", "sample": f"graph value of the double layer at {pos.shape[0]} uniformly drawn "
+                                           f"entries of E (pointwise definition, numpy fp64), {spent:.1f} s; "
+                                           f"errors are over the same entries",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    out = _peps_line(args, cfg, E, nat, res)
+    if cpu:
+        out["cpu_baseline"] = cpu
+        out.update({k: nat[k] for k in ("normwise_rel_err", "max_rel_err", "max_entry_err_rel_to_max")})
+    return out
+
+
+def _peps_line(args, cfg, E, nat, res):
     return {"metric": METRIC, "value": nat["value"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": nat["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
