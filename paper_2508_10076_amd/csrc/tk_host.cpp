@@ -499,15 +499,32 @@ template <typename TaskT>
 struct TaskListT {
   std::vector<TaskT> tasks;
   std::vector<int32_t> wg_first{0};
-  DevBuf d_tasks, d_wg;
+  std::vector<tk::TileTask> tiles;  // LDS-staged tiles (block permutes only)
+  DevBuf d_tasks, d_wg, d_tiles;
   int nwg() const { return static_cast<int>(wg_first.size()) - 1; }
+  int ntiles() const { return static_cast<int>(tiles.size()); }
   void upload() {
     d_tasks.upload(tasks);
     d_wg.upload(wg_first);
+    d_tiles.upload(tiles);
   }
 };
 
 using TaskList = TaskListT<PermTask>;
+
+// Enqueue a permute task list: the output-order walk over its tasks, then
+// its LDS-staged tiles.
+void launch_tasklist(int dtype, const TaskList& tl, const tk::Ptrs& ptrs, double alpha, double beta,
+                     hipStream_t stream, bool split, const char* what) {
+  if (tl.nwg() > 0)
+    hip_check(tk::launch_permute(dtype, static_cast<const PermTask*>(tl.d_tasks.p),
+                                 static_cast<const int32_t*>(tl.d_wg.p), tl.nwg(), ptrs, alpha, beta, stream, split),
+              what);
+  if (tl.ntiles() > 0)
+    hip_check(tk::launch_permute_tiles(dtype, static_cast<const tk::TileTask*>(tl.d_tiles.p), tl.ntiles(), ptrs,
+                                       alpha, beta, stream, split),
+              what);
+}
 using SkBlockList = TaskListT<tk::SkBlockTask>;
 
 // Limits of the workgroup tables of the zero-range and output-run kernels,
@@ -809,8 +826,12 @@ bool add_output_runs(RunSet& rs, const Structure& Ct, const Group& rg, const Gro
 }
 
 // Add one block (dims/strides in output order) as chunked tasks.
+// Blocks whose source and destination are contiguous along different
+// dimensions, both at least this long, are permuted through LDS tiles.
+constexpr int64_t kTileMinEdge = 16;
+
 void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int64_t dst, int n, const int64_t* dim,
-                     const int64_t* ss, const int64_t* ds, float sign) {
+                     const int64_t* ss, const int64_t* ds, float sign, int32_t lo = 0) {
   // drop unit dims, merge dims that are contiguous on both sides
   int64_t D[tk::kMaxDims], S[tk::kMaxDims], T[tk::kMaxDims];
   int m = 0;
@@ -834,7 +855,51 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
   int64_t total = 1;
   for (int i = 0; i < m; ++i) total *= D[i];
   if (total > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "block larger than 2^31 elements");
+  // source contiguous along dim a, destination along dim b != a: tiles of
+  // kTileEdge x kTileEdge through LDS at every index of the other dims
+  int a = -1, b = -1;
+  for (int i = 0; i < m; ++i) {
+    if (S[i] == 1 && a < 0) a = i;
+    if (T[i] == 1 && b < 0) b = i;
+  }
+  if (sbuf >= 0 && a >= 0 && b >= 0 && a != b && D[a] >= kTileMinEdge && D[b] >= kTileMinEdge) {
+    int64_t idx[tk::kMaxDims] = {0};
+    const int64_t E = tk::kTileEdge;
+    for (;;) {
+      int64_t so = src, dof = dst;
+      for (int i = 0; i < m; ++i)
+        if (i != a && i != b) {
+          so += idx[i] * S[i];
+          dof += idx[i] * T[i];
+        }
+      for (int64_t ia = 0; ia < D[a]; ia += E)
+        for (int64_t ib = 0; ib < D[b]; ib += E) {
+          tk::TileTask t{};
+          t.src = so + ia + ib * S[b];
+          t.dst = dof + ia * T[a] + ib;
+          t.ea = static_cast<int32_t>(std::min(E, D[a] - ia));
+          t.eb = static_cast<int32_t>(std::min(E, D[b] - ib));
+          t.sb = checked_i32(S[b], "stride");
+          t.ta = checked_i32(T[a], "stride");
+          t.src_buf = sbuf;
+          t.dst_buf = dbuf;
+          t.sign = sign;
+          t.lo = lo;
+          tl.tiles.push_back(t);
+        }
+      int i = 0;
+      for (; i < m; ++i) {
+        if (i == a || i == b) continue;
+        if (++idx[i] < D[i]) break;
+        idx[i] = 0;
+      }
+      if (i == m) break;
+    }
+    if (tl.tiles.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many permute tiles");
+    return;
+  }
   PermTask t{};
+  t.lo = lo;
   t.src = src;
   t.dst = dst;
   t.n = m;
@@ -951,9 +1016,22 @@ int channel_parity(const Structure& st, const uint8_t* tup, const std::vector<st
 
 // Permute plan A -> C (Alg. "Abelian Tensor Permutation"); twist additionally
 // multiplies by (-1)^{|x|} for every codomain leg of C on a dual space.
+// Split-BF16x3 operand planes of a permuted operand (the structure C of
+// plan_permute_tasks): per sector of C its first element in the planes (-1:
+// the sector is not split and keeps its place in the buffer dbuf, or is
+// skipped when dbuf < 0), the padded length ld of a row (rows: A~, element
+// (r, c) at off + r ld + c) or of a column (B~: off + r + c ld), the buffer of
+// the hi plane and the lo plane's distance from it.
+struct PlaneMap {
+  std::vector<int64_t> off, ld;
+  bool rows = false;
+  int16_t buf = 0;
+  int32_t lo = 0;
+};
+
 void plan_permute_tasks(const Structure& A, const std::vector<int>& p, const std::vector<int>& q, const Structure& C,
                         int16_t sbuf, int16_t dbuf, bool twist, TaskList& tl, std::vector<int64_t>* map_out = nullptr,
-                        std::vector<int32_t>* sign_out = nullptr) {
+                        std::vector<int32_t>* sign_out = nullptr, const PlaneMap* planes = nullptr) {
   const bool ferm = A.si.fermionic;
   const auto pairs = ferm ? exchanged_pairs(A.N1(), A.N2(), p, q) : std::vector<std::pair<int, int>>{};
   std::vector<int> src(p);
@@ -978,8 +1056,35 @@ void plan_permute_tasks(const Structure& A, const std::vector<int>& p, const std
       sign_out->push_back(par ? -1 : 1);
       return;
     }
+    if (planes && planes->off[b.sector] >= 0) {
+      // the block in the planes: rows of A~ or columns of B~ of length ld
+      const int64_t ld = planes->ld[b.sector];
+      const int64_t r0 = C.rg[b.sector]->off[b.row], c0 = C.cg[b.sector]->off[b.col];
+      int64_t pstr[TK_MAX_RANK];
+      for (int n = 0; n < N; ++n) {
+        const bool row_leg = n < C.N1();
+        const int64_t unit = row_leg ? ostr[n] : ostr[n] / b.R;  // stride in rows / in columns
+        pstr[n] = planes->rows ? (row_leg ? unit * ld : unit) : (row_leg ? unit : unit * ld);
+      }
+      const int64_t dst = planes->off[b.sector] + (planes->rows ? r0 * ld + c0 : r0 + c0 * ld);
+      add_block_tasks(tl, sbuf, off, planes->buf, dst, N, odim, oss, pstr, sign, planes->lo);
+      return;
+    }
+    if (dbuf < 0) return;
     add_block_tasks(tl, sbuf, off, dbuf, b.offset, N, odim, oss, ostr, sign);
   });
+}
+
+// Zero padding of split planes: in every split sector the k range K .. ld-1
+// of each of its n rows (A~) or columns (B~).
+void plan_plane_padding(const Structure& C, const PlaneMap& pm, TaskList& tl) {
+  for (size_t s = 0; s < C.keys.size(); ++s) {
+    if (pm.off[s] < 0) continue;
+    const int64_t K = pm.rows ? C.C[s] : C.R[s], n = pm.rows ? C.R[s] : C.C[s], pad = pm.ld[s] - K;
+    if (pad <= 0) continue;
+    const int64_t dim[2] = {pad, n}, zs[2] = {0, 0}, ds[2] = {1, pm.ld[s]};
+    add_block_tasks(tl, -1, 0, pm.buf, pm.off[s] + K, 2, dim, zs, ds, 1.0f, pm.lo);
+  }
 }
 
 // Partial trace (Alg. "Abelian Tensor Trace"): legs t1[i] and t2[i] of A are
@@ -1536,6 +1641,9 @@ struct tk_plan {
   DevBuf d_skchans, d_skpairs;
   std::vector<int64_t> mnk;  // (M, N, K) of every sector GEMM with K > 0, MFMA or streamed
   DevBuf wsA, wsB, wsC;
+  bool needA = false, needB = false;  // the A~ / B~ workspaces are written (some sector uses them)
+  int64_t planeA = 0, planeB = 0;     // elements of one split-BF16x3 plane of A~ / B~
+  DevBuf wsAp, wsBp;                  // hi then lo plane of A~ / B~
   double flops = 0;
   int64_t nzero = 0;
 };
@@ -1823,8 +1931,56 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       if (s.dual && std::find(s.p.begin(), s.p.end(), 1) != s.p.end()) twist = true;
   P->permA = !is_identity(pA, qA, sA.N1());
   P->permB = !is_identity(pB, qB, sB.N1()) || twist;
-  if (P->permA) plan_permute_tasks(sA, pA, qA, At, tk::kBufA, tk::kBufAt, false, P->pre);
-  if (P->permB) plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, tk::kBufBt, twist, P->pre);
+  // split-BF16x3: the operands of the MFMA sector GEMMs (K > kSmallK) are
+  // written once, by the operand permute, as bf16 hi / lo planes with k
+  // contiguous (identity permutations included); small-K sectors keep the
+  // element type in the ordinary workspaces
+  const bool split = precision == TK_PREC_BF16X3;
+  PlaneMap pmA, pmB;
+  bool smallk_any = false;
+  if (split) {
+    pmA.rows = true;
+    pmA.buf = tk::kBufAp;
+    pmB.buf = tk::kBufBp;
+    pmA.off.assign(At.keys.size(), -1);
+    pmA.ld.assign(At.keys.size(), 0);
+    pmB.off.assign(Bt.keys.size(), -1);
+    pmB.ld.assign(Bt.keys.size(), 0);
+    for (size_t sa = 0; sa < At.keys.size(); ++sa) {
+      const int sb = Bt.sector_of_key(At.keys[sa]);
+      if (sb < 0) continue;
+      const int64_t K = At.C[sa];
+      if (K <= kSmallK) {
+        smallk_any = true;
+        continue;
+      }
+      const int64_t ld = (K + 7) / 8 * 8;
+      if (ld >= (int64_t(1) << 22))
+        fail(TK_ERR_UNSUPPORTED, "split-BF16x3: contracted dimension of one coupled sector above 2^22");
+      pmA.off[sa] = P->planeA;
+      pmA.ld[sa] = ld;
+      P->planeA += At.R[sa] * ld;
+      pmB.off[sb] = P->planeB;
+      pmB.ld[sb] = ld;
+      P->planeB += Bt.C[sb] * ld;
+    }
+    if (P->planeA > INT32_MAX || P->planeB > INT32_MAX) fail(TK_ERR_UNSUPPORTED, "split-BF16x3 planes above 2^31 elements");
+    pmA.lo = static_cast<int32_t>(P->planeA);
+    pmB.lo = static_cast<int32_t>(P->planeB);
+    P->needA = P->permA && smallk_any;
+    P->needB = P->permB && smallk_any;
+    plan_permute_tasks(sA, pA, qA, At, tk::kBufA, P->needA ? tk::kBufAt : int16_t(-1), false, P->pre, nullptr,
+                       nullptr, &pmA);
+    plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, P->needB ? tk::kBufBt : int16_t(-1), twist, P->pre, nullptr,
+                       nullptr, &pmB);
+    plan_plane_padding(At, pmA, P->pre);
+    plan_plane_padding(Bt, pmB, P->pre);
+  } else {
+    P->needA = P->permA;
+    P->needB = P->permB;
+    if (P->permA) plan_permute_tasks(sA, pA, qA, At, tk::kBufA, tk::kBufAt, false, P->pre);
+    if (P->permB) plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, tk::kBufBt, twist, P->pre);
+  }
   pack_workgroups(P->pre);
 
   const bool idC = is_identity(pAB, qAB, Ct.N1());
@@ -2031,6 +2187,16 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             }
         continue;
       }
+      if (split) {
+        d.a = pmA.off[sa];
+        d.lda = checked_i32(pmA.ld[sa], "lda");
+        d.a_buf = tk::kBufAp;
+        d.alo = P->planeA;
+        d.b = pmB.off[sb];
+        d.ldb = checked_i32(pmB.ld[sb], "ldb");
+        d.b_buf = tk::kBufBp;
+        d.blo = P->planeB;
+      }
       if (idC) {
         d.mode = 0;
         d.c = sC.soff[sC.sector_of_key(key)];
@@ -2141,9 +2307,11 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
 
   if (ctx) {
     const size_t es = A->esize();
-    if (P->permA) P->wsA.alloc(At.size * es);
-    if (P->permB) P->wsB.alloc(Bt.size * es);
+    if (P->needA) P->wsA.alloc(At.size * es);
+    if (P->needB) P->wsB.alloc(Bt.size * es);
     if (P->post) P->wsC.alloc(Ct.size * es);
+    if (P->planeA) P->wsAp.alloc(4 * P->planeA);  // two bf16 planes
+    if (P->planeB) P->wsBp.alloc(4 * P->planeB);
     P->pre.upload();
     P->zero.upload();
     P->zranges.upload();
@@ -2176,6 +2344,8 @@ tk::Ptrs plan_ptrs(const tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_
   p.p[tk::kBufAt] = P.wsA.p;
   p.p[tk::kBufBt] = P.wsB.p;
   p.p[tk::kBufCt] = P.wsC.p;
+  p.p[tk::kBufAp] = P.wsAp.p;
+  p.p[tk::kBufBp] = P.wsBp.p;
   p.table = nullptr;
   return p;
 }
@@ -2195,10 +2365,8 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
   check_exec_tensor(C, P.C, P.dtype, "C");
   if (C->data && (C->data == A->data || C->data == B->data)) fail(TK_ERR_INVALID_ARG, "C aliases an operand");
   tk::Ptrs ptrs = plan_ptrs(P, A, B, C);
-  if ((stages & TK_STAGE_PERMUTE) && P.pre.nwg() > 0)
-    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.pre.d_tasks.p),
-                                 static_cast<const int32_t*>(P.pre.d_wg.p), P.pre.nwg(), ptrs, 1.0, 0.0, stream),
-              "permute launch");
+  if (stages & TK_STAGE_PERMUTE)
+    launch_tasklist(P.dtype, P.pre, ptrs, 1.0, 0.0, stream, P.precision == TK_PREC_BF16X3, "permute launch");
   const double ga = alpha, gb = P.post ? 0.0 : beta;
   if ((stages & TK_STAGE_GEMM) && !P.descs.empty()) {
     tk::GemmArgs ga_{};
@@ -2253,15 +2421,10 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
                                      static_cast<const int32_t*>(P.zranges.d_first.p),
                                      static_cast<const int64_t*>(P.zranges.d_wstart.p), P.zranges.nwg(), ptrs, P.post ? 0.0 : beta, stream),
               "zero-range launch");
-  if ((stages & TK_STAGE_ZERO) && P.zero.nwg() > 0)
-    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.zero.d_tasks.p),
-                                 static_cast<const int32_t*>(P.zero.d_wg.p), P.zero.nwg(), ptrs, P.post ? 1.0 : alpha,
-                                 P.post ? 0.0 : beta, stream),
-              "zero launch");
-  if ((stages & TK_STAGE_ZERO) && P.post && P.postp.nwg() > 0)
-    hip_check(tk::launch_permute(P.dtype, static_cast<const PermTask*>(P.postp.d_tasks.p),
-                                 static_cast<const int32_t*>(P.postp.d_wg.p), P.postp.nwg(), ptrs, alpha, beta, stream),
-              "permute launch");
+  if (stages & TK_STAGE_ZERO)
+    launch_tasklist(P.dtype, P.zero, ptrs, P.post ? 1.0 : alpha, P.post ? 0.0 : beta, stream, false, "zero launch");
+  if ((stages & TK_STAGE_ZERO) && P.post)
+    launch_tasklist(P.dtype, P.postp, ptrs, alpha, beta, stream, false, "permute launch");
 }
 
 std::string plan_key(const tk_tensor* A, const std::vector<int>& pA, const std::vector<int>& qA, const tk_tensor* B,
@@ -2596,10 +2759,7 @@ tk_status tk_tensor_permute(tk_context* ctx, const tk_tensor* A, const int32_t* 
     tk::Ptrs ptrs{};
     ptrs.p[tk::kBufA] = A->data;
     ptrs.p[tk::kBufC] = C->data;
-    hip_check(tk::launch_permute(A->dtype, static_cast<const PermTask*>(pp->tl.d_tasks.p),
-                                 static_cast<const int32_t*>(pp->tl.d_wg.p), pp->tl.nwg(), ptrs, 1.0, 0.0,
-                                 static_cast<hipStream_t>(stream)),
-              "permute launch");
+    launch_tasklist(A->dtype, pp->tl, ptrs, 1.0, 0.0, static_cast<hipStream_t>(stream), false, "permute launch");
   });
 }
 
@@ -2676,9 +2836,7 @@ tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, i
       tk::Ptrs ptrs{};
       ptrs.p[tk::kBufA] = A->data;
       ptrs.p[tk::kBufC] = sv->at.p;
-      hip_check(tk::launch_permute(TK_F64, static_cast<const PermTask*>(tl.d_tasks.p),
-                                   static_cast<const int32_t*>(tl.d_wg.p), tl.nwg(), ptrs, 1.0, 0.0, st),
-                "permute launch");
+      launch_tasklist(TK_F64, tl, ptrs, 1.0, 0.0, st, false, "permute launch");
       hip_check(hipStreamSynchronize(st), "stream synchronize");  // tl is freed on return
       X = static_cast<const double*>(sv->at.p);
     }
@@ -2826,9 +2984,7 @@ tk_status tk_svd_finish(tk_svd* svd, tk_tensor* U, tk_tensor* S, tk_tensor* Vh, 
     ptrs.p[1] = U->data;
     ptrs.p[2] = S->data;
     ptrs.p[3] = Vh->data;
-    hip_check(tk::launch_permute(TK_F64, static_cast<const PermTask*>(tl.d_tasks.p),
-                                 static_cast<const int32_t*>(tl.d_wg.p), tl.nwg(), ptrs, 1.0, 0.0, st),
-              "factor copy launch");
+    launch_tasklist(TK_F64, tl, ptrs, 1.0, 0.0, st, false, "factor copy launch");
     hip_check(hipStreamSynchronize(st), "stream synchronize");  // tl is freed on return
     if (trunc_err) *trunc_err = svd->err;
   });
@@ -2927,10 +3083,7 @@ tk_status tk_tensor_adjoint(tk_context* ctx, const tk_tensor* A, tk_tensor* C, v
     tk::Ptrs ptrs{};
     ptrs.p[tk::kBufA] = A->data;
     ptrs.p[tk::kBufC] = C->data;
-    hip_check(tk::launch_permute(A->dtype, static_cast<const PermTask*>(pp->tl.d_tasks.p),
-                                 static_cast<const int32_t*>(pp->tl.d_wg.p), pp->tl.nwg(), ptrs, 1.0, 0.0,
-                                 static_cast<hipStream_t>(stream)),
-              "adjoint launch");
+    launch_tasklist(A->dtype, pp->tl, ptrs, 1.0, 0.0, static_cast<hipStream_t>(stream), false, "adjoint launch");
   });
 }
 
@@ -2976,8 +3129,8 @@ tk_status tk_plan_info(const tk_plan* plan, int64_t* ngemm, double* flops, int64
     if (nzero) *nzero = plan->nzero;
     if (workspace_bytes) {
       const int64_t es = plan->dtype == TK_F64 ? 8 : 4;
-      *workspace_bytes = (plan->permA ? plan->At->size * es : 0) + (plan->permB ? plan->Bt->size * es : 0) +
-                         (plan->post ? plan->Ct->size * es : 0);
+      *workspace_bytes = (plan->needA ? plan->At->size * es : 0) + (plan->needB ? plan->Bt->size * es : 0) +
+                         (plan->post ? plan->Ct->size * es : 0) + 4 * (plan->planeA + plan->planeB);
     }
     if (tile_m) *tile_m = plan->tile_m;
     if (tile_n) *tile_n = plan->tile_n;
@@ -3003,7 +3156,8 @@ tk_status tk_plan_counts(const tk_plan* plan, int64_t* c) {
       nrun += static_cast<int64_t>(r.runs.size());
       nrw += r.nwg();
     }
-    const int64_t v[14] = {static_cast<int64_t>(P.pre.tasks.size()), P.pre.nwg(),
+    const int64_t v[14] = {static_cast<int64_t>(P.pre.tasks.size() + P.pre.tiles.size()),
+                           P.pre.nwg() + P.pre.ntiles(),
                            static_cast<int64_t>(P.zero.tasks.size() + P.zranges.ranges.size()),
                            P.zero.nwg() + P.zranges.nwg(), skt, skw,
                            static_cast<int64_t>(P.descs.size()), static_cast<int64_t>(P.tiles.size()),
@@ -3185,6 +3339,11 @@ void merge_tasks(TaskList& dst, const TaskList& src, int member) {
     dst.tasks.push_back(t);
   }
   for (size_t w = 1; w < src.wg_first.size(); ++w) dst.wg_first.push_back(base + src.wg_first[w]);
+  for (tk::TileTask t : src.tiles) {
+    if (t.src_buf >= 0) t.src_buf = static_cast<int16_t>(t.src_buf + member * tk::kBufsPerPlan);
+    t.dst_buf = static_cast<int16_t>(t.dst_buf + member * tk::kBufsPerPlan);
+    dst.tiles.push_back(t);
+  }
 }
 
 void merge_smallk(SmallKSet& dst, const SmallKSet& src, int member, int32_t chan_base, int32_t pair_base) {
@@ -3215,10 +3374,7 @@ void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
 void batch_launch_all(tk_batch& b, hipStream_t stream) {
   tk::Ptrs ptrs{};
   ptrs.table = static_cast<const uint64_t*>(b.d_table.p);
-  if (b.pre.nwg() > 0)
-    hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.pre.d_tasks.p),
-                                 static_cast<const int32_t*>(b.pre.d_wg.p), b.pre.nwg(), ptrs, 1.0, 0.0, stream),
-              "permute launch");
+  launch_tasklist(b.dtype, b.pre, ptrs, 1.0, 0.0, stream, b.precision == TK_PREC_BF16X3, "permute launch");
   if (!b.descs.empty()) {
     tk::GemmArgs ga{};
     ga.descs = static_cast<const GemmDesc*>(b.d_descs.p);
@@ -3267,11 +3423,7 @@ void batch_launch_all(tk_batch& b, hipStream_t stream) {
                                      static_cast<const int32_t*>(b.zranges.d_first.p),
                                      static_cast<const int64_t*>(b.zranges.d_wstart.p), b.zranges.nwg(), ptrs, b.beta, stream),
               "zero-range launch");
-  if (b.zero.nwg() > 0)
-    hip_check(tk::launch_permute(b.dtype, static_cast<const PermTask*>(b.zero.d_tasks.p),
-                                 static_cast<const int32_t*>(b.zero.d_wg.p), b.zero.nwg(), ptrs, b.alpha, b.beta,
-                                 stream),
-              "zero launch");
+  launch_tasklist(b.dtype, b.zero, ptrs, b.alpha, b.beta, stream, false, "zero launch");
 }
 
 }  // namespace
@@ -3300,16 +3452,25 @@ tk_status tk_batch_create(tk_context* ctx, tk_plan* const* plans, const tk_tenso
       check_exec_tensor(C[i], P.C, P.dtype, "C");
       const size_t es = A[i]->esize();
       auto wa = std::make_unique<DevBuf>(), wb = std::make_unique<DevBuf>();
-      if (P.permA) wa->alloc(P.At->size * es);
-      if (P.permB) wb->alloc(P.Bt->size * es);
+      auto wap = std::make_unique<DevBuf>(), wbp = std::make_unique<DevBuf>();
+      if (P.needA) wa->alloc(P.At->size * es);
+      if (P.needB) wb->alloc(P.Bt->size * es);
+      if (P.planeA) wap->alloc(4 * P.planeA);
+      if (P.planeB) wbp->alloc(4 * P.planeB);
+      // one entry per buffer id (kBufA .. kBufBp)
       table.push_back(reinterpret_cast<uint64_t>(A[i]->data));
       table.push_back(reinterpret_cast<uint64_t>(B[i]->data));
       table.push_back(reinterpret_cast<uint64_t>(C[i]->data));
       table.push_back(reinterpret_cast<uint64_t>(wa->p));
       table.push_back(reinterpret_cast<uint64_t>(wb->p));
       table.push_back(0);
+      table.push_back(reinterpret_cast<uint64_t>(wap->p));
+      table.push_back(reinterpret_cast<uint64_t>(wbp->p));
+      static_assert(tk::kBufsPerPlan == 8, "batch table layout");
       b->ws.push_back(std::move(wa));
       b->ws.push_back(std::move(wb));
+      b->ws.push_back(std::move(wap));
+      b->ws.push_back(std::move(wbp));
       merge_tasks(b->pre, P.pre, i);
       merge_tasks(b->zero, P.zero, i);
       for (const auto& r : P.zranges.raw)

@@ -13,11 +13,13 @@ constexpr int kPermChunk = 4096;  // elements of one block task (a workgroup vis
 constexpr int kThreads = 256;
 
 // Buffer ids used by task descriptors.  A plan reads/writes at most these
-// six buffers (operands, result, and workspaces for A~, B~ and, when the
-// output permute cannot be fused, C~); a batch offsets them by kBufsPerPlan
-// per member plan.
-enum BufId : int16_t { kBufA = 0, kBufB = 1, kBufC = 2, kBufAt = 3, kBufBt = 4, kBufCt = 5 };
-constexpr int kBufsPerPlan = 6;
+// eight buffers (operands, result, workspaces for A~, B~ and, when the
+// output permute cannot be fused, C~, and the split-BF16x3 operand planes of
+// A~ and B~); a batch offsets them by kBufsPerPlan per member plan.
+enum BufId : int16_t {
+  kBufA = 0, kBufB = 1, kBufC = 2, kBufAt = 3, kBufBt = 4, kBufCt = 5, kBufAp = 6, kBufBp = 7
+};
+constexpr int kBufsPerPlan = 8;
 
 // Base pointers: either inline (single plan) or a device table (batch).
 struct Ptrs {
@@ -40,7 +42,10 @@ struct PermTask {
   int16_t src_buf;
   int16_t dst_buf;
   float sign;
-  int32_t pad_;
+  // 0: the destination holds the element type; otherwise it is a bf16 hi
+  // plane and element x goes in as hi = bf16(x) at dst and
+  // lo = bf16(x - hi) at dst + lo (split-BF16x3 operands)
+  int32_t lo;
   int32_t dim[kMaxDims];
   int32_t ss[kMaxDims];
   int32_t ds[kMaxDims];
@@ -50,10 +55,31 @@ struct PermTask {
   uint8_t shr[kMaxDims];
 };
 
+// One tile of a block permute staged through LDS: the block's source is
+// contiguous along one dimension (a) and its destination along another (b).
+// The tile covers ea x eb elements (each at most kTileEdge) at a fixed index
+// of every other dimension: element (ia, ib) is read at src + ia + ib * sb and
+// written at dst + ia * ta + ib (times sign; lo as in PermTask), so the reads
+// run along a and the writes along b, both coalesced.
+constexpr int kTileEdge = 64;
+struct TileTask {
+  int64_t src, dst;
+  int32_t ea, eb;
+  int32_t sb, ta;
+  int16_t src_buf, dst_buf;
+  float sign;
+  int32_t lo;
+  int32_t pad_;
+};
+
 // One sector GEMM  C~^c (M x N) = A~^c (M x K) * B~^c (K x N), all
 // column-major.  mode 0: C~^c is written in place at c (ldc).  mode 1: the
 // epilogue scatters every element to its position in C (fused output
 // permute) through the row/column maps and the channel-pair table.
+// Split-BF16x3 operands (a_buf kBufAp, b_buf kBufBp) are bf16 planes with k
+// contiguous: A~ element (m, k) at a + m lda + k, B~ element (k, n) at
+// b + n ldb + k, lda = ldb = K rounded up to a multiple of 8 (the padding
+// holds zeros), and the lo planes alo and blo elements after the hi planes.
 struct GemmDesc {
   int64_t a, b, c;
   int32_t M, N, K;
@@ -64,6 +90,7 @@ struct GemmDesc {
   int32_t pair_base;  // first entry in the pair table
   int32_t ncc;        // column channels of this sector (pair = rc * ncc + cc)
   int32_t pad_;
+  int64_t alo, blo;   // lo-plane offsets of split operands (elements)
 };
 
 // One unit of work of the grouped GEMM: the (m0, n0) tile of sector GEMM
@@ -162,8 +189,12 @@ struct GemmArgs {
 };
 
 // Launchers (tk_kernels.hip).  dtype: 0 fp64, 1 fp32.  precision: tk_precision.
+// LDS-staged tiles (one workgroup each), same alpha / beta / split rules
+hipError_t launch_permute_tiles(int dtype, const TileTask* tiles, int ntiles, const Ptrs& ptrs, double alpha,
+                                double beta, hipStream_t stream, bool split = false);
+// split: tasks with lo != 0 write bf16 hi / lo planes (split-BF16x3 operands)
 hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
-                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream);
+                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream, bool split = false);
 hipError_t launch_gemm(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,
                        int nwg, hipStream_t stream);
 hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n, int tile_k, const GemmArgs& args,

@@ -46,9 +46,20 @@ __device__ __forceinline__ TK_GLOBAL T* buf_ptr(const Ptrs& P, int id) {
 // per thread (the kernel is bound by HBM bandwidth and latency, not ALU).
 constexpr int kBatch = 8;
 
+// One element as a split-BF16x3 operand: hi = bf16(x) (x rounded to fp32
+// first), lo = bf16(x - hi); hi + lo keeps about 16 significant bits.
+template <typename T>
+__device__ __forceinline__ void store_split(TK_GLOBAL __bf16* hi, int64_t lo, T v) {
+  const float x = static_cast<float>(v);
+  const __bf16 h = static_cast<__bf16>(x);
+  hi[0] = h;
+  hi[lo] = static_cast<__bf16>(x - static_cast<float>(h));
+}
+
 // One task, processed by `nthr` threads starting at thread `t0` of the
 // workgroup (the whole workgroup for a large task, one wave for small ones).
-template <typename T>
+// SPLIT: tasks with lo != 0 write bf16 hi and lo planes instead of T.
+template <typename T, bool SPLIT = false>
 __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, const Ptrs& P, double alpha,
                                              double beta, int lt, int nthr) {
   const int n = tk->n;
@@ -110,6 +121,16 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) v[u] = static_cast<T>(alpha) * v[u];
     }
+    if (SPLIT && tk->lo != 0) {
+      // the operand permute of a split-BF16x3 plan (alpha 1, beta 0)
+      TK_GLOBAL __bf16* hi = (TK_GLOBAL __bf16*)buf_ptr<void>(P, tk->dst_buf) + tk->dst;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) {
+        const int e = e0 + u * nthr + lt;
+        if (e < count) store_split(hi + dof[u], tk->lo, v[u]);
+      }
+      continue;
+    }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int e = e0 + u * nthr + lt;
@@ -121,18 +142,63 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
 // A workgroup holding one task spreads it over all its threads; one holding
 // several small tasks gives each wave its own tasks, so their loads are in
 // flight together instead of one task after another.
-template <typename T>
+template <typename T, bool SPLIT = false>
 __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __restrict__ tasks,
                                                            const int32_t* __restrict__ wg_first,
                                                            Ptrs P, double alpha, double beta) {
   const int t0 = wg_first[blockIdx.x];
   const int t1 = wg_first[blockIdx.x + 1];
   if (t1 - t0 == 1) {
-    permute_task<T>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
+    permute_task<T, SPLIT>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
     return;
   }
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T>(tasks + t, P, alpha, beta, lane, 64);
+  for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T, SPLIT>(tasks + t, P, alpha, beta, lane, 64);
+}
+
+// Block permute through LDS, one tile per workgroup: the tile is read with
+// consecutive lanes along the source's contiguous dimension a (16 rows of
+// 64 lanes per pass, all loads of a thread issued before the first LDS
+// store), staged as [ib][ia] with a padded row, and written with consecutive
+// lanes along the destination's contiguous dimension b.  Used where a block's
+// source and destination are contiguous along different dimensions (a plain
+// output-order walk would gather its reads or scatter its writes).
+template <typename T, bool SPLIT>
+__global__ __launch_bounds__(kThreads) void permute_tile_kernel(const TileTask* __restrict__ tiles, Ptrs P,
+                                                                double alpha, double beta) {
+  constexpr int E = kTileEdge, R = kThreads / E;  // R rows per pass
+  __shared__ T tile[E][E + 1];
+  const TileTask tk = tiles[blockIdx.x];
+  const int lane = threadIdx.x % E, row = threadIdx.x / E;
+  const T sign = static_cast<T>(tk.sign);
+  const bool has_src = tk.src_buf >= 0;
+  if (has_src) {
+    const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, tk.src_buf) + tk.src;
+    T v[E / R];
+#pragma unroll
+    for (int u = 0; u < E / R; ++u) {
+      const int ib = row + R * u;
+      v[u] = (lane < tk.ea && ib < tk.eb) ? src[lane + static_cast<int64_t>(ib) * tk.sb] : static_cast<T>(0);
+    }
+#pragma unroll
+    for (int u = 0; u < E / R; ++u) tile[row + R * u][lane] = v[u] * sign;
+  }
+  __syncthreads();
+  // write: lane runs along b, rows along a
+#pragma unroll 4
+  for (int ia = row; ia < tk.ea; ia += R) {
+    if (lane >= tk.eb) continue;
+    const T x = has_src ? tile[lane][ia] : static_cast<T>(0);
+    const int64_t o = static_cast<int64_t>(ia) * tk.ta + lane;
+    if (SPLIT && tk.lo != 0) {
+      store_split((TK_GLOBAL __bf16*)buf_ptr<void>(P, tk.dst_buf) + tk.dst + o, tk.lo, x);
+      continue;
+    }
+    TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk.dst_buf) + tk.dst;
+    T y = static_cast<T>(alpha) * x;
+    if (beta != 0.0) y += static_cast<T>(beta) * dst[o];
+    dst[o] = y;
+  }
 }
 
 // Partial trace: thread per output element; the element's index in the
@@ -679,37 +745,6 @@ struct F64Tile {
 };
 
 
-// Epilogue of a tile accumulated in fp32 (fp32 16x16 MFMA layout: value v
-// of lane l is row 4*(l/16) + v).  Split tiles store their partial sums
-// (fp64, lane-major) for the reduce kernel; others go straight to C.
-template <class TT, typename TS>
-__device__ __forceinline__ void gemm_epilogue_f32(const GemmArgs& args, const GemmDesc& d, const GemmTile& tile,
-                                                  const f4_t (&acc)[TT::TM][TT::TN], int tid, int wm, int wn, int g,
-                                                  int l16) {
-  constexpr int TM = TT::TM, TN = TT::TN, NT = TT::NT;
-  if (tile.nsplit > 1) {
-    double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (TT::WM * TT::WGM * TT::WN * TT::WGN);
-#pragma unroll
-    for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (tile.m0 + wm + 16 * mi + 4 * g + v < d.M && tile.n0 + wn + 16 * ni + l16 < d.N)
-            mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
-  } else {
-    TK_GLOBAL TS* C = buf_ptr<TS>(args.ptrs, d.c_buf);
-#pragma unroll
-    for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          store_elem<TS>(args, d, C, tile.m0 + wm + 16 * mi + 4 * g + v, tile.n0 + wn + 16 * ni + l16,
-                         acc[mi][ni][v]);
-  }
-}
-
 // Origin of wave w's sub-tile.  Waves w and w + NW/2 share a SIMD (waves of
 // a workgroup are spread round robin over the 4 SIMDs of a CU); the first
 // half of the waves covers the top row band, the second half the bottom row
@@ -955,9 +990,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
 // element) pairs: element e of a partial tile is the accumulator value the
 // GEMM thread e % NT held as its value number e / NT.
 // LAYOUT 0: fp64 arithmetic, transposed accumulators (row lane % 16,
-// column lane/16 + 4v); 2: fp32 arithmetic, transposed (row lane % 16,
-// column 4 (lane/16) + v); 1: bf16 kernel rows (4*(lane/16) + v), column
-// lane % 16.
+// column lane/16 + 4v); 2: fp32 accumulation (fp32 or split-BF16x3 MFMAs),
+// transposed (row lane % 16, column 4 (lane/16) + v).
 template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
@@ -977,9 +1011,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const GemmDesc d = const_ptr(args.descs)[tile.gemm];
     int wm, wn;
     wave_origin<TT>(wave, &wm, &wn);
-    const int r = tile.m0 + wm + 16 * mi + (LAYOUT == 1 ? 4 * (lane >> 4) + v : (lane & 15));
-    const int c = tile.n0 + wn + 16 * ni +
-                  (LAYOUT == 0 ? (lane >> 4) + 4 * v : LAYOUT == 2 ? 4 * (lane >> 4) + v : (lane & 15));
+    const int r = tile.m0 + wm + 16 * mi + (lane & 15);
+    const int c = tile.n0 + wn + 16 * ni + (LAYOUT == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
     if (r >= d.M || c >= d.N) continue;
     double sum = 0.0;
     const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
@@ -994,150 +1027,230 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 
-// Compensated split-BF16x3: every operand value a (rounded to fp32) is split
-// into hi = bf16(a) and lo = bf16(a - hi) as it enters LDS; each 16x16x32
-// block of the product is hi*hi + hi*lo + lo*hi on the bf16 MFMA with fp32
-// accumulation (the lo*lo term is dropped).  LDS holds A as [m][k] and B as
-// [n][k] (k contiguous) so a lane fetches its 8 consecutive k values of an
-// MFMA operand with one 16-byte read; lane group g = l/16 owns k = 8g..8g+7.
-template <typename TS, int BM, int BN, int WGM, int WGN, int BK>
-__global__ __launch_bounds__(64 * WGM* WGN, 2) void gemm_bf16x3_kernel(GemmArgs args) {
+// Compensated split-BF16x3 grouped GEMM.  The operand permute has already
+// split every value a (rounded to fp32) into hi = bf16(a) and
+// lo = bf16(a - hi), stored as two planes with k contiguous: A~ by rows
+// (element (m, k) at a + m lda + k), B~ by columns (element (k, n) at
+// b + n ldb + k), lda = ldb = K rounded up to 8 with zero padding.  So a
+// 16-byte load reads 8 consecutive k of one row of A~ or column of B~, both
+// operands stage into LDS as [row][k] with no conversion, and each 16x16x32
+// block of the product is lo*hi' + hi*lo' + hi*hi' on the bf16 MFMA with
+// fp32 accumulation (the lo*lo' term is dropped).  The pipeline is the one of
+// gemm_stream_kernel: every tile of a workgroup is one stream of BK-deep
+// stages (each tile's count rounded up to PF), a load cursor PF + 1 stages
+// ahead through a register ring, a double-buffered LDS stage, one barrier per
+// stage.  Loads are raw buffer loads: rows past M (N) lie past the
+// resource's records and k chunks past the tile's K range get an
+// out-of-range offset, so both read zero.  The MFMAs take B as the first
+// operand, so the accumulators hold the transposed tile (lane l, value v =
+// C[l % 16][4 (l/16) + v]) and the epilogue of the fp32 stream kernel
+// applies.  LDS rows are padded by 8 bf16 (16 bytes): the 16 rows one
+// 16-lane group reads start 20 banks apart and never share a bank.
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+
+template <typename TS, int BM, int BN, int WGM, int WGN, int BK, int PF = 2>
+__global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs args) {
   using TT = F64Tile<BM, BN, WGM, WGN, BK>;
   constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
-  constexpr int KP = BK + 8;  // padded row of bf16 values
-  constexpr int A_ITEMS = BM * BK / 8, B_ITEMS = BN * BK / 8;  // 8-value groups per stage
-  constexpr int A_PT = (A_ITEMS + NT - 1) / NT, B_PT = (B_ITEMS + NT - 1) / NT;
+  constexpr int KP = BK + 8;   // padded LDS row of bf16 values
+  constexpr int CPR = BK / 8;  // 16-byte chunks of a row per stage
+  constexpr int A_CH = BM * CPR, B_CH = BN * CPR;
+  constexpr int A_PT = (A_CH + NT - 1) / NT, B_PT = (B_CH + NT - 1) / NT;
   static_assert(BK % 32 == 0, "bf16 stage depth");
   __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][KP];
   __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][KP];
 
+  const TK_CONST GemmTile* tiles = const_ptr(args.tiles);
+  const TK_CONST GemmDesc* descs = const_ptr(args.descs);
+  const int t_begin = const_ptr(args.wg_first)[blockIdx.x], t_end = const_ptr(args.wg_first)[blockIdx.x + 1];
+  if (t_begin >= t_end) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   int wm, wn;
   wave_origin<TT>(wave, &wm, &wn);
+  auto uni = [](int x) { return __builtin_amdgcn_readfirstlane(x); };
+  auto uni64 = [](int64_t x) {
+    const uint64_t u = static_cast<uint64_t>(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+  };
+  auto padded_stages = [&](int t) {
+    const GemmTile tt = tiles[t];
+    const int n = max(1, (tt.k1 - tt.k0 + BK - 1) / BK);
+    return (n + PF - 1) / PF * PF;
+  };
+  int total = 0;
+  for (int t = t_begin; t < t_end; ++t) total += padded_stages(t);
 
-  for (int ti = args.wg_first[blockIdx.x]; ti < args.wg_first[blockIdx.x + 1]; ++ti) {
-    const GemmTile tile = args.tiles[ti];
-    const GemmDesc d = args.descs[tile.gemm];
-    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a;
-    const TK_GLOBAL TS* B = buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b;
-    f4_t acc[TM][TN];
+  // load cursor: the tile's resources (hi and lo planes of its A rows and B
+  // columns, records = valid rows x ld), its stage count and K range, and
+  // this lane's chunk offsets within a stage
+  int l_t = 0, l_s = 0, l_ns = 0, l_k0 = 0, l_kend = 0;
+  const char *pah = nullptr, *pal = nullptr, *pbh = nullptr, *pbl = nullptr;
+  uint32_t abytes = 0, bbytes = 0;
+  uint32_t a_off[A_PT], b_off[B_PT];
+  int a_kc[A_PT], b_kc[B_PT];
+  auto make_rsrc = [](const char* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), 0, bytes, kBufWord3);
+  };
+  auto uptr = [&](const TK_GLOBAL __bf16* x) {
+    return reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const __bf16*)x)));
+  };
+  auto load_tile = [&](int t_) {
+    const int t = uni(t_);
+    l_t = t;
+    l_s = 0;
+    if (t >= t_end) {  // past the last tile: every later load reads zero
+      l_ns = 1 << 30;
+      l_kend = l_k0;
+      return;
+    }
+    const GemmTile tile = tiles[t];
+    const GemmDesc d = descs[tile.gemm];
+    l_ns = uni(padded_stages(t));
+    l_k0 = uni(tile.k0);
+    l_kend = uni(tile.k1);
+    const TK_GLOBAL __bf16* A = (const TK_GLOBAL __bf16*)buf_ptr<const void>(args.ptrs, d.a_buf) + d.a +
+                                static_cast<int64_t>(tile.m0) * d.lda;
+    const TK_GLOBAL __bf16* B = (const TK_GLOBAL __bf16*)buf_ptr<const void>(args.ptrs, d.b_buf) + d.b +
+                                static_cast<int64_t>(tile.n0) * d.ldb;
+    abytes = static_cast<uint32_t>(uni(max(0, min(BM, d.M - tile.m0)) * d.lda * 2));
+    bbytes = static_cast<uint32_t>(uni(max(0, min(BN, d.N - tile.n0)) * d.ldb * 2));
+    pah = uptr(A);
+    pal = uptr(A + d.alo);
+    pbh = uptr(B);
+    pbl = uptr(B + d.blo);
+#pragma unroll
+    for (int p = 0; p < A_PT; ++p) {
+      const int c = tid + p * NT;
+      a_kc[p] = 8 * (c % CPR);
+      a_off[p] = static_cast<uint32_t>(((c / CPR) * d.lda + a_kc[p]) * 2);
+    }
+#pragma unroll
+    for (int p = 0; p < B_PT; ++p) {
+      const int c = tid + p * NT;
+      b_kc[p] = 8 * (c % CPR);
+      b_off[p] = static_cast<uint32_t>(((c / CPR) * d.ldb + b_kc[p]) * 2);
+    }
+  };
+  u4_t rah_r[PF][A_PT], ral_r[PF][A_PT], rbh_r[PF][B_PT], rbl_r[PF][B_PT];
+  auto gload_next = [&](int slot) {
+    const int k0 = l_k0 + l_s * BK;
+    const __amdgpu_buffer_rsrc_t rah = make_rsrc(pah, abytes), ral = make_rsrc(pal, abytes);
+    const __amdgpu_buffer_rsrc_t rbh = make_rsrc(pbh, bbytes), rbl = make_rsrc(pbl, bbytes);
+#pragma unroll
+    for (int p = 0; p < A_PT; ++p) {
+      const bool ok = (A_CH % NT == 0 || tid + p * NT < A_CH) && k0 + a_kc[p] < l_kend;
+      const uint32_t off = ok ? a_off[p] + static_cast<uint32_t>(k0 * 2) : 0x80000000u;
+      rah_r[slot][p] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(rah, off, 0, 0));
+      ral_r[slot][p] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(ral, off, 0, 0));
+    }
+#pragma unroll
+    for (int p = 0; p < B_PT; ++p) {
+      const bool ok = (B_CH % NT == 0 || tid + p * NT < B_CH) && k0 + b_kc[p] < l_kend;
+      const uint32_t off = ok ? b_off[p] + static_cast<uint32_t>(k0 * 2) : 0x80000000u;
+      rbh_r[slot][p] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(rbh, off, 0, 0));
+      rbl_r[slot][p] = __builtin_bit_cast(u4_t, __builtin_amdgcn_raw_buffer_load_b128(rbl, off, 0, 0));
+    }
+    if (++l_s == l_ns) load_tile(l_t + 1);
+  };
+  auto lstore = [&](int slot, int buf) {
+#pragma unroll
+    for (int p = 0; p < A_PT; ++p) {
+      const int c = tid + p * NT;
+      if (A_CH % NT == 0 || c < A_CH) {
+        *reinterpret_cast<u4_t*>(&Ah[buf][c / CPR][8 * (c % CPR)]) = rah_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Al[buf][c / CPR][8 * (c % CPR)]) = ral_r[slot][p];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < B_PT; ++p) {
+      const int c = tid + p * NT;
+      if (B_CH % NT == 0 || c < B_CH) {
+        *reinterpret_cast<u4_t*>(&Bh[buf][c / CPR][8 * (c % CPR)]) = rbh_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Bl[buf][c / CPR][8 * (c % CPR)]) = rbl_r[slot][p];
+      }
+    }
+  };
+
+  f4_t acc[TM][TN];
+  auto compute = [&](int cur) {
+#pragma unroll
+    for (int kb = 0; kb < BK / 32; ++kb) {
+      bf8_t ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi) {
+        ah[mi] = *reinterpret_cast<const bf8_t*>(&Ah[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
+        al[mi] = *reinterpret_cast<const bf8_t*>(&Al[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
+      }
+#pragma unroll
+      for (int ni = 0; ni < TN; ++ni) {
+        bh[ni] = *reinterpret_cast<const bf8_t*>(&Bh[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
+        bl[ni] = *reinterpret_cast<const bf8_t*>(&Bl[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
+      }
+#pragma unroll
+      for (int mi = 0; mi < TM; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < TN; ++ni) {
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl[ni], ah[mi], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[ni], al[mi], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh[ni], ah[mi], acc[mi][ni], 0, 0, 0);
+        }
+    }
+  };
+
+  int ct = t_begin, cbase = 0, cnst = 0;
+  bool active = false;
+  auto compute_tile = [&](int t) {
+    const GemmTile tile = tiles[t];
+    const GemmDesc d = descs[tile.gemm];
+    cnst = max(1, (tile.k1 - tile.k0 + BK - 1) / BK);
+    active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
-    const int kend = tile.k1;
-    float ra[A_PT][8], rb[B_PT][8];
-    // A item x: m = x % BM, k group = x / BM (consecutive threads, consecutive m)
-    // B item x: k group = x % (BK/8), n = x / (BK/8) (a column's k groups adjacent)
-    auto gload = [&](int k0) {
+  };
+  compute_tile(ct);
+
+  load_tile(t_begin);
 #pragma unroll
-      for (int p = 0; p < A_PT; ++p) {
-        const int x = tid + p * NT;
-        const int m = x % BM, kg = x / BM;
-        const int gm = tile.m0 + m;
+  for (int p = 0; p < PF; ++p) gload_next(p);
+  lstore(0, 0);
+  gload_next(0);
+  for (int G0 = 0; G0 < total; G0 += PF) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = k0 + 8 * kg + q;
-          ra[p][q] = (x < A_ITEMS && gm < d.M && k < kend) ? static_cast<float>(A[static_cast<int64_t>(k) * d.lda + gm])
-                                                           : 0.f;
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < B_PT; ++p) {
-        const int x = tid + p * NT;
-        const int kg = x % (BK / 8), n = x / (BK / 8);
-        const int gn = tile.n0 + n;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int k = k0 + 8 * kg + q;
-          rb[p][q] = (x < B_ITEMS && gn < d.N && k < kend) ? static_cast<float>(B[static_cast<int64_t>(gn) * d.ldb + k])
-                                                           : 0.f;
-        }
-      }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-      for (int p = 0; p < A_PT; ++p) {
-        const int x = tid + p * NT;
-        if (x < A_ITEMS) {
-          const int m = x % BM, kg = x / BM;
-          bf8_t h, l;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            h[q] = static_cast<__bf16>(ra[p][q]);
-            l[q] = static_cast<__bf16>(ra[p][q] - static_cast<float>(h[q]));
-          }
-          *reinterpret_cast<bf8_t*>(&Ah[buf][m][8 * kg]) = h;
-          *reinterpret_cast<bf8_t*>(&Al[buf][m][8 * kg]) = l;
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < B_PT; ++p) {
-        const int x = tid + p * NT;
-        if (x < B_ITEMS) {
-          const int kg = x % (BK / 8), n = x / (BK / 8);
-          bf8_t h, l;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            h[q] = static_cast<__bf16>(rb[p][q]);
-            l[q] = static_cast<__bf16>(rb[p][q] - static_cast<float>(h[q]));
-          }
-          *reinterpret_cast<bf8_t*>(&Bh[buf][n][8 * kg]) = h;
-          *reinterpret_cast<bf8_t*>(&Bl[buf][n][8 * kg]) = l;
-        }
-      }
-    };
-    const bool active = tile.m0 + wm < d.M && tile.n0 + wn < d.N;
-    auto compute = [&](int cur) {
-      if (!active) return;
-#pragma unroll
-      for (int kb = 0; kb < BK / 32; ++kb) {
-        bf8_t ah[TM], al[TM], bh[TN], bl[TN];
-#pragma unroll
-        for (int mi = 0; mi < TM; ++mi) {
-          ah[mi] = *reinterpret_cast<const bf8_t*>(&Ah[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
-          al[mi] = *reinterpret_cast<const bf8_t*>(&Al[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
-        }
-#pragma unroll
-        for (int ni = 0; ni < TN; ++ni) {
-          bh[ni] = *reinterpret_cast<const bf8_t*>(&Bh[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
-          bl[ni] = *reinterpret_cast<const bf8_t*>(&Bl[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
-        }
+    for (int u = 0; u < PF; ++u) {
+      const int G = G0 + u;
+      __syncthreads();
+      lstore((u + 1) % PF, (G + 1) & 1);
+      gload_next((u + 1) % PF);
+      if (active && G - cbase < cnst) compute(G & 1);
+    }
+    if (G0 + PF - cbase >= cnst) {
+      const GemmTile tile = tiles[ct];
+      const GemmDesc d = descs[tile.gemm];
+      if (tile.nsplit > 1) {
+        double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
-          for (int ni = 0; ni < TN; ++ni) {
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
-          }
+          for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + 4 * g + v < d.N)
+                mine[((mi * TN + ni) * 4 + v) * NT + tid] = static_cast<double>(acc[mi][ni][v]);
+      } else {
+        store_tile_t<TS, f4_t, TM, TN, 1>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
+                                          tile.n0 + wn + 4 * g, acc);
       }
-    };
-    const int nst = (tile.k1 - tile.k0 + BK - 1) / BK;
-    gload(tile.k0);
-    lstore(0);
-    if (nst > 1) gload(tile.k0 + BK);
-    int st = 0;
-    for (; st + 2 < nst; ++st) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      gload(tile.k0 + (st + 2) * BK);
-      compute(st & 1);
+      cbase = G0 + PF;
+      if (++ct < t_end) compute_tile(ct);
     }
-    if (st + 1 < nst) {
-      __syncthreads();
-      lstore((st + 1) & 1);
-      compute(st & 1);
-      ++st;
-    }
-    __syncthreads();
-    compute(st & 1);
-    gemm_epilogue_f32<TT, TS>(args, d, tile, acc, tid, wm, wn, g, l16);
-    __syncthreads();
   }
 }
 
@@ -1561,14 +1674,38 @@ hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, d
   return hipGetLastError();
 }
 
+hipError_t launch_permute_tiles(int dtype, const TileTask* tiles, int ntiles, const Ptrs& ptrs, double alpha,
+                                double beta, hipStream_t stream, bool split) {
+  if (ntiles <= 0) return hipSuccess;
+  if (dtype == 0 && split)
+    hipLaunchKernelGGL((permute_tile_kernel<double, true>), dim3(ntiles), dim3(kThreads), 0, stream, tiles, ptrs,
+                       alpha, beta);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((permute_tile_kernel<double, false>), dim3(ntiles), dim3(kThreads), 0, stream, tiles, ptrs,
+                       alpha, beta);
+  else if (split)
+    hipLaunchKernelGGL((permute_tile_kernel<float, true>), dim3(ntiles), dim3(kThreads), 0, stream, tiles, ptrs,
+                       alpha, beta);
+  else
+    hipLaunchKernelGGL((permute_tile_kernel<float, false>), dim3(ntiles), dim3(kThreads), 0, stream, tiles, ptrs,
+                       alpha, beta);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute(int dtype, const PermTask* tasks, const int32_t* wg_first, int nwg,
-                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream) {
+                          const Ptrs& ptrs, double alpha, double beta, hipStream_t stream, bool split) {
   if (nwg <= 0) return hipSuccess;
-  if (dtype == 0)
-    hipLaunchKernelGGL(permute_kernel<double>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+  if (dtype == 0 && split)
+    hipLaunchKernelGGL((permute_kernel<double, true>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+                       ptrs, alpha, beta);
+  else if (dtype == 0)
+    hipLaunchKernelGGL((permute_kernel<double, false>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+                       ptrs, alpha, beta);
+  else if (split)
+    hipLaunchKernelGGL((permute_kernel<float, true>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
                        ptrs, alpha, beta);
   else
-    hipLaunchKernelGGL(permute_kernel<float>, dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
+    hipLaunchKernelGGL((permute_kernel<float, false>), dim3(nwg), dim3(kThreads), 0, stream, tasks, wg_first,
                        ptrs, alpha, beta);
   return hipGetLastError();
 }
@@ -1729,7 +1866,7 @@ static void launch_gemm_kind(int kind, const GemmArgs& args, int nwg, hipStream_
     hipLaunchKernelGGL((gemm_stream_kernel<TS, float, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
   } else {
     if constexpr (BK % 32 == 0)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
+      hipLaunchKernelGGL((gemm_split3_kernel<TS, BM, BN, WM, WN, BK>), grid, block, 0, stream, args);
   }
 }
 
@@ -1764,7 +1901,8 @@ static int blocks_per_cu_kind(int kind) {
                                                      64 * WM * WN, 0);
   } else {
     if constexpr (BK % 32 == 0)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_bf16x3_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, gemm_split3_kernel<TS, BM, BN, WM, WN, BK>, 64 * WM * WN,
+                                                       0);
   }
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -1799,14 +1937,10 @@ hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n
   if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                       \
     if (dtype == 0 && kind == 0) {                                                             \
       TK_RED_LAUNCH(double, 0, BM_, BN_, WM_, WN_);                                                                \
-    } else if (dtype == 0 && kind == 1) {                                                      \
-      TK_RED_LAUNCH(double, 2, BM_, BN_, WM_, WN_);                                                                \
     } else if (dtype == 0) {                                                                   \
-      TK_RED_LAUNCH(double, 1, BM_, BN_, WM_, WN_);                                                                \
-    } else if (kind == 1) {                                                                    \
-      TK_RED_LAUNCH(float, 2, BM_, BN_, WM_, WN_);                                                                 \
+      TK_RED_LAUNCH(double, 2, BM_, BN_, WM_, WN_);                                                                \
     } else {                                                                                   \
-      TK_RED_LAUNCH(float, 1, BM_, BN_, WM_, WN_);                                                                 \
+      TK_RED_LAUNCH(float, 2, BM_, BN_, WM_, WN_);                                                                 \
     }                                                                                          \
     return hipGetLastError();                                                                  \
   }

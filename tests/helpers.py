@@ -5,7 +5,8 @@ import itertools
 
 import numpy as np
 
-from oracle.graded import Space, Structure
+from oracle import blockwise
+from oracle.graded import Space, Structure, permute_spaces
 from paper_2508_10076_amd import synth
 
 
@@ -122,3 +123,46 @@ def wide_n_case(rng, sym):
         oc = [int(x) for x in rng.permutation(4)]
         n1 = int(rng.integers(0, 5))
         return tA, (0, 1), (2,), tB, (0,), (1, 2), oc[:n1], oc[n1:]
+
+
+def random_tdict(rng, sym, n1, n2, **kw):
+    while True:
+        t = dict(sym=sym, cod=[synth.random_space(rng, sym, **kw) for _ in range(n1)],
+                 dom=[synth.random_space(rng, sym, **kw) for _ in range(n2)])
+        if ostruct(t).size:
+            return t
+
+
+def plan_case(rng, sym, max_deg=3):
+    """A random valid contraction: A over 1-2 + 1-2 random legs, contracted
+    over a random subset, B built around the contracted spaces with 0-2 free
+    legs, random leg orders and codomain / domain splits for B~ and C."""
+    while True:
+        tA = random_tdict(rng, sym, int(rng.integers(1, 3)), int(rng.integers(1, 3)), max_deg=max_deg)
+        stA = ostruct(tA)
+        nA = stA.N1 + stA.N2
+        k = int(rng.integers(1, nA + 1))
+        legs = [int(x) for x in rng.permutation(nA)]
+        qA, pA = legs[:k], legs[k:]
+        _, Adom = permute_spaces(stA.cod, stA.dom, pA, qA)
+        free = [synth.random_space(rng, sym, max_deg=max_deg) for _ in range(int(rng.integers(0, 3)))]
+        Bt = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in Adom], dom=free)
+        stBt = ostruct(Bt)
+        if not stBt.size:
+            continue
+        nB = k + len(free)
+        order = [int(x) for x in rng.permutation(nB)]
+        n1B = int(rng.integers(0, nB + 1))
+        stB, _ = blockwise.permute(stBt, {}, order[:n1B], order[n1B:])
+        inv = [0] * nB
+        for n, l in enumerate(order):
+            inv[l] = n
+        pB, qB = inv[:k], inv[k:]
+        tB = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.cod],
+                  dom=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.dom])
+        if not stB.size:
+            continue
+        nC = len(pA) + len(qB)
+        oc = [int(x) for x in rng.permutation(nC)]
+        n1C = int(rng.integers(0, nC + 1))
+        return tA, pA, qA, tB, pB, qB, oc[:n1C], oc[n1C:]

@@ -12,7 +12,7 @@ import pytest
 from oracle import blockwise
 from oracle.graded import Structure, permute_spaces
 from paper_2508_10076_amd import synth
-from tests.helpers import ospace, ostruct
+from tests.helpers import ospace, ostruct, plan_case
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 tk = pytest.importorskip("paper_2508_10076_amd.tk")
@@ -127,35 +127,7 @@ def test_permute_map_and_signs_match_oracle(sym):
 
 def _plan_case(rng, sym):
     """A random valid contraction (as in the oracle pins)."""
-    while True:
-        tA = random_tdict(rng, sym, int(rng.integers(1, 3)), int(rng.integers(1, 3)), max_deg=3)
-        stA = ostruct(tA)
-        nA = stA.N1 + stA.N2
-        k = int(rng.integers(1, nA + 1))
-        legs = [int(x) for x in rng.permutation(nA)]
-        qA, pA = legs[:k], legs[k:]
-        _, Adom = permute_spaces(stA.cod, stA.dom, pA, qA)
-        free = [synth.random_space(rng, sym, max_deg=3) for _ in range(int(rng.integers(0, 3)))]
-        Bt = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in Adom], dom=free)
-        stBt = ostruct(Bt)
-        if not stBt.size:
-            continue
-        nB = k + len(free)
-        order = [int(x) for x in rng.permutation(nB)]
-        n1B = int(rng.integers(0, nB + 1))
-        stB, _ = blockwise.permute(stBt, {}, order[:n1B], order[n1B:])
-        inv = [0] * nB
-        for n, l in enumerate(order):
-            inv[l] = n
-        pB, qB = inv[:k], inv[k:]
-        tB = dict(sym=sym, cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.cod],
-                  dom=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in stB.dom])
-        if not stB.size:
-            continue
-        nC = len(pA) + len(qB)
-        oc = [int(x) for x in rng.permutation(nC)]
-        n1C = int(rng.integers(0, nC + 1))
-        return tA, pA, qA, tB, pB, qB, oc[:n1C], oc[n1C:]
+    return plan_case(rng, sym)
 
 
 @pytest.mark.parametrize("sym", ["U1", "U1xFZ2"])

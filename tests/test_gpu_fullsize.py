@@ -413,3 +413,140 @@ def test_peps_d16_bf16x3_gaussian_sampled_bound(ctx):
     say(f"peps D16 bf16x3: max |err| / (|A+||A|) = {np.max(err[nz] / absum[nz]):.3e}, "
         f"normwise over the sample {np.linalg.norm(err) / np.linalg.norm(ref):.3e}")
     assert np.max(err) > 0     # the reduced precision really was used
+
+
+# ---------------------------------------------------------------------------
+# split-BF16x3 operand planes (written by the operand permute)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sym", ["U1", "U1xFZ2"])
+def test_bf16x3_planes_random_contractions_integer_exact(ctx, sym):
+    """Random contractions with degeneracies up to 12, so coupled sectors
+    with K > 8 (split operand planes, MFMA) and K <= 8 (small-K path) mix in
+    one plan, with random leg orders (identity permutations and dual
+    contracted legs included): integers are exact in bf16 and every partial
+    sum stays below 2^24, so the split-BF16x3 mode equals the oracle."""
+    from tests.helpers import plan_case
+    rng = np.random.default_rng(3300 + len(sym))
+    mfma = 0
+    for trial in range(24):
+        tA, pA, qA, tB, pB, qB, pAB, qAB = plan_case(rng, sym, max_deg=12)
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, pB, qB, pAB, qAB)
+        P = tk.Plan(ctx, A, pA, qA, B, pB, qB, pAB, qAB, Cg, precision="bf16x3")
+        mfma += int((P.gemms()[:, 2] > 8).sum()) if P.info()["ngemm"] else 0
+        fill(Cg)
+        P.execute(A, B, Cg)
+        _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, pB, qB, pAB, qAB)
+        assert np.array_equal(download(Cg), ref), (sym, trial)
+    assert mfma >= 4
+
+
+def test_bf16x3_planes_identity_and_twist(ctx):
+    """Operands that need no permute (their planes come from an identity
+    permute) and a contracted dual odd leg (the composition twist folded
+    into B~'s planes), U(1) x fZ2, integer data, exact."""
+    V = synth.space([(q, p) for p in (0, 1) for q in (-1, 0, 1)], [5, 9, 6, 7, 4, 11])
+    W = synth.space([(0, 0), (1, 1), (-1, 1)], [13, 10, 12])
+    rng = np.random.default_rng(3310)
+    for dual in (False, True):
+        Wk = synth.dual(W) if dual else W
+        tA = dict(sym="U1xFZ2", cod=[V], dom=[Wk, V])
+        tB = dict(sym="U1xFZ2", cod=[Wk, V], dom=[W])
+        stA, stB = ostruct(tA), ostruct(tB)
+        a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+        A, B = make(ctx, tA, a), make(ctx, tB, b)
+        for pAB, qAB in (((0,), (1,)), ((1,), (0,)), ((0, 1), ())):
+            Cg = tk.tensor_create_contracted(ctx, A, (0,), (1, 2), B, (0, 1), (2,), pAB, qAB)
+            fill(Cg)
+            tk.tensor_contract(ctx, A, (0,), (1, 2), B, (0, 1), (2,), pAB, qAB, precision="bf16x3", C_=Cg)
+            _, ref = blockwise.contract_storage(stA, a, (0,), (1, 2), stB, b, (0, 1), (2,), pAB, qAB)
+            assert np.array_equal(download(Cg), ref), (dual, pAB, qAB)
+
+
+def test_bf16x3_batch_config4_integer_exact(ctx):
+    """The 64-contraction batch in split-BF16x3 (per-member operand planes
+    in the batch's buffer table), replayed from a graph: exact on integers."""
+    cfg = synth.config4()
+    rng = np.random.default_rng(4410)
+    data = [(int_vec(rng, ostruct(it["A"]).size), int_vec(rng, ostruct(it["B"]).size)) for it in cfg["items"]]
+    refs = batch_oracle(cfg, data)
+    call = cfg["call"]
+    plans, As, Bs, Cs = [], [], [], []
+    for it, (a, b) in zip(cfg["items"], data):
+        A, B = make(ctx, it["A"], a), make(ctx, it["B"], b)
+        Cg = tk.tensor_create_contracted(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"],
+                                         call["qAB"])
+        plans.append(tk.Plan(ctx, A, call["pA"], call["qA"], B, call["pB"], call["qB"], call["pAB"], call["qAB"],
+                             Cg, precision="bf16x3"))
+        As.append(A)
+        Bs.append(B)
+        Cs.append(Cg)
+    batch = tk.Batch(ctx, plans, As, Bs, Cs)
+    say("case config4 bf16x3 batch")
+
+    def check(i, got, rep):
+        assert np.array_equal(got, refs[i]), (i, rep)
+    replays(batch, Cs, torch.cuda.Stream(), check)
+
+
+# ---------------------------------------------------------------------------
+# LDS-staged block permutes (source and destination contiguous along
+# different legs)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tile_permute_every_leg_order_exact(ctx, dtype):
+    """A U(1) tensor with long legs (17..131, ragged against the 64-wide
+    tiles) permuted into every leg order and codomain / domain split: the
+    blocks whose fastest source and destination legs differ go through LDS
+    tiles, the rest through the output-order walk; bit-exact in fp64 and
+    fp32 (a permute moves values, it does not round them)."""
+    import itertools
+    V = synth.u1_space([-1, 0, 1], [17, 131, 64])
+    W = synth.u1_space([0, 1], [70, 23])
+    t = dict(sym="U1", cod=[V, W], dom=[V])
+    st = ostruct(t)
+    v = np.random.default_rng(61).standard_normal(st.size)
+    if dtype == "f32":
+        v = v.astype(np.float32).astype(np.float64)
+    A = make(ctx, t, v, dtype)
+    tiles = 0
+    for perm in itertools.permutations(range(3)):
+        for n1 in range(4):
+            p, q = perm[:n1], perm[n1:]
+            Cg = tk.tensor_create_permuted(ctx, A, p, q)
+            fill(Cg)
+            tk.tensor_permute(ctx, A, p, q, Cg)
+            _, ref = blockwise.permute_storage(st, v, p, q)
+            assert np.array_equal(download(Cg), ref), (p, q)
+            tiles += 1
+    assert tiles == 24
+
+
+def test_tile_permute_after_gemm_alpha_beta(ctx):
+    """An output permute that cannot be fused (five row legs in C~) runs after
+    the sector GEMMs, here through LDS tiles (C~ is contiguous along X, C
+    along W, both 16..20 long), with alpha = 2 and beta = -1: integer data,
+    exact against the oracle."""
+    X = synth.u1_space([0, 1], [17, 20])
+    Y = synth.u1_space([0], [2])
+    Kl = synth.u1_space([-1, 0, 1], [9, 12, 10])
+    Wl = synth.u1_space([0, 1], [16, 19])
+    tA = dict(sym="U1", cod=[X, Y, X], dom=[Y, Y, Kl])
+    stA = ostruct(tA)
+    pA, qA = (0, 1, 2, 3, 4), (5,)
+    from oracle.graded import permute_spaces
+    _, Adom = permute_spaces(stA.cod, stA.dom, pA, qA)
+    tB = dict(sym="U1", cod=[synth.SpaceSpec(s.sectors, s.degs, s.dual) for s in Adom], dom=[Wl])
+    stB = ostruct(tB)
+    rng = np.random.default_rng(62)
+    a, b = int_vec(rng, stA.size), int_vec(rng, stB.size)
+    A, B = make(ctx, tA, a), make(ctx, tB, b)
+    pAB, qAB = (5, 0, 4), (1, 3, 2)
+    Cg = tk.tensor_create_contracted(ctx, A, pA, qA, B, (0,), (1,), pAB, qAB)
+    c0 = int_vec(rng, Cg.nelem)
+    upload(Cg, c0)
+    tk.tensor_contract(ctx, A, pA, qA, B, (0,), (1,), pAB, qAB, alpha=2.0, beta=-1.0, C_=Cg)
+    _, ref = blockwise.contract_storage(stA, a, pA, qA, stB, b, (0,), (1,), pAB, qAB, alpha=2.0, beta=-1.0, vC=c0)
+    assert np.array_equal(download(Cg), ref)
