@@ -23,8 +23,23 @@ Conventions (shared with the HIP path only through this description):
   first leg fastest), then by intermediates e_2..e_{N-1} (colex).
 * permute(t, (p, q)) moves output codomain leg k to input leg p[k] and
   output domain leg k to input leg q[k]; here every p[k] is a codomain leg
-  and every q[k] a domain leg (braids within each side; bending legs between
-  the sides is not covered).
+  and every q[k] a domain leg (braids within each side).
+* Dual legs (section "Duality Fusion Tree Manipulations"): a leg may carry
+  the dual space V_j* of its sectors.  The canonical trees keep spin j on
+  such a leg and add the isomorphism between V_j* and V_j on the outer line
+  (Z^dagger on a splitting tree, Z on a fusion tree); here Z maps the dual
+  basis vector of m to (-1)^(j-m) times the vector of -m, so on a dual leg
+  the dense index of m (position i = j - m) holds (-1)^i times the tree's
+  value at -m, on either side.  For SU(2) the Frobenius-Schur phase of spin j
+  is (-1)^(2j).
+* transpose(t, (p, q)) (the generalised transpose and permute of the
+  paper: any legs may cross between codomain and domain, a crossing leg
+  turning into the dual space): on dense arrays a bend is the identity on
+  components (coevaluation and evaluation pair a basis with its dual basis),
+  so the transformed map is the array with its axes reordered to (p, q),
+  projected onto the canonical trees of the new structure.  Its
+  coefficients per pair of trees are computed the same way on the dense
+  form of one tree pair (pair_coeffs) and applied to the reduced arrays.
 
 The transformation coefficients are the overlaps of each permuted tree with
 the canonical trees (the projection method of Section "Fusion Tree
@@ -135,13 +150,37 @@ def tree_tensor(outer, inter, tc) -> np.ndarray:
     return T
 
 
-class SU2Map:
-    """Structure of t : cod <- dom (legs as lists of (tj, deg))."""
+def dualize(T, axes):
+    """Puts the isomorphism Z between V_j* and V_j on the given axes of a dense
+    tree or tree pair: along each axis, entry i becomes (-1)^i times entry
+    2j - i (m = j - i goes to -m)."""
+    for ax in axes:
+        n = T.shape[ax]
+        sign = np.array([(-1.0) ** i for i in range(n)])
+        shape = [1] * T.ndim
+        shape[ax] = n
+        T = np.flip(T, axis=ax) * sign.reshape(shape)
+    return T
 
-    def __init__(self, cod, dom):
+
+def pair_tensor(cod_outer, dom_outer, s_inter, f_inter, tc, duals=()) -> np.ndarray:
+    """Dense tree pair X_s . X_f^T summed over m_c, axes [m_cod.., m_dom..],
+    with Z on the legs listed in duals (global leg numbers)."""
+    X = tree_tensor(cod_outer, s_inter, tc)
+    Y = tree_tensor(dom_outer, f_inter, tc)
+    G = np.tensordot(X, Y, axes=([len(cod_outer)], [len(dom_outer)]))
+    return dualize(G, duals)
+
+
+class SU2Map:
+    """Structure of t : cod <- dom (legs as lists of (tj, deg)); dual lists
+    the legs (0-based, codomain then domain) that carry the dual space."""
+
+    def __init__(self, cod, dom, dual=()):
         self.cod = [sorted(l) for l in cod]
         self.dom = [sorted(l) for l in dom]
         self.N1, self.N2 = len(self.cod), len(self.dom)
+        self.dual = tuple(sorted(dual))
         assert self.N1 >= 1 and self.N2 >= 1
         rows = self._side(self.cod)
         cols = self._side(self.dom)
@@ -269,9 +308,7 @@ def to_dense(st: SU2Map, vec) -> np.ndarray:
     info = [leg_dense_index(l) for l in legs]
     T = np.zeros([n for _, n in info])
     for tc, s, f in st.pairs():
-        X = tree_tensor(st.outer(s, 0), s[1], tc)
-        Y = tree_tensor(st.outer(f, 1), f[1], tc)
-        G = np.tensordot(X, Y, axes=([st.N1], [st.N2]))  # [m_cod.., m_dom..]
+        G = pair_tensor(st.outer(s, 0), st.outer(f, 1), s[1], f[1], tc, st.dual)  # [m_cod.., m_dom..]
         r = st.get(vec, tc, s, f)  # [i_cod.., j_dom..]
         N = st.N1 + st.N2
         # block[i_1, m_1, i_2, m_2, ...] = r[i..] * G[m..]
@@ -296,9 +333,7 @@ def from_dense(st: SU2Map, T) -> np.ndarray:
     N = st.N1 + st.N2
     vec = np.zeros(st.size)
     for tc, s, f in st.pairs():
-        X = tree_tensor(st.outer(s, 0), s[1], tc)
-        Y = tree_tensor(st.outer(f, 1), f[1], tc)
-        G = np.tensordot(X, Y, axes=([st.N1], [st.N2]))
+        G = pair_tensor(st.outer(s, 0), st.outer(f, 1), s[1], f[1], tc, st.dual)
         idx = list(s[0]) + list(f[0])
         sl, shape = [], []
         for k in range(N):
@@ -310,3 +345,69 @@ def from_dense(st: SU2Map, T) -> np.ndarray:
         r = np.tensordot(blk, G, axes=(list(range(1, 2 * N, 2)), list(range(N))))
         st.add(vec, tc, s, f, r / (tc + 1))
     return vec
+
+
+def transpose_legs(st: SU2Map, p, q) -> SU2Map:
+    """Structure of transpose(t, (p, q)): output codomain leg k is input leg
+    p[k], output domain leg k input leg q[k]; a leg that changes sides carries
+    the dual of its space."""
+    N1 = st.N1
+    legs = st.cod + st.dom
+    assert sorted(list(p) + list(q)) == list(range(len(legs))) and len(p) >= 1 and len(q) >= 1
+    dual = []
+    for k, g in enumerate(list(p) + list(q)):
+        crossed = (g < N1) != (k < len(p))
+        if (g in st.dual) != crossed:
+            dual.append(k)
+    return SU2Map([legs[g] for g in p], [legs[g] for g in q], dual)
+
+
+def pair_coeffs(st: SU2Map, out: SU2Map, cod_outer, dom_outer, s_inter, f_inter, tc, p, q):
+    """Coefficients of one input tree pair, its dense form with axes
+    reordered to (p, q), in the canonical tree pairs of the output with the
+    same outer spins: {(s_inter', f_inter', tc'): coefficient}."""
+    order = list(p) + list(q)
+    G = pair_tensor(cod_outer, dom_outer, s_inter, f_inter, tc, st.dual).transpose(order)
+    outer = list(cod_outer) + list(dom_outer)
+    oc, od = [outer[g] for g in p], [outer[g] for g in q]
+    res = {}
+    for si, c1 in trees(oc):
+        for fi, c2 in trees(od):
+            if c1 != c2:
+                continue
+            H = pair_tensor(oc, od, si, fi, c1, out.dual)
+            v = float(np.sum(H * G)) / (c1 + 1)  # tree pairs are orthonormal: d_c per pair
+            if abs(v) > 1e-13:
+                res[(si, fi, c1)] = v
+    return res
+
+
+def transpose(st: SU2Map, vec, p, q):
+    """transpose(t, (p, q)) by coefficients: every input pair (s, f) adds
+    coefficient times its reduced array, axes reordered to (p, q), to every
+    output pair it reaches.  Returns (structure, data)."""
+    out = transpose_legs(st, p, q)
+    order = list(p) + list(q)
+    y = np.zeros(out.size)
+    rowpos = {tc: {(r[0], r[1]): r for r in out.rows[tc]} for tc in out.blocks}
+    colpos = {tc: {(c[0], c[1]): c for c in out.cols[tc]} for tc in out.blocks}
+    cache = {}
+    for tc, s, f in st.pairs():
+        co, do = st.outer(s, 0), st.outer(f, 1)
+        key = (tuple(co), tuple(do), s[1], f[1], tc)
+        if key not in cache:
+            cache[key] = pair_coeffs(st, out, co, do, s[1], f[1], tc, p, q)
+        xp = st.get(vec, tc, s, f).transpose(order)
+        idx = list(s[0]) + list(f[0])
+        sidx = tuple(idx[g] for g in p)
+        fidx = tuple(idx[g] for g in q)
+        for (si, fi, c2), cf in cache[key].items():
+            out.add(y, c2, rowpos[c2][(sidx, si)], colpos[c2][(fidx, fi)], cf * xp)
+    return out, y
+
+
+def transpose_dense(st: SU2Map, vec, p, q):
+    """The definition: the dense array with its axes reordered to (p, q),
+    projected onto the output's canonical tree pairs."""
+    out = transpose_legs(st, p, q)
+    return out, from_dense(out, to_dense(st, vec).transpose(list(p) + list(q)))

@@ -173,3 +173,125 @@ def test_identity_permutation_is_a_copy():
     out, y = su2.permute(st, x, [0, 1, 2, 3], [4, 5])
     # each tree overlaps itself with 1, up to the rounding of the dense sums
     np.testing.assert_allclose(y, x, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# transposition: legs moving between codomain and domain (dual legs)
+# ---------------------------------------------------------------------------
+def _transpose_fixture():
+    lines = [l for l in open(os.path.join(GOLDEN, "su2_transpose_matrix.txt")).read().splitlines()
+             if l and not l.startswith("#")]
+    i, j = lines.index("formula"), lines.index("matrix")
+    form = np.zeros((9, 9))
+    for l in lines[i + 1:j]:
+        lhs, rhs = l.split("=")
+        for term in rhs.split("+"):
+            c, ch = term.strip().split("*")
+            form[int(lhs) - 1, int(ch) - 1] = float(c)
+    mat = np.array([[float(x) for x in l.split()] for l in lines[j + 1:]])
+    return form, mat
+
+
+def test_dual_trees_are_invariant():
+    """A tree pair with dual legs (Z on the outer lines) is an intertwiner:
+    on a dual leg the generators act as -J^T (the dual representation), so
+    sum over legs of the generator annihilates the dense pair; this pins the
+    isomorphism Z (a wrong sign or index order breaks it)."""
+    outer_c, outer_d = [1, 2], [3]
+    for s_inter, tc in su2.trees(outer_c):
+        for f_inter, tc2 in su2.trees(outer_d):
+            if tc != tc2:
+                continue
+            for duals in [(), (0,), (1, 2), (0, 1, 2)]:
+                G = su2.pair_tensor(outer_c, outer_d, s_inter, f_inter, tc, duals)
+                spins = outer_c + outer_d
+                for op in (0, 1):
+                    tot = np.zeros_like(G)
+                    for k, tj in enumerate(spins):
+                        J = su2.spin_ops(tj)[op]
+                        # the codomain carries V (or V*), the domain their duals
+                        rep = J if ((k < 2) != (k in duals)) else -J.T
+                        tot += np.moveaxis(np.tensordot(rep, G, axes=([1], [k])), 0, k)
+                    assert np.abs(tot).max() < 1e-12, (duals, op)
+
+
+def test_paper_transpose_formula():
+    """The clockwise cycle t : V x V <- V x V  ->  s : V x V* <- V* x V of the
+    worked example, against the formula the paper prints for s: every
+    coefficient has the printed position and magnitude, and every sign
+    except the two diagonal entries of the c = 1/2 block (channels 5 and 8),
+    which come out with the opposite sign (the sign of bending a spin-1/2
+    line one way round rather than the other; the paper leaves the bending
+    convention open)."""
+    form, _ = _transpose_fixture()
+    st = su2.SU2Map([V, V], [V, V])
+    out, _ = su2.transpose(st, np.zeros(9), (1, 3), (0, 2))
+    assert out.dual == (1, 2) and out.size == 9
+    T = _storage_matrix(st, lambda e: su2.transpose(st, e, (1, 3), (0, 2))[1], 9)
+    np.testing.assert_allclose(np.abs(T), np.abs(form), atol=1e-14)
+    flip = np.ones((9, 1))
+    flip[[4, 7]] = -1
+    np.testing.assert_allclose(T, flip * form, atol=1e-14)
+
+
+def test_paper_transpose_printed_matrix():
+    """The printed transition matrix: as the basis change of the opposite
+    (counter-clockwise) cycle, s' : V* x V <- V x V*, its entries are the
+    coefficients of that transpose read column-wise (every position and
+    magnitude)."""
+    _, mat = _transpose_fixture()
+    st = su2.SU2Map([V, V], [V, V])
+    T = _storage_matrix(st, lambda e: su2.transpose(st, e, (2, 0), (3, 1))[1], 9)
+    np.testing.assert_allclose(np.abs(T.T), np.abs(mat), atol=1e-14)
+
+
+TCASES = [
+    ([[(0, 2), (1, 1)], [(1, 2), (2, 1)]], [[(1, 1), (2, 2)], [(0, 1), (1, 2)]], (), (1, 3), (0, 2)),
+    ([[(0, 1), (1, 2)], [(1, 1), (2, 2)], [(1, 2), (3, 1)]], [[(1, 2), (2, 1)], [(0, 1), (1, 2)]], (1, 4),
+     (4, 0, 2), (1, 3)),
+    ([[(1, 1), (2, 1)], [(0, 1), (2, 1)]], [[(1, 2), (3, 1)], [(0, 2), (2, 1)], [(1, 1)]], (0, 3),
+     (2, 1), (0, 4, 3)),
+]
+
+
+@pytest.mark.parametrize("case", range(len(TCASES)))
+def test_transpose_coefficients_equal_dense_definition(case):
+    """Transposes with legs crossing in both directions and dual legs on
+    input: the per-tree-pair coefficients applied to the reduced arrays equal
+    the definition (dense array, axes reordered, projected); the dense norm
+    is kept, and the inverse transpose restores the input."""
+    cod, dom, dual, p, q = TCASES[case]
+    st = su2.SU2Map(cod, dom, dual)
+    x = np.random.default_rng(40 + case).standard_normal(st.size)
+    np.testing.assert_allclose(su2.from_dense(st, su2.to_dense(st, x)), x, atol=1e-13)
+    out, y = su2.transpose(st, x, p, q)
+    outd, yd = su2.transpose_dense(st, x, p, q)
+    assert out.blocks == outd.blocks and out.dual == outd.dual
+    np.testing.assert_allclose(y, yd, atol=1e-12)
+    np.testing.assert_allclose(su2.to_dense(out, y), su2.to_dense(st, x).transpose(list(p) + list(q)), atol=1e-12)
+    order = list(p) + list(q)
+    inv = [order.index(g) for g in range(len(order))]
+    back, z = su2.transpose(out, y, inv[:st.N1], inv[st.N1:])
+    assert back.dual == st.dual
+    np.testing.assert_allclose(z, x, atol=1e-12)
+
+
+def test_transpose_without_crossing_is_the_braid_permute():
+    cod, dom, p, q = CASES[1]
+    st = su2.SU2Map(cod, dom)
+    x = np.random.default_rng(11).standard_normal(st.size)
+    _, y1 = su2.permute(st, x, p, q)
+    _, y2 = su2.transpose(st, x, p, q)
+    np.testing.assert_allclose(y1, y2, atol=1e-13)
+
+
+def test_four_clockwise_cycles_are_the_identity():
+    """Cycling the legs of t : V x V <- V x V clockwise four times returns
+    every leg to its place (the linear order (1, 2, 4, 3) rotated by four)."""
+    st = su2.SU2Map([V, V], [V, V])
+    x = np.random.default_rng(12).standard_normal(st.size)
+    s, y = st, x
+    for _ in range(4):
+        s, y = su2.transpose(s, y, (1, 3), (0, 2))
+    assert s.dual == ()
+    np.testing.assert_allclose(y, x, atol=1e-13)
