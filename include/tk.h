@@ -409,10 +409,20 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int
  * The trees of one c are ordered by outer sectors (colex, first leg
  * fastest), then by intermediates e_2..e_{N-1} (colex, e_2 fastest).
  *
- * permute(A, (p, q)): output codomain leg k is input leg p[k] (p permutes
- * 0..n1-1), output domain leg k is input leg q[k] (q permutes
- * n1..n1+n2-1).  Moving legs between codomain and domain is not supported
- * (TK_ERR_INVALID_ARG).
+ * permute(A, (p, q)): output codomain leg k is input leg p[k], output
+ * domain leg k is input leg q[k]; (p, q) lists every input leg once.  Legs
+ * may move between codomain and domain (the transposes and general
+ * permutes of the section on index manipulations): a leg that changes
+ * sides carries the dual of its space.  A leg over a dual space keeps the
+ * spins of its sectors (SU(2) irreps are self-dual) and its canonical trees
+ * carry the isomorphism Z between V_j* and V_j on the outer line (section
+ * "Duality Fusion Tree Manipulations"), here Z mapping the dual basis
+ * vector of m to (-1)^(j-m) times the vector of -m.  Coefficients of braids
+ * within each side come from F- and R-moves; when a leg crosses (or a leg is
+ * dual) each coefficient is the overlap of the output tree pair with the
+ * input tree pair with its legs reordered, summed over magnetic quantum
+ * numbers with Clebsch-Gordan vertices (bends act on components as the
+ * identity, pairing a basis with its dual basis).
  *
  * tk_su2_plan_create: builds both structures and the coefficient table on
  *   the host and copies the device tables to the current HIP device (the
@@ -437,6 +447,17 @@ tk_status tk_batch_set_tile(tk_batch* batch, int32_t tile_m, int32_t tile_n, int
 typedef struct tk_su2_plan tk_su2_plan;
 tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
                              const int32_t* p, const int32_t* q, tk_su2_plan** out);
+/* As tk_su2_plan_create, with isdual[l] != 0 for input legs over dual
+ * spaces (NULL: none) and an output of np codomain legs p[0..np-1] and nq
+ * domain legs q[0..nq-1] (np, nq >= 1, np + nq = n1 + n2).
+ * tk_su2_plan_create(n1, n2, .., p, q, out) is this call with isdual NULL,
+ * np = n1 and nq = n2. */
+tk_status tk_su2_plan_create_dual(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj,
+                                  const int64_t* deg, const int32_t* isdual, const int32_t* p, int32_t np,
+                                  const int32_t* q, int32_t nq, tk_su2_plan** out);
+/* The output's leg counts and, per output leg, whether it is over a dual
+ * space (n1 + n2 values; any pointer may be NULL).  Host only. */
+tk_status tk_su2_plan_legs(const tk_su2_plan* plan, int32_t* n1, int32_t* n2, int32_t* isdual);
 tk_status tk_su2_plan_info(const tk_su2_plan* plan, int64_t* in_size, int64_t* out_size, int64_t* ncontrib);
 tk_status tk_su2_plan_contribs(const tk_su2_plan* plan, int64_t cap, int64_t* dst, int64_t* src, double* coef);
 tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* C, double alpha, double beta,

@@ -1280,6 +1280,7 @@ double swap_coeff(int e, int a, int b, int g, int f, int f2) {
 struct Leg {
   std::vector<int> tj;
   std::vector<int64_t> deg;
+  bool dual = false;  // the leg carries the dual space (Z on its outer line)
 };
 
 struct Tree {
@@ -1419,14 +1420,112 @@ struct Plan {
   std::vector<int64_t> tab_dst, tab_src;
   DevBuf d_contribs;
   int device = -1;
+  bool gather = true;  // every output array's inputs share their strides
 };
+
+// Contributions by output tree pair (coupled spin, row tree, column tree):
+// the input array (first element) with its strides in output leg order and
+// the coefficient.
+using Contribs = std::map<std::tuple<int, int, int>, std::vector<std::pair<tk::TraceContrib, int64_t>>>;
+
+// Clebsch-Gordan coefficient <j1 m1, j2 m2 | J M> with Condon-Shortley
+// phases (all arguments twice their value), by Racah's closed formula.
+double cgc(int j1, int m1, int j2, int m2, int J, int M) {
+  if (m1 + m2 != M || !triangle(j1, j2, J) || std::abs(m1) > j1 || std::abs(m2) > j2 || std::abs(M) > J) return 0.0;
+  if (((j1 + m1) & 1) || ((j2 + m2) & 1) || ((J + M) & 1)) return 0.0;
+  const long double pre = (J + 1) * fact_half(J + j1 - j2) * fact_half(J - j1 + j2) * fact_half(j1 + j2 - J) /
+                          fact_half(j1 + j2 + J + 2) * fact_half(J + M) * fact_half(J - M) * fact_half(j1 - m1) *
+                          fact_half(j1 + m1) * fact_half(j2 - m2) * fact_half(j2 + m2);
+  long double sum = 0.0L;
+  for (int k = 0; k <= j1 + j2; k += 2) {
+    const int a[5] = {j1 + j2 - J - k, j1 - m1 - k, j2 + m2 - k, J - j2 + m1 + k, J - j1 - m2 + k};
+    if (*std::min_element(a, a + 5) < 0) continue;
+    long double den = fact_half(k);
+    for (int x : a) den *= fact_half(x);
+    sum += ((k / 2) & 1) ? -1.0L / den : 1.0L / den;
+  }
+  return static_cast<double>(std::sqrt(pre) * sum);
+}
+
+// Dense canonical splitting tree of outer spins o_1..o_N with e_1 = o_1,
+// .., e_N = c: X[m_1, .., m_N, m_c] flat, first index fastest, index i of a
+// spin j standing for m = j - i.
+std::vector<double> tree_dense(const std::vector<int>& outer, const std::vector<int>& e) {
+  const int N = static_cast<int>(outer.size());
+  std::vector<double> T(static_cast<size_t>((outer[0] + 1) * (outer[0] + 1)), 0.0);
+  for (int i = 0; i <= outer[0]; ++i) T[i + (outer[0] + 1) * i] = 1.0;  // [m_1, e_1]
+  int64_t lead = outer[0] + 1;                                          // product of the outer dims so far
+  for (int k = 1; k < N; ++k) {
+    const int a = e[k - 1], b = outer[k], c = e[k];
+    std::vector<double> U(static_cast<size_t>(lead * (b + 1) * (c + 1)), 0.0);
+    for (int ie = 0; ie <= a; ++ie)
+      for (int ib = 0; ib <= b; ++ib)
+        for (int ic = 0; ic <= c; ++ic) {
+          const double w = cgc(a, a - 2 * ie, b, b - 2 * ib, c, c - 2 * ic);
+          if (w == 0.0) continue;
+          const double* src = T.data() + static_cast<int64_t>(ie) * lead;
+          double* dst = U.data() + (static_cast<int64_t>(ic) * (b + 1) + ib) * lead;
+          for (int64_t x = 0; x < lead; ++x) dst[x] += w * src[x];
+        }
+    T.swap(U);
+    lead *= b + 1;
+  }
+  return T;
+}
+
+// Dense tree pair X_s X_f^T summed over m_c: flat over the codomain then the
+// domain legs (first fastest), with the isomorphism Z on dual legs: along
+// such a leg entry i is (-1)^i times entry d - 1 - i (m goes to -m).
+std::vector<double> pair_dense(const std::vector<int>& co, const std::vector<int>& es, const std::vector<int>& dout,
+                               const std::vector<int>& ef, const std::vector<char>& dual) {
+  const std::vector<double> X = tree_dense(co, es), Y = tree_dense(dout, ef);
+  const int c = es.back();
+  int64_t nr = 1, nc = 1;
+  for (int x : co) nr *= x + 1;
+  for (int x : dout) nc *= x + 1;
+  std::vector<double> G(static_cast<size_t>(nr * nc), 0.0);
+  for (int mc = 0; mc <= c; ++mc)
+    for (int64_t j = 0; j < nc; ++j) {
+      const double y = Y[j + nc * mc];
+      if (y == 0.0) continue;
+      for (int64_t i = 0; i < nr; ++i) G[i + nr * j] += X[i + nr * mc] * y;
+    }
+  std::vector<int> dims(co);
+  dims.insert(dims.end(), dout.begin(), dout.end());
+  int64_t stride = 1;
+  for (size_t l = 0; l < dims.size(); ++l) {
+    const int64_t d = dims[l] + 1;
+    if (dual[l]) {
+      std::vector<double> H(G.size());
+      for (int64_t x = 0; x < static_cast<int64_t>(G.size()); ++x) {
+        const int64_t i = (x / stride) % d, inew = d - 1 - i;
+        H[x + (inew - i) * stride] = (inew & 1) ? -G[x] : G[x];
+      }
+      G.swap(H);
+    }
+    stride *= d;
+  }
+  return G;
+}
 
 // Elements per recoupling task: one pass of the gather kernel's 256-thread
 // workgroup at 8 elements per thread (1024 and 4096 measured slower on the
 // spin-1 two-site swap).
 constexpr int64_t kSu2Chunk = 2048;
 
-void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q) {
+// Strides of the reduced array of tree t (legs of one side, first fastest),
+// starting at base.
+void tree_strides(const std::vector<Leg>& legs, const Tree& t, int64_t base, int64_t* out) {
+  int64_t st = base;
+  for (size_t k = 0; k < legs.size(); ++k) {
+    out[k] = st;
+    st *= legs[k].deg[t.sec[k]];
+  }
+}
+
+// Contributions of a braid within each side: the coefficient of a pair is
+// the product of its two trees' coefficients.
+Contribs braid_contribs(const Plan& P, const std::vector<int>& p, const std::vector<int>& q) {
   const Map& A = P.A;
   const Map& C = P.C;
   const int N1 = static_cast<int>(A.cod.size()), N2 = static_cast<int>(A.dom.size()), n = N1 + N2;
@@ -1455,14 +1554,7 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
   };
   const auto rmap = side_map(A.cod, A.rows, C.rows, p);
   const auto cmap = side_map(A.dom, A.cols, C.cols, qd);
-  auto strides = [](const std::vector<Leg>& legs, const Tree& t, int64_t base, int64_t* out) {
-    int64_t st = base;
-    for (size_t k = 0; k < legs.size(); ++k) {
-      out[k] = st;
-      st *= legs[k].deg[t.sec[k]];
-    }
-  };
-  std::map<std::tuple<int, int, int>, std::vector<std::pair<tk::TraceContrib, int64_t>>> by_out;
+  Contribs by_out;
   for (const auto& [c, blk] : A.blocks) {
     const int64_t off = blk[0], R = blk[1];
     const auto& rows = A.rows.by_c.at(c);
@@ -1470,8 +1562,8 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
     for (size_t i = 0; i < rows.size(); ++i)
       for (size_t j = 0; j < cols.size(); ++j) {
         int64_t is[TK_MAX_RANK], js[TK_MAX_RANK];
-        strides(A.cod, rows[i], 1, is);
-        strides(A.dom, cols[j], R, js);
+        tree_strides(A.cod, rows[i], 1, is);
+        tree_strides(A.dom, cols[j], R, js);
         tk::TraceContrib cb{};
         cb.src = off + rows[i].r0 + cols[j].r0 * R;
         cb.nd = 0;
@@ -1483,6 +1575,15 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
           }
       }
   }
+  return by_out;
+}
+
+// Tasks of the gather: one per chunk of every output tree pair, with the
+// contributions that reach it (output pairs with the same outer sectors
+// interleaved, see below).
+void build_tasks(Plan& P, const Contribs& by_out) {
+  const Map& C = P.C;
+  const int N1 = static_cast<int>(C.cod.size()), N2 = static_cast<int>(C.dom.size()), n = N1 + N2;
   // Output pairs with the same outer sectors (they differ only in
   // intermediate spins) read the same input arrays at the same relative
   // offsets; their tasks are interleaved in runs of 8 chunks so that chunk k
@@ -1506,8 +1607,8 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
         groups[g->second].emplace_back();
         auto& mine = groups[g->second].back();
         int64_t os[TK_MAX_RANK], od[TK_MAX_RANK];
-        strides(C.cod, rows[i], 1, os);
-        strides(C.dom, cols[j], R, os + N1);
+        tree_strides(C.cod, rows[i], 1, os);
+        tree_strides(C.dom, cols[j], R, os + N1);
         for (int m = 0; m < N1; ++m) od[m] = C.cod[m].deg[rows[i].sec[m]];
         for (int m = 0; m < N2; ++m) od[N1 + m] = C.dom[m].deg[cols[j].sec[m]];
         const int64_t dst = off + rows[i].r0 + cols[j].r0 * R;
@@ -1515,11 +1616,13 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
         auto it = by_out.find({c, static_cast<int>(i), static_cast<int>(j)});
         if (it != by_out.end())
           for (const auto& [cb, src] : it->second) {
-            // the gather kernel forms one source offset per element: every input
-            // of this output array (same outer sectors, same coupled spin) has
-            // the same strides
-            if (std::memcmp(cb.ss, it->second.front().first.ss, sizeof(cb.ss)) != 0)
-              fail(TK_ERR_INVALID_ARG, "internal: SU(2) inputs of one output differ in strides");
+            // the gather kernel forms one source offset per element, which
+            // needs every input of this output array to have the same
+            // strides (true for braids: same outer sectors, same coupled
+            // spin); a transpose can mix inputs of different coupled spins,
+            // whose domain strides differ: then the plan uses the trace
+            // kernel's per-contribution strides
+            if (std::memcmp(cb.ss, it->second.front().first.ss, sizeof(cb.ss)) != 0) P.gather = false;
             P.contribs.push_back(cb);
             P.tab_dst.push_back(dst);
             P.tab_src.push_back(src);
@@ -1556,6 +1659,118 @@ void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q)
   }
   pack_workgroups(P.tl, kSu2Chunk);
 }
+
+void plan_permute(Plan& P, const std::vector<int>& p, const std::vector<int>& q) {
+  build_tasks(P, braid_contribs(P, p, q));
+}
+
+// Contributions of a transpose (legs may cross between codomain and
+// domain; order = output codomain legs then output domain legs, as input leg
+// numbers): the coefficient of input pair (s, f) in output pair (s', f') is
+// the overlap of the dense form of (s', f') with the dense form of (s, f)
+// whose legs are reordered, divided by d_c' (tree pairs are orthonormal with
+// norm d_c), i.e. the Clebsch-Gordan sum that the bending moves (with the Z
+// isomorphisms on dual legs) and the recoupling moves evaluate.
+Contribs transpose_contribs(const Plan& P, const std::vector<int>& order) {
+  const Map& A = P.A;
+  const Map& C = P.C;
+  const int N1 = static_cast<int>(A.cod.size()), N = N1 + static_cast<int>(A.dom.size());
+  const int M1 = static_cast<int>(C.cod.size());
+  std::vector<const Leg*> in(N), outl(N);
+  for (int k = 0; k < N; ++k) in[k] = k < N1 ? &A.cod[k] : &A.dom[k - N1];
+  for (int k = 0; k < N; ++k) outl[k] = k < M1 ? &C.cod[k] : &C.dom[k - M1];
+  std::vector<char> din(N), dout(N);
+  for (int k = 0; k < N; ++k) {
+    din[k] = in[k]->dual;
+    dout[k] = outl[k]->dual;
+  }
+  std::map<std::vector<int>, std::vector<double>> out_dense;  // (outer sectors, e's) -> dense output pair
+  Contribs by_out;
+  for (const auto& [c, blk] : A.blocks) {
+    const int64_t off = blk[0], R = blk[1];
+    const auto& rows = A.rows.by_c.at(c);
+    const auto& cols = A.cols.by_c.at(c);
+    for (size_t i = 0; i < rows.size(); ++i)
+      for (size_t j = 0; j < cols.size(); ++j) {
+        std::vector<int> sec(N), spin(N);
+        for (int k = 0; k < N; ++k) {
+          sec[k] = k < N1 ? rows[i].sec[k] : cols[j].sec[k - N1];
+          spin[k] = in[k]->tj[sec[k]];
+        }
+        std::vector<int> co(spin.begin(), spin.begin() + N1), dv(spin.begin() + N1, spin.end());
+        const std::vector<double> G = pair_dense(co, rows[i].e, dv, cols[j].e, din);
+        // the input pair with its legs in output order
+        std::vector<int64_t> dim(N), istr(N);
+        int64_t tot = 1;
+        for (int k = 0; k < N; ++k) {
+          dim[k] = spin[k] + 1;
+          istr[k] = tot;
+          tot *= dim[k];
+        }
+        std::vector<double> Gp(G.size());
+        {
+          std::vector<int64_t> ostr(N);
+          int64_t st = 1;
+          for (int m = 0; m < N; ++m) {
+            ostr[order[m]] = st;
+            st *= dim[order[m]];
+          }
+          std::vector<int64_t> idx(N, 0);
+          for (int64_t x = 0; x < tot; ++x) {
+            int64_t y = 0;
+            for (int k = 0; k < N; ++k) y += idx[k] * ostr[k];
+            Gp[y] = G[x];
+            for (int k = 0; k < N; ++k) {
+              if (++idx[k] < dim[k]) break;
+              idx[k] = 0;
+            }
+          }
+        }
+        // output outer sectors and spins
+        std::vector<int> osec(N), ospin(N);
+        for (int m = 0; m < N; ++m) {
+          osec[m] = sec[order[m]];
+          ospin[m] = spin[order[m]];
+        }
+        std::vector<int> osc(osec.begin(), osec.begin() + M1), osd(osec.begin() + M1, osec.end());
+        std::vector<int> oco(ospin.begin(), ospin.begin() + M1), odv(ospin.begin() + M1, ospin.end());
+        // input strides in output leg order
+        int64_t is[TK_MAX_RANK], js[TK_MAX_RANK];
+        tree_strides(A.cod, rows[i], 1, is);
+        tree_strides(A.dom, cols[j], R, js);
+        tk::TraceContrib cb{};
+        cb.src = off + rows[i].r0 + cols[j].r0 * R;
+        cb.nd = 0;
+        for (int m = 0; m < N; ++m) cb.ss[m] = checked_i32(order[m] < N1 ? is[order[m]] : js[order[m] - N1], "stride");
+        for (const auto& [c2, orow] : C.rows.by_c) {
+          auto cit = C.cols.by_c.find(c2);
+          if (cit == C.cols.by_c.end() || !C.blocks.count(c2)) continue;
+          for (size_t si = 0; si < orow.size(); ++si) {
+            if (orow[si].sec != osc) continue;
+            for (size_t fj = 0; fj < cit->second.size(); ++fj) {
+              const Tree& ft = cit->second[fj];
+              if (ft.sec != osd) continue;
+              std::vector<int> key(osec);
+              key.insert(key.end(), orow[si].e.begin(), orow[si].e.end());
+              key.insert(key.end(), ft.e.begin(), ft.e.end());
+              auto hit = out_dense.find(key);
+              if (hit == out_dense.end()) hit = out_dense.emplace(key, pair_dense(oco, orow[si].e, odv, ft.e, dout)).first;
+              const std::vector<double>& H = hit->second;
+              double v = 0.0;
+              for (size_t x = 0; x < H.size(); ++x) v += H[x] * Gp[x];
+              v /= (c2 + 1);
+              if (std::fabs(v) < 1e-13) continue;
+              cb.coef = v;
+              by_out[{c2, static_cast<int>(si), static_cast<int>(fj)}].emplace_back(cb, cb.src);
+            }
+          }
+        }
+      }
+  }
+  return by_out;
+}
+
+void plan_transpose(Plan& P, const std::vector<int>& order) { build_tasks(P, transpose_contribs(P, order)); }
 
 }  // namespace su2
 
@@ -3627,18 +3842,22 @@ struct tk_su2_plan {
   su2::Plan P;
 };
 
-tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
-                             const int32_t* p, const int32_t* q, tk_su2_plan** out) {
+tk_status tk_su2_plan_create_dual(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj,
+                                  const int64_t* deg, const int32_t* isdual, const int32_t* p, int32_t np,
+                                  const int32_t* q, int32_t nq, tk_su2_plan** out) {
   return guarded([&] {
     if (!out || !nsec || !twoj || !deg || !p || !q) fail(TK_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
     if (n1 < 1 || n2 < 1) fail(TK_ERR_INVALID_ARG, "codomain and domain need at least one leg each");
     if (n1 + n2 > tk::kMaxDims) fail(TK_ERR_UNSUPPORTED, "more than 8 legs");
+    if (np < 1 || nq < 1 || np + nq != n1 + n2) fail(TK_ERR_INVALID_ARG, "p and q must split the legs, both non-empty");
     auto plan = std::make_unique<tk_su2_plan>();
+    std::vector<su2::Leg> legs;
     int64_t k = 0;
     for (int l = 0; l < n1 + n2; ++l) {
       if (nsec[l] < 1 || nsec[l] > 64) fail(TK_ERR_INVALID_ARG, "a leg needs 1..64 sectors");
       su2::Leg leg;
+      leg.dual = isdual && isdual[l] != 0;
       for (int i = 0; i < nsec[l]; ++i, ++k) {
         if (twoj[k] < 0 || twoj[k] > 64) fail(TK_ERR_CHARGE, "spin (twice its value) outside 0..64");
         if (i > 0 && twoj[k] <= leg.tj.back()) fail(TK_ERR_CHARGE, "spins of a leg must be strictly ascending");
@@ -3646,18 +3865,31 @@ tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const 
         leg.tj.push_back(twoj[k]);
         leg.deg.push_back(deg[k]);
       }
+      legs.push_back(leg);
       (l < n1 ? plan->P.A.cod : plan->P.A.dom).push_back(std::move(leg));
     }
-    std::vector<int> pv(p, p + n1), qv(q, q + n2), seen(n1 + n2, 0);
-    for (int x : pv)
-      if (x < 0 || x >= n1 || seen[x]++) fail(TK_ERR_INVALID_ARG, "p must permute the codomain legs 0..n1-1");
-    for (int x : qv)
-      if (x < n1 || x >= n1 + n2 || seen[x]++) fail(TK_ERR_INVALID_ARG, "q must permute the domain legs n1..n1+n2-1");
-    for (int x : pv) plan->P.C.cod.push_back(plan->P.A.cod[x]);
-    for (int x : qv) plan->P.C.dom.push_back(plan->P.A.dom[x - n1]);
+    std::vector<int> order(p, p + np), seen(n1 + n2, 0);
+    order.insert(order.end(), q, q + nq);
+    for (int x : order)
+      if (x < 0 || x >= n1 + n2 || seen[x]++) fail(TK_ERR_INVALID_ARG, "(p, q) must list every leg once");
+    bool crossing = false;
+    for (int m = 0; m < n1 + n2; ++m) {
+      su2::Leg leg = legs[order[m]];
+      const bool crossed = (order[m] < n1) != (m < np);
+      crossing = crossing || crossed;
+      leg.dual = leg.dual != crossed;  // a leg changing sides turns into the dual space
+      (m < np ? plan->P.C.cod : plan->P.C.dom).push_back(std::move(leg));
+    }
     plan->P.A.build();
     plan->P.C.build();
-    su2::plan_permute(plan->P, pv, qv);
+    bool anydual = false;
+    for (const auto& l : legs) anydual = anydual || l.dual;
+    if (crossing || anydual) {
+      su2::plan_transpose(plan->P, order);
+    } else {
+      std::vector<int> pv(p, p + np), qv(q, q + nq);
+      su2::plan_permute(plan->P, pv, qv);
+    }
     // device tables go to the current device now, so launches allocate
     // nothing (and may be captured); without a device the plan is host only
     int ndev = 0;
@@ -3671,6 +3903,25 @@ tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const 
       (void)hipGetLastError();
     }
     *out = plan.release();
+  });
+}
+
+tk_status tk_su2_plan_create(int32_t n1, int32_t n2, const int32_t* nsec, const int32_t* twoj, const int64_t* deg,
+                             const int32_t* p, const int32_t* q, tk_su2_plan** out) {
+  return tk_su2_plan_create_dual(n1, n2, nsec, twoj, deg, nullptr, p, n1, q, n2, out);
+}
+
+tk_status tk_su2_plan_legs(const tk_su2_plan* plan, int32_t* n1, int32_t* n2, int32_t* isdual) {
+  return guarded([&] {
+    if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
+    const auto& C = plan->P.C;
+    if (n1) *n1 = static_cast<int32_t>(C.cod.size());
+    if (n2) *n2 = static_cast<int32_t>(C.dom.size());
+    if (isdual) {
+      int k = 0;
+      for (const auto& l : C.cod) isdual[k++] = l.dual;
+      for (const auto& l : C.dom) isdual[k++] = l.dual;
+    }
   });
 }
 
@@ -3714,7 +3965,7 @@ tk_status tk_su2_permute(tk_su2_plan* plan, int32_t dtype, const void* A, void* 
     ptrs.p[tk::kBufC] = C;
     hip_check(tk::launch_trace(dtype, static_cast<const tk::TraceTask*>(P.tl.d_tasks.p),
                                static_cast<const int32_t*>(P.tl.d_wg.p), P.tl.nwg(),
-                               static_cast<const tk::TraceContrib*>(P.d_contribs.p), ptrs, alpha, beta, true,
+                               static_cast<const tk::TraceContrib*>(P.d_contribs.p), ptrs, alpha, beta, P.gather,
                                static_cast<hipStream_t>(stream)),
               "SU(2) permute launch");
   });

@@ -98,6 +98,9 @@ _SIGS = {
     "tk_tile_shapes": [_I32P, _I32P],
     "tk_plan_set_tile": [_P, C.c_int32, C.c_int32, C.c_int32],
     "tk_su2_plan_create": [C.c_int32, C.c_int32, _I32P, _I32P, _I64P, _I32P, _I32P, C.POINTER(_P)],
+    "tk_su2_plan_create_dual": [C.c_int32, C.c_int32, _I32P, _I32P, _I64P, _I32P, _I32P, C.c_int32, _I32P,
+                                C.c_int32, C.POINTER(_P)],
+    "tk_su2_plan_legs": [_P, _I32P, _I32P, _I32P],
     "tk_su2_plan_info": [_P, _I64P, _I64P, _I64P],
     "tk_su2_plan_contribs": [_P, C.c_int64, _I64P, _I64P, C.POINTER(C.c_double)],
     "tk_su2_permute": [_P, C.c_int32, _P, _P, C.c_double, C.c_double, _P],
@@ -378,17 +381,23 @@ class SU2Plan:
     lists of (twice the spin, degeneracy); p and q permute the codomain and
     the domain legs (numbered as in tk_su2_plan_create)."""
 
-    def __init__(self, cod, dom, p, q):
+    def __init__(self, cod, dom, p, q, dual=()):
         legs = [sorted(l) for l in list(cod) + list(dom)]
         nsec, nl = _ilist([len(l) for l in legs])
         tj, _ = _ilist([x for l in legs for x, _ in l])
         deg = (C.c_int64 * max(1, sum(len(l) for l in legs)))(*[d for l in legs for _, d in l])
+        isd, _ = _ilist([1 if k in set(dual) else 0 for k in range(len(legs))])
         (pa, npa), (qa, nqa) = _ilist(p), _ilist(q)
         self.h = C.c_void_p()
-        _check(lib.tk_su2_plan_create(len(cod), len(dom), nsec, tj, deg, pa, qa, C.byref(self.h)))
+        _check(lib.tk_su2_plan_create_dual(len(cod), len(dom), nsec, tj, deg, isd, pa, npa, qa, nqa,
+                                           C.byref(self.h)))
         a, b, n = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib.tk_su2_plan_info(self.h, C.byref(a), C.byref(b), C.byref(n)))
         self.in_size, self.out_size, self.ncontrib = a.value, b.value, n.value
+        o1, o2 = C.c_int32(), C.c_int32()
+        od = (C.c_int32 * len(legs))()
+        _check(lib.tk_su2_plan_legs(self.h, C.byref(o1), C.byref(o2), od))
+        self.out_dual = tuple(k for k in range(len(legs)) if od[k])
 
     def contribs(self):
         """Host table: (output array start, input array start, coefficient)."""

@@ -309,7 +309,7 @@ def test_su2_coefficients_match_oracle(case):
 def test_su2_error_paths():
     V = [(0, 1), (1, 1)]
     with pytest.raises(tk.TkError) as e:
-        tk.SU2Plan([V, V], [V, V], [0, 2], [1, 3])  # a leg would change sides
+        tk.SU2Plan([V, V], [V, V], [0, 2], [1, 2])  # a leg listed twice, one missing
     assert e.value.status == 1
     with pytest.raises(tk.TkError) as e:
         tk.SU2Plan([V, V], [V, V], [0, 0], [2, 3])
@@ -325,3 +325,48 @@ def test_su2_error_paths():
     assert e.value.status == 5
     plan = tk.SU2Plan([[(1, 1)]], [[(0, 1)]], [0], [1])  # no common coupled spin
     assert plan.in_size == 0 and plan.out_size == 0 and plan.ncontrib == 0
+
+
+def _su2_oracle_transpose_table(st, p, q):
+    """As _su2_oracle_table, for the oracle's transpose (legs may cross)."""
+    from oracle import su2
+    res = {}
+    for tc, s, f in st.pairs():
+        off, R, _ = st.blocks[tc]
+        src = off + s[2] + f[2] * R
+        e = np.zeros(st.size)
+        e[src] = 1.0
+        _, y = su2.transpose(st, e, p, q)
+        for i in np.nonzero(np.abs(y) > 1e-14)[0]:
+            res[(int(i), src)] = y[i]
+    return res
+
+
+SU2_TRANSPOSE_CASES = [
+    ([[(0, 1), (1, 1)]] * 2, [[(0, 1), (1, 1)]] * 2, (), [1, 3], [0, 2]),   # the worked transposition
+    ([[(0, 1), (1, 1)]] * 2, [[(0, 1), (1, 1)]] * 2, (), [2, 0], [3, 1]),
+    ([[(0, 2), (1, 1)], [(1, 2), (2, 1)]], [[(1, 1), (2, 2)], [(0, 1), (1, 2)]], (1,), [1, 3, 0], [2]),
+    ([[(0, 1), (1, 2)], [(1, 1), (2, 2)], [(1, 2), (3, 1)]], [[(1, 2), (2, 1)], [(0, 1), (1, 2)]], (1, 4),
+     [4, 0, 2], [1, 3]),
+    ([[(2, 2), (4, 1)], [(2, 1)], [(2, 1)]], [[(0, 1), (2, 2), (4, 1)]], (), [0, 1], [3, 2]),
+]
+
+
+@pytest.mark.parametrize("case", range(len(SU2_TRANSPOSE_CASES)))
+def test_su2_transpose_coefficients_match_oracle(case):
+    """Transposes (legs crossing, dual legs): the library's Clebsch-Gordan
+    overlaps against the oracle's per-tree-pair projections, coefficient by
+    coefficient, and the output's dual legs."""
+    from oracle import su2
+    cod, dom, dual, p, q = SU2_TRANSPOSE_CASES[case]
+    st = su2.SU2Map(cod, dom, dual)
+    out = su2.transpose_legs(st, p, q)
+    plan = tk.SU2Plan(cod, dom, p, q, dual=dual)
+    assert plan.in_size == st.size and plan.out_size == out.size
+    assert plan.out_dual == out.dual
+    got = {}
+    for d, s, c in plan.contribs():
+        got[(d, s)] = got.get((d, s), 0.0) + c
+    want = _su2_oracle_transpose_table(st, p, q)
+    assert set(got) == set(want)
+    assert max(abs(got[k] - want[k]) for k in want) < 1e-13
