@@ -34,26 +34,40 @@ def _run(cmd, verbose):
         print(out)
 
 
-def build(verbose: bool = False) -> str:
+# host-side sanitizers for the planner (tk_host.cpp): every flag applies to
+# the host compilation only, device code is built as usual
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+            "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+LIB_SANITIZED = os.path.join(HERE, "libtk_asan.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compiles libtk.so; with sanitize=True, libtk_asan.so instead, whose
+    planner is built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (load it with TK_LIBRARY=<path> and the sanitizer runtime preloaded, see
+    DESIGN.md)."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
     objs, cmds = [], []
+    tag = ".asan" if sanitize else ""
     for src in ("tk_host.cpp", "tk_kernels.hip"):
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(BUILD, src + tag + ".o")
         cmd = [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC] + COMMON + ["-x", "hip"] + DEVICE + (SANITIZE + ["-g"] if sanitize else []) + \
+                  ["-c", os.path.join(CSRC, src), "-o", obj]
         cmds.append(cmd)
         objs.append(obj)
     # the two translation units compile side by side
     with ThreadPoolExecutor(len(cmds)) as pool:
         for f in [pool.submit(_run, c, verbose) for c in cmds]:
             f.result()
-    tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    lib = LIB_SANITIZED if sanitize else LIB
+    tmp = lib + ".tmp"
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs + (SANITIZE if sanitize else []), verbose)
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

@@ -145,7 +145,7 @@ struct Side {
     if (!lookup_built) {
       for (const auto& kv : groups) {
         const Group& gr = kv.second;
-        for (int32_t i = 0; i < gr.n(); ++i) lookup[pack(&gr.idx[size_t(i) * nlegs], nlegs)] = i;
+        for (int32_t i = 0; i < gr.n(); ++i) lookup[pack(gr.idx.data() + size_t(i) * nlegs, nlegs)] = i;
       }
       lookup_built = true;
     }
@@ -2235,10 +2235,10 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
       d.K = checked_i32(K, "K");
       d.lda = d.M;
       d.ldb = d.K;
-      // the GEMM kernels address a stage of B with 32-bit byte offsets of a
-      // few columns (at most 3 * ldb + 64 elements)
-      if (K > kSmallK && K >= (int64_t(1) << 26))
-        fail(TK_ERR_UNSUPPORTED, "contracted dimension of one coupled sector above 2^26");
+      // the GEMM kernels address one stage of A (up to 32 rows of M) and of B
+      // (up to 128 columns of K) with 32-bit byte offsets
+      if (K > kSmallK && (M >= (int64_t(1) << 23) || K >= (int64_t(1) << 21)))
+        fail(TK_ERR_UNSUPPORTED, "MFMA sector GEMM with M >= 2^23 or K >= 2^21");
       d.a_buf = abuf;
       d.b_buf = bbuf;
       P->flops += 2.0 * double(M) * double(N) * double(K);
@@ -2431,7 +2431,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
         d.ncc = cg.n();
         // row maps: every row of the sector -> (channel, leg indices)
         for (int32_t i = 0; i < rg.n(); ++i) {
-          const uint8_t* t = &rg.idx[size_t(i) * Ct.N1()];
+          const uint8_t* t = rg.idx.data() + size_t(i) * Ct.N1();
           for (int64_t r = 0; r < rg.size[i]; ++r) {
             LegMap lm{};
             lm.chan = i;
@@ -2445,7 +2445,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
           }
         }
         for (int32_t j = 0; j < cg.n(); ++j) {
-          const uint8_t* t = &cg.idx[size_t(j) * Ct.N2()];
+          const uint8_t* t = cg.idx.data() + size_t(j) * Ct.N2();
           for (int64_t c = 0; c < cg.size[j]; ++c) {
             LegMap lm{};
             lm.chan = j;

@@ -834,15 +834,20 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
   // record count is the number of valid m of that run, or zero past the K
   // range.  B: each instruction reads 64/BK columns of BK consecutive k;
   // invalid lanes get an out-of-range offset.
-  // load cursor: tile, stage, stage count and K range of the tile, operand
-  // bases and strides (wave-uniform, kept in scalar registers), plus the
-  // lane's B offset and column validity
+  // load cursor: tile, stage, stage count and K range of the tile; one
+  // resource per operand and stage whose base advances by a whole stage
+  // (wave-uniform, scalar registers), and per lane the byte offset of each
+  // of its loads inside a stage, fixed for the tile (0x80000000: the lane's
+  // row or column lies past M or N, the load reads zero).  A's record count
+  // ends at the tile's K range, so its rows past K read zero; B's loads past
+  // the K range get the invalid offset.  The offsets stay below
+  // BK * lda * 8 and BN * ldb * 8 < 2^31 (the planner checks).
   int l_t = 0, l_s = 0, l_ns = 0, l_k0 = 0, l_kend = 0;
-  const char* a_base = nullptr;
-  const char* b_base = nullptr;
-  int64_t lda8 = 0, ldb8 = 0;
-  uint32_t a_recs = 0, b_off = 0;
-  bool b_nok[B_LDK];
+  const char* a_stage = nullptr;
+  const char* b_stage = nullptr;
+  int64_t a_adv = 0;  // bytes between two stages of A (BK rows)
+  int64_t lda8 = 0;
+  uint32_t a_voff[A_LD], b_voff[B_LDK];
   auto uni = [](int x) { return __builtin_amdgcn_readfirstlane(x); };
   auto uni64 = [](int64_t x) {
     const uint64_t u = static_cast<uint64_t>(x);
@@ -865,35 +870,40 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
     l_k0 = uni(tile.k0);
     l_kend = uni(tile.k1);
     lda8 = uni64(static_cast<int64_t>(d.lda) * ES);
-    ldb8 = uni64(static_cast<int64_t>(d.ldb) * ES);
-    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a + tile.m0 + a_m0;
+    a_adv = uni64(static_cast<int64_t>(d.lda) * ES * BK);
+    const TK_GLOBAL TS* A = buf_ptr<const TS>(args.ptrs, d.a_buf) + d.a + tile.m0 + a_m0 +
+                            static_cast<int64_t>(tile.k0 + a_k) * d.lda;
     const TK_GLOBAL TS* B =
-        buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b + static_cast<int64_t>(tile.n0 + b_c0) * d.ldb;
-    a_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)A)));
-    b_base = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)B)));
-    a_recs = static_cast<uint32_t>(uni(max(0, min(64, d.M - tile.m0 - a_m0)) * ES));
-    b_off = static_cast<uint32_t>((static_cast<int64_t>(b_cl) * d.ldb + b_k) * ES);
+        buf_ptr<const TS>(args.ptrs, d.b_buf) + d.b + static_cast<int64_t>(tile.n0 + b_c0) * d.ldb + tile.k0;
+    a_stage = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)A)));
+    b_stage = reinterpret_cast<const char*>(uni64(reinterpret_cast<int64_t>((const TS*)B)));
+    const bool m_ok = lane < d.M - tile.m0 - a_m0;
 #pragma unroll
-    for (int i = 0; i < B_LDK; ++i) b_nok[i] = tile.n0 + b_c0 + B_NPL * i + b_cl < d.N;
+    for (int i = 0; i < A_LD; ++i)
+      a_voff[i] = m_ok ? static_cast<uint32_t>((A_TPM * i * d.lda + lane) * ES) : 0x80000000u;
+#pragma unroll
+    for (int i = 0; i < B_LDK; ++i)
+      b_voff[i] = tile.n0 + b_c0 + B_NPL * i + b_cl < d.N
+                      ? static_cast<uint32_t>(((B_NPL * i + b_cl) * d.ldb + b_k) * ES)
+                      : 0x80000000u;
   };
   TS ra[PF][A_LD], rb[PF][B_LDK];
   // loads the load cursor's stage into ring slot `slot` and advances it
   auto gload_next = [&](int slot) {
     const int k0 = l_k0 + l_s * BK;
+    // A rows k0 + a_k + A_TPM i of the K range lie below the record count
+    const int64_t rem = static_cast<int64_t>(l_kend - k0 - a_k) * lda8;
+    const uint32_t recs = rem <= 0 ? 0u : rem >= 0x7fffffff ? 0x7fffffffu : static_cast<uint32_t>(rem);
+    const __amdgpu_buffer_rsrc_t r_a = __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(a_stage), 0, recs, kBufWord3);
 #pragma unroll
-    for (int i = 0; i < A_LD; ++i) {
-      const int k = k0 + a_k + A_TPM * i;
-      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(a_base + k * lda8), 0, k < l_kend ? a_recs : 0u, kBufWord3);
-      ra[slot][i] = buffer_load<TS>(r, lane * ES);
-    }
+    for (int i = 0; i < A_LD; ++i) ra[slot][i] = buffer_load<TS>(r_a, a_voff[i]);
     const bool k_ok = k0 + b_k < l_kend;
+    const __amdgpu_buffer_rsrc_t r_b =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(b_stage), 0, 0x7fffffff, kBufWord3);
 #pragma unroll
-    for (int i = 0; i < B_LDK; ++i) {
-      const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-          const_cast<char*>(b_base + B_NPL * i * ldb8 + int64_t(k0) * ES), 0, 0x7fffffff, kBufWord3);
-      rb[slot][i] = buffer_load<TS>(r, (k_ok && b_nok[i]) ? b_off : 0x80000000u);
-    }
+    for (int i = 0; i < B_LDK; ++i) rb[slot][i] = buffer_load<TS>(r_b, k_ok ? b_voff[i] : 0x80000000u);
+    a_stage += a_adv;
+    b_stage += BK * ES;
     if (++l_s == l_ns) load_tile(l_t + 1);
   };
   auto lstore = [&](int slot, int buf) {
@@ -1044,23 +1054,29 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 // out-of-range offset, so both read zero.  The MFMAs take B as the first
 // operand, so the accumulators hold the transposed tile (lane l, value v =
 // C[l % 16][4 (l/16) + v]) and the epilogue of the fp32 stream kernel
-// applies.  LDS rows are padded by 8 bf16 (16 bytes): the 16 rows one
-// 16-lane group reads start 20 banks apart and never share a bank.
+// applies.  LDS rows hold BK = 32 bf16 (64 bytes, four 16-byte chunks)
+// with no padding; chunk c of row r sits at position c ^ ((r >> 1) & 3).
+// Measured with an LDS probe on gfx950 (SQ_LDS_BANK_CONFLICT): both the
+// MFMA operand reads (16 rows, one chunk each) and the staging writes (4
+// rows of 4 chunks per 16 lanes) are then conflict free, where rows padded
+// by 8 bf16 stalled on conflicts for about half of the LDS-active cycles.
 typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+
+// element offset of 16-byte chunk c of row r in the swizzled LDS tile
+__device__ __forceinline__ int swz(int r, int c) { return r * 32 + 8 * (c ^ ((r >> 1) & 3)); }
 
 template <typename TS, int BM, int BN, int WGM, int WGN, int BK, int PF = 2>
 __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs args) {
   using TT = F64Tile<BM, BN, WGM, WGN, BK>;
   constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
-  constexpr int KP = BK + 8;   // padded LDS row of bf16 values
   constexpr int CPR = BK / 8;  // 16-byte chunks of a row per stage
   constexpr int A_CH = BM * CPR, B_CH = BN * CPR;
   constexpr int A_PT = (A_CH + NT - 1) / NT, B_PT = (B_CH + NT - 1) / NT;
-  static_assert(BK % 32 == 0, "bf16 stage depth");
-  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][KP];
+  static_assert(BK == 32, "bf16 stage depth (one 16x16x32 MFMA step, swizzled 64-byte rows)");
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN * BK];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN * BK];
 
   const TK_CONST GemmTile* tiles = const_ptr(args.tiles);
   const TK_CONST GemmDesc* descs = const_ptr(args.descs);
@@ -1163,34 +1179,33 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs
     for (int p = 0; p < A_PT; ++p) {
       const int c = tid + p * NT;
       if (A_CH % NT == 0 || c < A_CH) {
-        *reinterpret_cast<u4_t*>(&Ah[buf][c / CPR][8 * (c % CPR)]) = rah_r[slot][p];
-        *reinterpret_cast<u4_t*>(&Al[buf][c / CPR][8 * (c % CPR)]) = ral_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Ah[buf][swz(c / CPR, c % CPR)]) = rah_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Al[buf][swz(c / CPR, c % CPR)]) = ral_r[slot][p];
       }
     }
 #pragma unroll
     for (int p = 0; p < B_PT; ++p) {
       const int c = tid + p * NT;
       if (B_CH % NT == 0 || c < B_CH) {
-        *reinterpret_cast<u4_t*>(&Bh[buf][c / CPR][8 * (c % CPR)]) = rbh_r[slot][p];
-        *reinterpret_cast<u4_t*>(&Bl[buf][c / CPR][8 * (c % CPR)]) = rbl_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Bh[buf][swz(c / CPR, c % CPR)]) = rbh_r[slot][p];
+        *reinterpret_cast<u4_t*>(&Bl[buf][swz(c / CPR, c % CPR)]) = rbl_r[slot][p];
       }
     }
   };
 
   f4_t acc[TM][TN];
   auto compute = [&](int cur) {
-#pragma unroll
-    for (int kb = 0; kb < BK / 32; ++kb) {
+    {
       bf8_t ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi) {
-        ah[mi] = *reinterpret_cast<const bf8_t*>(&Ah[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
-        al[mi] = *reinterpret_cast<const bf8_t*>(&Al[cur][wm + 16 * mi + l16][32 * kb + 8 * g]);
+        ah[mi] = *reinterpret_cast<const bf8_t*>(&Ah[cur][swz(wm + 16 * mi + l16, g)]);
+        al[mi] = *reinterpret_cast<const bf8_t*>(&Al[cur][swz(wm + 16 * mi + l16, g)]);
       }
 #pragma unroll
       for (int ni = 0; ni < TN; ++ni) {
-        bh[ni] = *reinterpret_cast<const bf8_t*>(&Bh[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
-        bl[ni] = *reinterpret_cast<const bf8_t*>(&Bl[cur][wn + 16 * ni + l16][32 * kb + 8 * g]);
+        bh[ni] = *reinterpret_cast<const bf8_t*>(&Bh[cur][swz(wn + 16 * ni + l16, g)]);
+        bl[ni] = *reinterpret_cast<const bf8_t*>(&Bl[cur][swz(wn + 16 * ni + l16, g)]);
       }
 #pragma unroll
       for (int mi = 0; mi < TM; ++mi)

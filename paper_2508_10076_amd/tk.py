@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtk.so")
+# TK_LIBRARY selects another build of the same library (the sanitized one)
+LIB_PATH = os.environ.get("TK_LIBRARY") or os.path.join(_HERE, "libtk.so")
 
 SYM = {"Z1": 0, "Z2": 1, "FZ2": 2, "U1": 3, "U1xFZ2": 4}
 NCOMP = {0: 0, 1: 1, 2: 1, 3: 1, 4: 2}

@@ -39,8 +39,9 @@ def test_binding_refuses_to_run_without_library(tmp_path):
     pkg.mkdir()
     (pkg / "__init__.py").write_text("")
     (pkg / "tk.py").write_text(open(os.path.join(ROOT, "paper_2508_10076_amd", "tk.py")).read())
+    env = {k: v for k, v in os.environ.items() if k != "TK_LIBRARY"}
     r = subprocess.run([sys.executable, "-c", "import paper_2508_10076_amd.tk"], cwd=tmp_path,
-                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, env=env)
     assert r.returncode != 0 and "libtk.so is missing" in r.stdout
 
 
