@@ -898,25 +898,42 @@ void add_block_tasks(TaskList& tl, int16_t sbuf, int64_t src, int16_t dbuf, int6
     if (tl.tiles.size() > static_cast<size_t>(INT32_MAX)) fail(TK_ERR_UNSUPPORTED, "too many permute tiles");
     return;
   }
-  PermTask t{};
-  t.lo = lo;
-  t.src = src;
-  t.dst = dst;
-  t.n = m;
-  t.src_buf = sbuf;
-  t.dst_buf = dbuf;
-  t.sign = sign;
-  for (int i = 0; i < tk::kMaxDims; ++i) {
-    t.dim[i] = i < m ? checked_i32(D[i], "dim") : 1;
-    t.ss[i] = i < m ? checked_i32(S[i], "stride") : 0;
-    t.ds[i] = i < m ? checked_i32(T[i], "stride") : 0;
-    division_magic(static_cast<uint32_t>(t.dim[i]), &t.mag[i], &t.shr[i]);
-  }
-  for (int64_t s0 = 0; s0 < total; s0 += tk::kPermChunk) {
-    t.start = static_cast<int32_t>(s0);
-    t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, total - s0));
-    tl.tasks.push_back(t);
-  }
+  // The kernel forms element offsets in 32 bits, relative to the task's
+  // source and destination.  A block whose offsets span 2^31 or more (a
+  // small block inside a huge sector) is cut along its outermost dims into
+  // slices that fit, each with its own 64-bit base.
+  std::function<void(int64_t, int64_t, int)> emit = [&](int64_t so, int64_t dof, int md) {
+    int64_t sspan = 0, dspan = 0, cnt = 1;
+    for (int i = 0; i < md; ++i) {
+      sspan += (D[i] - 1) * S[i];
+      dspan += (D[i] - 1) * T[i];
+      cnt *= D[i];
+    }
+    if (sspan > INT32_MAX || dspan > INT32_MAX) {
+      for (int64_t x = 0; x < D[md - 1]; ++x) emit(so + x * S[md - 1], dof + x * T[md - 1], md - 1);
+      return;
+    }
+    PermTask t{};
+    t.lo = lo;
+    t.src = so;
+    t.dst = dof;
+    t.n = std::max(md, 1);
+    t.src_buf = sbuf;
+    t.dst_buf = dbuf;
+    t.sign = sign;
+    for (int i = 0; i < tk::kMaxDims; ++i) {
+      t.dim[i] = i < md ? checked_i32(D[i], "dim") : 1;
+      t.ss[i] = i < md ? checked_i32(S[i], "stride") : 0;
+      t.ds[i] = i < md ? checked_i32(T[i], "stride") : 0;
+      division_magic(static_cast<uint32_t>(t.dim[i]), &t.mag[i], &t.shr[i]);
+    }
+    for (int64_t s0 = 0; s0 < cnt; s0 += tk::kPermChunk) {
+      t.start = static_cast<int32_t>(s0);
+      t.count = static_cast<int32_t>(std::min<int64_t>(tk::kPermChunk, cnt - s0));
+      tl.tasks.push_back(t);
+    }
+  };
+  emit(src, dst, m);
 }
 
 // Sector GEMMs with K at most this run as an output-stationary stream.

@@ -59,6 +59,10 @@ __device__ __forceinline__ void store_split(TK_GLOBAL __bf16* hi, int64_t lo, T 
 // One task, processed by `nthr` threads starting at thread `t0` of the
 // workgroup (the whole workgroup for a large task, one wave for small ones).
 // SPLIT: tasks with lo != 0 write bf16 hi and lo planes instead of T.
+// The task record is uniform over those threads (scalar loads), and element
+// offsets are 32-bit, relative to the task's source and destination: a
+// block holds fewer than 2^31 elements (the planner refuses larger ones) and
+// a split plane fewer than 2^31 values.
 template <typename T, bool SPLIT = false>
 __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, const Ptrs& P, double alpha,
                                              double beta, int lt, int nthr) {
@@ -66,22 +70,11 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
   const int count = tk->count;
   const uint32_t start = static_cast<uint32_t>(tk->start);
   const T sign = static_cast<T>(tk->sign);
-  int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
-  uint32_t mag[kMaxDims];
-  int shr[kMaxDims];
-#pragma unroll
-  for (int d = 0; d < kMaxDims; ++d) {
-    dim[d] = tk->dim[d];
-    ss[d] = tk->ss[d];
-    ds[d] = tk->ds[d];
-    mag[d] = tk->mag[d];
-    shr[d] = tk->shr[d];
-  }
   TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
   const bool has_src = tk->src_buf >= 0;
   const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, has_src ? tk->src_buf : tk->dst_buf) + tk->src;
   for (int e0 = 0; e0 < count; e0 += nthr * kBatch) {
-    int64_t so[kBatch], dof[kBatch];
+    int32_t so[kBatch], dof[kBatch];
     T v[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
@@ -89,16 +82,16 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
       // unconditional; their stores are skipped)
       const int e = min(e0 + u * nthr + lt, count - 1);
       uint32_t lin = start + static_cast<uint32_t>(e);
-      int64_t a = 0, b = 0;
+      int32_t a = 0, b = 0;
 #pragma unroll
       for (int d = 0; d < kMaxDims; ++d) {
         if (d < n) {
           // lin < 2^31: division by dim[d] as a multiply-high (host-side magic)
-          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
-          const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
+          const uint32_t i = lin - q * static_cast<uint32_t>(tk->dim[d]);
           lin = q;
-          a += static_cast<int64_t>(i) * ss[d];
-          b += static_cast<int64_t>(i) * ds[d];
+          a += static_cast<int32_t>(i) * tk->ss[d];
+          b += static_cast<int32_t>(i) * tk->ds[d];
         }
       }
       so[u] = a;
@@ -152,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void permute_kernel(const PermTask* __res
     permute_task<T, SPLIT>(tasks + t0, P, alpha, beta, threadIdx.x, kThreads);
     return;
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   for (int t = t0 + wave; t < t1; t += kThreads / 64) permute_task<T, SPLIT>(tasks + t, P, alpha, beta, lane, 64);
 }
 
@@ -988,6 +981,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
         store_tile_t<TS, AT, TM, TN, VS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
                                          tile.n0 + wn + GS * g, acc);
       }
+      // nothing left in flight (see the same wait in gemm_split3_kernel)
+      __builtin_amdgcn_s_waitcnt(0x0F70);
       cbase = G0 + PF;
       if (++ct < t_end) compute_tile(ct);
     }
@@ -1263,6 +1258,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs
         store_tile_t<TS, f4_t, TM, TN, 1>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
                                           tile.n0 + wn + 4 * g, acc);
       }
+      // The epilogue's table loads are done by now (the stage loads issued
+      // before them are too: the counter is in order), but some of their
+      // results are never read, and the compiler would otherwise keep those
+      // registers pending and make every later stage wait for its own
+      // prefetch before the LDS reads.  vmcnt(0): nothing is left in flight.
+      __builtin_amdgcn_s_waitcnt(0x0F70);
       cbase = G0 + PF;
       if (++ct < t_end) compute_tile(ct);
     }
