@@ -656,6 +656,8 @@ def bench_svd(args, tk, torch, np):
             U, S, Vh, err = tk.tensor_svd(ctx, A, (0, 1), (2, 3), max_dim=1024, stream=stream)
     torch.cuda.synchronize()
     ms = (_t.perf_counter() - t0) * 1e3 / steps
+    with torch.cuda.stream(stream):
+        sweeps = tk.tensor_svd(ctx, A, (0, 1), (2, 3), max_dim=1024, stream=stream, info=True)[4]["max_sweeps"]
     nbytes = 8.0 * (A.nelem + U.nelem + S.nelem + Vh.nelem)
     _, rows, cols, _ = A.sectors()  # the split (a, p1) | (b, p2) is the stored matrix form
     mn = [(int(max(r, c)), int(min(r, c))) for r, c in zip(rows, cols)]
@@ -666,7 +668,7 @@ def bench_svd(args, tk, torch, np):
             "dtype": "f64", "data": "synthetic",
             "config": {"workload": "svd_u1_D1024: truncated SVD of x2 : V x P <- V x P*, (a, p1) | (b, p2), "
                                    "D=1024, 1024 kept", "sectors": len(mn), "largest_block": max(mn),
-                       "truncation_error": err, "parallelism": "1 GPU",
+                       "truncation_error": err, "jacobi_sweeps": sweeps, "parallelism": "1 GPU",
                        "value_counts": "4 m n^2 per sector matrix (the singular values of an m x n block)"},
             "roofline": {"bound": "hbm", "achieved": round(gbps, 2), "peak": HBM_PEAK, "unit": "GB/s",
                          "frac": round(gbps / HBM_PEAK, 5), "traffic": None,

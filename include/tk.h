@@ -185,7 +185,10 @@ tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* de
  * (descending within each coupled charge), Vh : W <- dom(A~), where the
  * bond space W has one sector per coupled charge of A~, of degeneracy the
  * number of singular values kept there.  Each coupled-charge matrix is
- * decomposed on the device by one-sided Jacobi rotations; the kept values
+ * decomposed on the device by one-sided Jacobi rotations, as a block method
+ * (column blocks of 16; every block pair of every matrix in a round is one
+ * workgroup, which rotates its 32 columns by one Jacobi sweep over their
+ * Gram matrix); the kept values
  * are the largest over all charges, at most max_dim of them (max_dim < 0:
  * no bound) and only those above cutoff.  Three steps:
  *   tk_svd_create -- enqueues the decomposition on `stream`, waits for it,
@@ -195,8 +198,11 @@ tk_status tk_tensor_create_adjoint(tk_context* ctx, const tk_tensor* A, void* de
  *     S (1) or Vh (2), on caller storage as tk_tensor_create;
  *   tk_svd_finish -- fills U, S and Vh (waits for the copies) and returns
  *     the truncation error (the norm of the discarded singular values).
- * Sweeps stop when one rotates no pair (a pair counts as orthogonal when
- * |w_p . w_q| <= 4 eps |w_p| |w_q|); a sector still rotating after 60
+ * Sweeps (one pass over all block pairs; the host waits after each) stop
+ * when one rotates no pair (a pair counts as orthogonal when
+ * |w_p . w_q| <= max(4, sqrt(m)) eps |w_p| |w_q|, m the longer side of the
+ * sector matrix: the rounding level of an m-term inner product); a sector
+ * still rotating after 60
  * sweeps fails tk_svd_create with TK_ERR_UNSUPPORTED (its values would not
  * be converged).  tk_svd_info reports the number of decomposed sector
  * matrices, of kept values, and the largest sweep count (any pointer may be

@@ -3091,36 +3091,90 @@ tk_status tk_svd_create(tk_context* ctx, const tk_tensor* A, const int32_t* p, i
       sv->sec.push_back(r);
       sv->sec_sector.push_back(static_cast<int32_t>(k));
     }
-    for (auto& r : sv->sec) {  // singular values (and the sweep count) after every matrix
+    for (auto& r : sv->sec) {  // singular values after every matrix
       r.s = wsz;
-      wsz += r.n + 1;
+      wsz += r.n;
     }
     sv->ws.alloc(std::max<int64_t>(wsz, 1) * sizeof(double));
     sv->secs.upload(sv->sec);
-    const double tol = std::numeric_limits<double>::epsilon() * 4.0;
-    hip_check(tk::launch_jacobi_svd(static_cast<const tk::SvdSector*>(sv->secs.p), static_cast<int>(sv->sec.size()), X,
-                                    static_cast<double*>(sv->ws.p), kSvdMaxSweeps, tol, st),
-              "Jacobi SVD launch");
-    hip_check(hipStreamSynchronize(st), "stream synchronize");
-    int64_t nsig = 0;
-    for (const auto& r : sv->sec) nsig += r.n + 1;
-    std::vector<double> sig(nsig);
-    if (nsig)
-      hip_check(hipMemcpy(sig.data(), static_cast<double*>(sv->ws.p) + sv->sec.front().s, nsig * sizeof(double),
-                          hipMemcpyDeviceToHost),
-                "copy of the singular values");
-    // per sector: n singular values, then the sweep count (negative: the
-    // iteration reached the sweep limit while still rotating)
-    sv->sigma.clear();
-    for (size_t r = 0, o = 0; r < sv->sec.size(); o += sv->sec[r].n + 1, ++r) {
-      sv->sigma.insert(sv->sigma.end(), sig.begin() + o, sig.begin() + o + sv->sec[r].n);
-      const int sweeps = static_cast<int>(sig[o + sv->sec[r].n]);
-      sv->max_sweeps = std::max(sv->max_sweeps, std::abs(sweeps));
-      if (sweeps <= 0)
+    const double tol = std::numeric_limits<double>::epsilon();  // scaled per sector in the kernel
+    // Block one-sided Jacobi: the columns of each sector form blocks of
+    // kSvdBlock; round g of a sweep holds the g-th round of the round-robin
+    // pairing of every sector's blocks (a sector with b blocks has b' - 1
+    // rounds, b' = b rounded up to even; one block alone: one round).
+    const int nsec = static_cast<int>(sv->sec.size());
+    std::vector<std::vector<tk::SvdItem>> rounds;
+    for (int r = 0; r < nsec; ++r) {
+      const int n = sv->sec[r].n, B = tk::kSvdBlock;
+      const int nb = (n + B - 1) / B;
+      if (nb <= 1) {
+        if (rounds.empty()) rounds.resize(1);
+        rounds[0].push_back({r, 0, n, 0, 0, 0});
+        continue;
+      }
+      const int nbp = nb + (nb & 1);
+      if (static_cast<int>(rounds.size()) < nbp - 1) rounds.resize(nbp - 1);
+      for (int g = 0; g < nbp - 1; ++g)
+        for (int i = 0; i < nbp / 2; ++i) {
+          const int P = i == 0 ? 0 : 1 + (g + i) % (nbp - 1);
+          const int Q = i == 0 ? 1 + g : 1 + (g - i + nbp - 1) % (nbp - 1);
+          const int p0 = std::min(n, P * B), np = std::min(n, (P + 1) * B) - p0;
+          const int q0 = std::min(n, Q * B), nq = std::min(n, (Q + 1) * B) - q0;
+          if (np > 0) rounds[g].push_back({r, p0, np, q0, nq, 0});
+          else if (nq > 0) rounds[g].push_back({r, q0, nq, 0, 0, 0});
+        }
+    }
+    std::vector<tk::SvdItem> items;
+    std::vector<int> roff{0};
+    for (const auto& rd : rounds) {
+      items.insert(items.end(), rd.begin(), rd.end());
+      roff.push_back(static_cast<int>(items.size()));
+    }
+    DevBuf d_items, d_flags;
+    d_items.upload(items);
+    d_flags.alloc(std::max<size_t>(1, 2 * size_t(nsec)) * sizeof(int32_t));
+    const tk::SvdSector* d_secs = static_cast<const tk::SvdSector*>(sv->secs.p);
+    double* d_ws = static_cast<double*>(sv->ws.p);
+    int32_t* flags = static_cast<int32_t*>(d_flags.p);
+    hip_check(tk::launch_svd_init(d_secs, nsec, X, d_ws, st), "SVD init launch");
+    // sweeps until a sweep rotates nothing (per sector: the sweeps used,
+    // 0 while it still rotates)
+    std::vector<int32_t> rotated(nsec), sweeps(nsec, 0);
+    bool all_done = nsec == 0;
+    for (int sw = 0; sw < kSvdMaxSweeps && !all_done; ++sw) {
+      int32_t* cur = flags + (sw & 1) * nsec;
+      const int32_t* prev = flags + ((sw + 1) & 1) * nsec;
+      hip_check(hipMemsetAsync(cur, 0, nsec * sizeof(int32_t), st), "flag clear");
+      for (size_t g = 0; g < rounds.size(); ++g)
+        hip_check(tk::launch_svd_round(static_cast<const tk::SvdItem*>(d_items.p) + roff[g], roff[g + 1] - roff[g],
+                                       d_secs, d_ws, prev, cur, sw, tol, st),
+                  "SVD round launch");
+      hip_check(hipMemcpyAsync(rotated.data(), cur, nsec * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                "copy of the rotation flags");
+      hip_check(hipStreamSynchronize(st), "stream synchronize");
+      all_done = true;
+      for (int r = 0; r < nsec; ++r) {
+        if (sweeps[r] != 0) continue;
+        if (rotated[r] == 0) sweeps[r] = sw + 1;
+        else all_done = false;
+      }
+    }
+    for (int r = 0; r < nsec; ++r) {
+      sv->max_sweeps = std::max(sv->max_sweeps, sweeps[r] != 0 ? sweeps[r] : kSvdMaxSweeps);
+      if (sweeps[r] == 0)
         fail(TK_ERR_UNSUPPORTED, "the Jacobi iteration of a " + std::to_string(sv->sec[r].m) + " x " +
                                      std::to_string(sv->sec[r].n) + " sector did not converge in " +
                                      std::to_string(kSvdMaxSweeps) + " sweeps");
     }
+    hip_check(tk::launch_svd_finish(d_secs, nsec, d_ws, st), "SVD finish launch");
+    hip_check(hipStreamSynchronize(st), "stream synchronize");
+    int64_t nsig = 0;
+    for (const auto& r : sv->sec) nsig += r.n;
+    std::vector<double> sig(nsig);
+    if (nsig)
+      hip_check(hipMemcpy(sig.data(), d_ws + sv->sec.front().s, nsig * sizeof(double), hipMemcpyDeviceToHost),
+                "copy of the singular values");
+    sv->sigma = sig;
     // the largest values over all sectors (ties: sector order, then index)
     struct Val {
       double s;

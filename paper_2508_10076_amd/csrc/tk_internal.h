@@ -304,18 +304,27 @@ hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_fir
 // Singular value decomposition of one coupled-sector matrix (R x C,
 // column-major) by one-sided Jacobi rotations on its m x n working copy W
 // (the matrix, or its transpose when R < C, so that m >= n), with the
-// rotations accumulated in V (n x n).  On exit sigma[j] = |W_j| and W_j is
-// normalised (the left singular vectors of the working matrix), and
-// sigma[n] holds the number of sweeps used, negated when the last sweep still
-// rotated a pair (the iteration stopped at max_sweeps without converging).
+// rotations accumulated in V (n x n).  At the end sigma[j] = |W_j| and W_j is
+// normalised (the left singular vectors of the working matrix).
 struct SvdSector {
   int64_t x;         // the matrix in its buffer
   int64_t w, v, s;   // W, V and sigma in the workspace (elements)
   int32_t R, C, m, n, trans, pad_;
 };
 constexpr int kSvdThreads = 1024;
-hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, double* ws, int max_sweeps,
-                             double tol, hipStream_t stream);
+// Block Jacobi: columns per block, threads of a block-pair workgroup (one
+// 16-thread group per column pair of a round of 2 kSvdBlock columns).
+constexpr int kSvdBlock = 16;
+constexpr int kSvdRoundThreads = kSvdBlock * 16;
+// One block pair of one sector in a round: columns p0 .. p0+np-1 and
+// q0 .. q0+nq-1 of its W (nq = 0: a block paired with the empty one).
+struct SvdItem {
+  int32_t sec, p0, np, q0, nq, pad_;
+};
+hipError_t launch_svd_init(const SvdSector* secs, int nsec, const double* X, double* ws, hipStream_t stream);
+hipError_t launch_svd_round(const SvdItem* items, int nitems, const SvdSector* secs, double* ws, const int32_t* prev,
+                            int32_t* flag, int sweep, double tol, hipStream_t stream);
+hipError_t launch_svd_finish(const SvdSector* secs, int nsec, double* ws, hipStream_t stream);
 
 // Bytes of the per-device scratch array that the allocation-free
 // contraction lays its tables and workspaces into (TK_SCRATCH_BYTES).

@@ -335,26 +335,31 @@ __global__ __launch_bounds__(kThreads) void trace_kernel(const TraceTask* __rest
   }
 }
 
-// One-sided (Hestenes) Jacobi SVD, one workgroup per coupled-sector
-// matrix.  A sweep pairs every two columns once, in n' - 1 rounds of n'/2
-// disjoint pairs (round-robin order, n' = n rounded up to even, the extra
-// column a dummy); a wave takes a pair, forms |W_p|^2, |W_q|^2 and W_p.W_q
-// over the rows, and, unless the pair is already orthogonal to tol, rotates
-// both columns of W and of V so that it becomes so.  Rounds are separated by
-// barriers (their pairs are disjoint); sweeps stop when one applies no
-// rotation or after max_sweeps.
-constexpr int kSvdCache = 8;  // elements per lane held in registers (columns up to 512 rows)
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// One-sided (Hestenes) Jacobi SVD of the coupled-sector matrices, as a
+// block method spread over the whole GPU.  Each sector matrix (m x n, the
+// taller side as rows) is copied into W, with V = I.  Its columns form
+// blocks of kSvdBlock; a sweep pairs every two blocks once, in rounds of
+// disjoint block pairs (round-robin order), and every pair of every sector
+// in a round is one workgroup.  The workgroup forms the Gram matrix
+// G = W_K^T W_K of its k <= 2 kSvdBlock columns, and unless all of them are
+// already orthogonal (to eps max(4, sqrt(m))), applies one cyclic Jacobi sweep to G (each
+// column pair rotated, by the same rotation the one-sided method would
+// apply to W, in k - 1 rounds of disjoint pairs), accumulating the
+// rotations in J; then W_K <- W_K J and V_K <- V_K J.  The host runs sweeps
+// until one rotates nothing in a sector (a sector that rotated nothing in a
+// sweep is skipped from then on: its columns no longer change).  Last, each
+// column's norm is its singular value and W's columns are normalised (U).
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
 
-__global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector* __restrict__ secs,
-                                                                 const double* __restrict__ X,
-                                                                 double* __restrict__ ws, int max_sweeps,
-                                                                 double tol) {
+__global__ __launch_bounds__(kSvdThreads) void svd_init_kernel(const SvdSector* __restrict__ secs,
+                                                               const double* __restrict__ X,
+                                                               double* __restrict__ ws) {
   const SvdSector sc = secs[blockIdx.x];
   const int m = sc.m, n = sc.n, R = sc.R;
   double* W = ws + sc.w;
@@ -366,117 +371,175 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(const SvdSector
   }
   for (int64_t e = threadIdx.x; e < static_cast<int64_t>(n) * n; e += kSvdThreads)
     V[e] = (e % n == e / n) ? 1.0 : 0.0;
-  __shared__ int s_rot;
-  // squared column norms of W (columns of up to kSvdCache * 64 rows, so
-  // n <= m <= 512): formed at the start of every sweep and carried through
-  // each rotation (a' = a - t g, b' = b + t g), so a rotation reduces only
-  // the inner product g across the wave
-  __shared__ double s_nrm[kSvdCache * 64];
-  const bool cached = m <= kSvdCache * 64;
-  __syncthreads();
-  const int nn = n + (n & 1), wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kSvdThreads / 64;
-  int done = 0;
-  bool converged = false;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (threadIdx.x == 0) s_rot = 0;
-    if (cached) {
-      for (int j = wave; j < n; j += nw) {
-        const double* Wj = W + static_cast<int64_t>(m) * j;
-        double a = 0.0;
-        for (int i = lane; i < m; i += 64) a += Wj[i] * Wj[i];
-        a = wave_sum(a);
-        if (lane == 0) s_nrm[j] = a;
-      }
+}
+
+// Rows of W_K (or V_K) staged in LDS per pass.
+constexpr int kSvdRows = 64;
+// Inner Jacobi sweeps over a block pair's Gram matrix at most (more inner
+// sweeps barely reduce the outer ones: one is the cheapest overall).
+constexpr int kSvdInner = 1;
+
+// One block pair (see above); `prev` holds each sector's rotation flag of
+// the previous sweep (skip the sector when it is 0), `flag` this sweep's.
+// The Gram matrix and the products W_K J, V_K J run on the fp64 MFMA
+// (16x16x4: lane l supplies X[l%16][l/16] and Y[l/16][l%16], and value v of
+// its result is D[l/16 + 4v][l%16] of D = X Y), one 16x16 tile per wave;
+// the rows pass through LDS kSvdRows at a time, the next pass's loads in
+// flight while the current one is multiplied.
+__global__ __launch_bounds__(kSvdRoundThreads) void svd_round_kernel(const SvdItem* __restrict__ items,
+                                                                     const SvdSector* __restrict__ secs,
+                                                                     double* __restrict__ ws,
+                                                                     const int32_t* __restrict__ prev,
+                                                                     int32_t* __restrict__ flag, int sweep,
+                                                                     double tol) {
+  constexpr int KM = 2 * kSvdBlock, NT = kSvdRoundThreads, PASS = kSvdRows * KM / NT;
+  static_assert(NT == (KM / 2) * 16, "one 16-thread group per column pair of a round");
+  static_assert(KM == 32 && NT == 256, "four waves, one 16x16 Gram tile each");
+  __shared__ double G[KM][KM + 1];
+  __shared__ double J[KM][KM + 1];
+  __shared__ double Wc[kSvdRows][KM + 1];
+  const SvdItem it = items[blockIdx.x];
+  if (sweep > 0 && prev[it.sec] == 0) return;
+  const SvdSector sc = secs[it.sec];
+  const int k = it.np + it.nq, tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
+  // orthogonality threshold of the sector: eps max(4, sqrt(m)) (tol = eps);
+  // the rounding of an m-term inner product is of order sqrt(m) eps
+  tol *= fmax(4.0, sqrt(static_cast<double>(sc.m)));
+  // column c of the pair's k columns: its column of W (and of V)
+  auto col = [&](int c) { return c < it.np ? it.p0 + c : it.q0 + (c - it.np); };
+  double* W = ws + sc.w;
+  double* V = ws + sc.v;
+  // element x of a pass: row x % kSvdRows, column x / kSvdRows (coalesced
+  // along each column)
+  double stage[PASS];
+  auto load_pass = [&](const double* X, int rows, int r0) {
+#pragma unroll
+    for (int e = 0; e < PASS; ++e) {
+      const int x = tid + NT * e, rr = x % kSvdRows, c = x / kSvdRows;
+      stage[e] = (r0 + rr < rows && c < k) ? X[r0 + rr + static_cast<int64_t>(rows) * col(c)] : 0.0;
     }
+  };
+  auto store_pass = [&]() {
+#pragma unroll
+    for (int e = 0; e < PASS; ++e) {
+      const int x = tid + NT * e;
+      Wc[x % kSvdRows][x / kSvdRows] = stage[e];
+    }
+  };
+
+  // 1. Gram matrix: wave w forms tile (w / 2, w % 2)
+  const int ti = wave >> 1, tj = wave & 1;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  load_pass(W, sc.m, 0);
+  for (int r0 = 0; r0 < sc.m; r0 += kSvdRows) {
+    store_pass();
     __syncthreads();
-    for (int r = 0; r < nn - 1; ++r) {
-      for (int k = wave; k < nn / 2; k += nw) {
-        const int p = k == 0 ? 0 : 1 + (r + k) % (nn - 1);
-        const int q = k == 0 ? 1 + r : 1 + (r - k + nn - 1) % (nn - 1);
-        if (p >= n || q >= n) continue;  // the dummy column
-        double* Wp = W + static_cast<int64_t>(m) * p;
-        double* Wq = W + static_cast<int64_t>(m) * q;
-        double* Vp = V + static_cast<int64_t>(n) * p;
-        double* Vq = V + static_cast<int64_t>(n) * q;
-        double a = 0.0, b = 0.0, g = 0.0;
-        if (cached) {
-          // columns of up to kSvdCache * 64 rows: every element this lane
-          // needs (of W and of V) is loaded once, before any arithmetic
-          double xw[kSvdCache], yw[kSvdCache], xv[kSvdCache], yv[kSvdCache];
+    if (r0 + kSvdRows < sc.m) load_pass(W, sc.m, r0 + kSvdRows);
 #pragma unroll
-          for (int u = 0; u < kSvdCache; ++u) {
-            const int i = lane + 64 * u;
-            xw[u] = i < m ? Wp[i] : 0.0;
-            yw[u] = i < m ? Wq[i] : 0.0;
-            xv[u] = i < n ? Vp[i] : 0.0;
-            yv[u] = i < n ? Vq[i] : 0.0;
-          }
+    for (int st = 0; st < kSvdRows / 4; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Wc[4 * st + g4][16 * ti + l16], Wc[4 * st + g4][16 * tj + l16],
+                                                 acc, 0, 0, 0);
+    __syncthreads();
+  }
 #pragma unroll
-          for (int u = 0; u < kSvdCache; ++u) g += xw[u] * yw[u];
-          a = s_nrm[p];
-          b = s_nrm[q];
-          g = wave_sum(g);
-          if (!(a > 0.0 && b > 0.0) || fabs(g) <= tol * sqrt(a * b)) continue;
+  for (int v = 0; v < 4; ++v) G[16 * ti + g4 + 4 * v][16 * tj + l16] = acc[v];
+  for (int x = tid; x < KM * KM; x += NT) J[x / KM][x % KM] = (x / KM == x % KM) ? 1.0 : 0.0;
+  __syncthreads();
+  // 2. are all pairs orthogonal to tol already?
+  bool rot = false;
+  for (int x = tid; x < KM * KM; x += NT) {
+    const int a = x / KM, b = x % KM;
+    if (a < b && b < k) {
+      const double ga = G[a][a], gb = G[b][b], g = G[a][b];
+      rot |= ga > 0.0 && gb > 0.0 && fabs(g) > tol * sqrt(ga * gb);
+    }
+  }
+  if (!__syncthreads_or(rot)) return;
+  // 3. cyclic sweeps over the k columns until one rotates nothing (k' = k
+  // rounded up to even, the extra index a dummy): round r pairs (0, 1 + r)
+  // and (1 + (r + i) % (k' - 1), 1 + (r - i) % (k' - 1)), i = 1 .. k'/2 - 1
+  const int kk = k + (k & 1);
+  const int pi = tid / 16, p16 = tid % 16;
+  for (int inner = 0; inner < kSvdInner; ++inner) {
+    bool any = false;
+    for (int r = 0; r < kk - 1; ++r) {
+      const int p = pi == 0 ? 0 : 1 + (r + pi) % (kk - 1);
+      const int q = pi == 0 ? 1 + r : 1 + (r - pi + kk - 1) % (kk - 1);
+      bool doit = 2 * pi < kk && p < k && q < k;
+      double c = 1.0, s = 0.0;
+      if (doit) {
+        const double a = G[p][p], b = G[q][q], g = G[p][q];
+        doit = a > 0.0 && b > 0.0 && fabs(g) > tol * sqrt(a * b);
+        if (doit) {
           const double zeta = (b - a) / (2.0 * g);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-#pragma unroll
-          for (int u = 0; u < kSvdCache; ++u) {
-            const int i = lane + 64 * u;
-            if (i < m) {
-              Wp[i] = c * xw[u] - s * yw[u];
-              Wq[i] = s * xw[u] + c * yw[u];
-            }
-            if (i < n) {
-              Vp[i] = c * xv[u] - s * yv[u];
-              Vq[i] = s * xv[u] + c * yv[u];
-            }
-          }
-          if (lane == 0) {
-            s_rot = 1;
-            s_nrm[p] = a - t * g;
-            s_nrm[q] = b + t * g;
-          }
-          continue;
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = c * t;
         }
-        for (int i = lane; i < m; i += 64) {
-          const double x = Wp[i], y = Wq[i];
-          a += x * x;
-          b += y * y;
-          g += x * y;
+      }
+      any |= doit;
+      __syncthreads();  // every rotation of the round is formed from the same G
+      if (doit) {       // rows p and q: G <- R^T G
+        for (int jj = p16; jj < k; jj += 16) {
+          const double x = G[p][jj], y = G[q][jj];
+          G[p][jj] = c * x - s * y;
+          G[q][jj] = s * x + c * y;
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        g = wave_sum(g);
-        if (!(a > 0.0 && b > 0.0) || fabs(g) <= tol * sqrt(a * b)) continue;
-        const double zeta = (b - a) / (2.0 * g);
-        const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = lane; i < m; i += 64) {
-          const double x = Wp[i], y = Wq[i];
-          Wp[i] = c * x - s * y;
-          Wq[i] = s * x + c * y;
+      }
+      __syncthreads();
+      if (doit) {  // columns p and q: G <- G R, J <- J R
+        for (int ii = p16; ii < k; ii += 16) {
+          const double x = G[ii][p], y = G[ii][q];
+          G[ii][p] = c * x - s * y;
+          G[ii][q] = s * x + c * y;
+          const double u = J[ii][p], v = J[ii][q];
+          J[ii][p] = c * u - s * v;
+          J[ii][q] = s * u + c * v;
         }
-        for (int i = lane; i < n; i += 64) {
-          const double x = Vp[i], y = Vq[i];
-          Vp[i] = c * x - s * y;
-          Vq[i] = s * x + c * y;
-        }
-        if (lane == 0) s_rot = 1;
       }
       __syncthreads();
     }
-    const int rotated = s_rot;
-    __syncthreads();
-    done = sweep + 1;
-    if (!rotated) {
-      converged = true;
-      break;
+    if (!__syncthreads_or(any)) break;
+  }
+  // 4. W_K <- W_K J and V_K <- V_K J: in each pass wave w forms rows
+  // 16 w .. 16 w + 15 of the pass, both 16-column tiles
+  for (int side = 0; side < 2; ++side) {
+    double* X = side == 0 ? W : V;
+    const int rows = side == 0 ? sc.m : sc.n;
+    load_pass(X, rows, 0);
+    for (int r0 = 0; r0 < rows; r0 += kSvdRows) {
+      store_pass();
+      __syncthreads();
+      if (r0 + kSvdRows < rows) load_pass(X, rows, r0 + kSvdRows);
+      d4_t o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int st = 0; st < KM / 4; ++st) {
+        const double a = Wc[16 * wave + l16][4 * st + g4];
+        o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, J[4 * st + g4][l16], o0, 0, 0, 0);
+        o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, J[4 * st + g4][16 + l16], o1, 0, 0, 0);
+      }
+      __syncthreads();  // the pass is read; the next store_pass may overwrite it
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * wave + g4 + 4 * v;
+        if (row >= rows) continue;
+        if (l16 < k) X[row + static_cast<int64_t>(rows) * col(l16)] = o0[v];
+        if (16 + l16 < k) X[row + static_cast<int64_t>(rows) * col(16 + l16)] = o1[v];
+      }
     }
   }
-  // sweeps used, negative when the last one still rotated (not converged)
-  if (threadIdx.x == 0) ws[sc.s + n] = converged ? done : -done;
+  if (tid == 0) flag[it.sec] = 1;
+}
+
+// Singular values (column norms of W) and U (W's columns normalised).
+__global__ __launch_bounds__(kSvdThreads) void svd_finish_kernel(const SvdSector* __restrict__ secs,
+                                                                 double* __restrict__ ws) {
+  const SvdSector sc = secs[blockIdx.x];
+  const int m = sc.m, n = sc.n;
+  double* W = ws + sc.w;
   double* S = ws + sc.s;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = kSvdThreads / 64;
   for (int j = wave; j < n; j += nw) {
     double* Wj = W + static_cast<int64_t>(m) * j;
     double a = 0.0;
@@ -591,7 +654,6 @@ __global__ __launch_bounds__(kThreads) void zero_ranges_kernel(const ZeroRange* 
 // ---------------------------------------------------------------------------
 // grouped sector GEMM, fp64 MFMA
 // ---------------------------------------------------------------------------
-typedef double d4_t __attribute__((ext_vector_type(4)));
 
 // Epilogue store of one accumulated element of C~ (row r, column s of the
 // sector GEMM d): in place (mode 0) or scattered into C (mode 1).
@@ -1683,10 +1745,23 @@ hipError_t launch_trace(int dtype, const TraceTask* tasks, const int32_t* wg_fir
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_svd(const SvdSector* secs, int nsec, const double* X, double* ws, int max_sweeps,
-                             double tol, hipStream_t stream) {
+hipError_t launch_svd_init(const SvdSector* secs, int nsec, const double* X, double* ws, hipStream_t stream) {
   if (nsec <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(nsec), dim3(kSvdThreads), 0, stream, secs, X, ws, max_sweeps, tol);
+  hipLaunchKernelGGL(svd_init_kernel, dim3(nsec), dim3(kSvdThreads), 0, stream, secs, X, ws);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_round(const SvdItem* items, int nitems, const SvdSector* secs, double* ws, const int32_t* prev,
+                            int32_t* flag, int sweep, double tol, hipStream_t stream) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_round_kernel, dim3(nitems), dim3(kSvdRoundThreads), 0, stream, items, secs, ws, prev, flag,
+                     sweep, tol);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_finish(const SvdSector* secs, int nsec, double* ws, hipStream_t stream) {
+  if (nsec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(svd_finish_kernel, dim3(nsec), dim3(kSvdThreads), 0, stream, secs, ws);
   return hipGetLastError();
 }
 
