@@ -317,11 +317,21 @@ tk_status tk_plan_destroy(tk_plan* plan);
 /* Enqueue only some stages of a plan, in the fixed order operand permutes
  * (TK_STAGE_PERMUTE), grouped GEMM (TK_STAGE_GEMM), zero blocks
  * (TK_STAGE_ZERO); executing all three equals tk_plan_execute.  Lets a
- * caller bracket one stage with events (per-kernel timing). */
+ * caller bracket one stage with events (per-kernel timing).
+ * TK_STAGE_PERMUTE_A and TK_STAGE_PERMUTE_B are the operand permute of A
+ * alone and of B alone (with TK_PREC_BF16X3: that operand's bf16 planes);
+ * the two together equal TK_STAGE_PERMUTE, which runs both in one launch.
+ * They let a caller enqueue the permute of an operand that is ready early
+ * (an input of a chain of contractions) on another stream, concurrently
+ * with earlier work, and the rest of the plan after an event.  The GEMM
+ * stage needs both permutes done; the zero stage of a plan whose output is
+ * permuted after the GEMM (see tk_plan_counts) needs the GEMM stage done. */
 #define TK_STAGE_PERMUTE 1
 #define TK_STAGE_GEMM 2
 #define TK_STAGE_ZERO 4
 #define TK_STAGE_ALL 7
+#define TK_STAGE_PERMUTE_A 8
+#define TK_STAGE_PERMUTE_B 16
 tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_tensor* B, tk_tensor* C,
                                  double alpha, double beta, int32_t stages, void* stream);
 

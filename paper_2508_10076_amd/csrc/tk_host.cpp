@@ -1851,6 +1851,10 @@ struct tk_plan {
   int precision = 0, dtype = 0;
   bool permA = false, permB = false, scatter = false, post = false;
   TaskList pre, zero, postp;
+  // operand permutes of A and of B alone; filled only when both have work
+  // (pre_owner: bit 0 A has permute work, bit 1 B has)
+  TaskList preA, preB;
+  int pre_owner = 0;
   std::vector<GemmDesc> descs;
   std::vector<LegMap> row_map, col_map;
   std::vector<PairDesc> pairs;
@@ -2201,19 +2205,38 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     pmB.lo = static_cast<int32_t>(P->planeB);
     P->needA = P->permA && smallk_any;
     P->needB = P->permB && smallk_any;
-    plan_permute_tasks(sA, pA, qA, At, tk::kBufA, P->needA ? tk::kBufAt : int16_t(-1), false, P->pre, nullptr,
+    plan_permute_tasks(sA, pA, qA, At, tk::kBufA, P->needA ? tk::kBufAt : int16_t(-1), false, P->preA, nullptr,
                        nullptr, &pmA);
-    plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, P->needB ? tk::kBufBt : int16_t(-1), twist, P->pre, nullptr,
+    plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, P->needB ? tk::kBufBt : int16_t(-1), twist, P->preB, nullptr,
                        nullptr, &pmB);
-    plan_plane_padding(At, pmA, P->pre);
-    plan_plane_padding(Bt, pmB, P->pre);
+    plan_plane_padding(At, pmA, P->preA);
+    plan_plane_padding(Bt, pmB, P->preB);
   } else {
     P->needA = P->permA;
     P->needB = P->permB;
-    if (P->permA) plan_permute_tasks(sA, pA, qA, At, tk::kBufA, tk::kBufAt, false, P->pre);
-    if (P->permB) plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, tk::kBufBt, twist, P->pre);
+    if (P->permA) plan_permute_tasks(sA, pA, qA, At, tk::kBufA, tk::kBufAt, false, P->preA);
+    if (P->permB) plan_permute_tasks(sB, pB, qB, Bt, tk::kBufB, tk::kBufBt, twist, P->preB);
   }
+  // the whole operand permute as one list (one launch of each kernel); the
+  // per-operand lists are kept apart only when both operands have work, so
+  // that either can be enqueued alone (TK_STAGE_PERMUTE_A / _B)
+  auto has_work = [](const TaskList& t) { return !t.tasks.empty() || !t.tiles.empty(); };
+  P->pre_owner = (has_work(P->preA) ? 1 : 0) | (has_work(P->preB) ? 2 : 0);
+  P->pre.tasks = P->preA.tasks;
+  P->pre.tasks.insert(P->pre.tasks.end(), P->preB.tasks.begin(), P->preB.tasks.end());
+  P->pre.tiles = P->preA.tiles;
+  P->pre.tiles.insert(P->pre.tiles.end(), P->preB.tiles.begin(), P->preB.tiles.end());
   pack_workgroups(P->pre);
+  if (P->pre_owner == 3) {
+    pack_workgroups(P->preA);
+    pack_workgroups(P->preB);
+  } else {
+    for (TaskList* t : {&P->preA, &P->preB}) {
+      t->tasks.clear();
+      t->tiles.clear();
+      t->wg_first.assign(1, 0);
+    }
+  }
 
   const bool idC = is_identity(pAB, qAB, Ct.N1());
   // fused scatter needs <= 4 legs per side of C~ and 16-bit leg indices
@@ -2545,6 +2568,8 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
     if (P->planeA) P->wsAp.alloc(4 * P->planeA);  // two bf16 planes
     if (P->planeB) P->wsBp.alloc(4 * P->planeB);
     P->pre.upload();
+    P->preA.upload();
+    P->preB.upload();
     P->zero.upload();
     P->zranges.upload();
     P->postp.upload();
@@ -2597,8 +2622,18 @@ void execute_plan(tk_plan& P, const tk_tensor* A, const tk_tensor* B, tk_tensor*
   check_exec_tensor(C, P.C, P.dtype, "C");
   if (C->data && (C->data == A->data || C->data == B->data)) fail(TK_ERR_INVALID_ARG, "C aliases an operand");
   tk::Ptrs ptrs = plan_ptrs(P, A, B, C);
-  if (stages & TK_STAGE_PERMUTE)
-    launch_tasklist(P.dtype, P.pre, ptrs, 1.0, 0.0, stream, P.precision == TK_PREC_BF16X3, "permute launch");
+  {
+    const bool pa = (stages & (TK_STAGE_PERMUTE | TK_STAGE_PERMUTE_A)) != 0;
+    const bool pb = (stages & (TK_STAGE_PERMUTE | TK_STAGE_PERMUTE_B)) != 0;
+    const bool split = P.precision == TK_PREC_BF16X3;
+    // one operand alone: its own list when both have work, else the whole
+    // list if it is that operand's
+    const TaskList* tl = nullptr;
+    if (pa && pb) tl = &P.pre;
+    else if (pa) tl = P.pre_owner == 3 ? &P.preA : P.pre_owner == 1 ? &P.pre : nullptr;
+    else if (pb) tl = P.pre_owner == 3 ? &P.preB : P.pre_owner == 2 ? &P.pre : nullptr;
+    if (tl) launch_tasklist(P.dtype, *tl, ptrs, 1.0, 0.0, stream, split, "permute launch");
+  }
   const double ga = alpha, gb = P.post ? 0.0 : beta;
   if ((stages & TK_STAGE_GEMM) && !P.descs.empty()) {
     tk::GemmArgs ga_{};
@@ -3397,7 +3432,8 @@ tk_status tk_plan_execute_stages(tk_plan* plan, const tk_tensor* A, const tk_ten
                                  double beta, int32_t stages, void* stream) {
   return guarded([&] {
     if (!plan) fail(TK_ERR_INVALID_ARG, "null plan");
-    if (stages < 0 || stages > TK_STAGE_ALL) fail(TK_ERR_INVALID_ARG, "bad stage mask");
+    if (stages < 0 || stages > (TK_STAGE_ALL | TK_STAGE_PERMUTE_A | TK_STAGE_PERMUTE_B))
+      fail(TK_ERR_INVALID_ARG, "bad stage mask");
     execute_plan(*plan, A, B, C, alpha, beta, static_cast<hipStream_t>(stream), stages);
   });
 }

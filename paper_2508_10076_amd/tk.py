@@ -21,6 +21,7 @@ NCOMP = {0: 0, 1: 1, 2: 1, 3: 1, 4: 2}
 DTYPE = {"f64": 0, "f32": 1}
 PREC = {"native": 0, "f32": 1, "bf16x3": 2}
 STAGE_PERMUTE, STAGE_GEMM, STAGE_ZERO, STAGE_ALL = 1, 2, 4, 7
+STAGE_PERMUTE_A, STAGE_PERMUTE_B = 8, 16
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "SPACE_MISMATCH", 3: "CHARGE", 4: "DTYPE", 5: "UNSUPPORTED",
           6: "OOM", 7: "HIP"}
 
