@@ -84,7 +84,7 @@ struct GemmDesc {
   int64_t a, b, c;
   int32_t M, N, K;
   int32_t lda, ldb, ldc;
-  int16_t a_buf, b_buf, c_buf, mode;
+  int32_t a_buf, b_buf, c_buf, mode;  // 32-bit: a 16-bit field read alone is a vector load
   int32_t row_map;    // first entry of this sector in the row map
   int32_t col_map;    // first entry in the column map
   int32_t pair_base;  // first entry in the pair table

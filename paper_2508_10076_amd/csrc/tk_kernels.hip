@@ -56,6 +56,38 @@ __device__ __forceinline__ void store_split(TK_GLOBAL __bf16* hi, int64_t lo, T 
   hi[lo] = static_cast<__bf16>(x - static_cast<float>(h));
 }
 
+// A task's source and destination buffer ids (adjacent 16-bit fields, the
+// first 4-byte aligned) as one 32-bit scalar load: a 16-bit field read on its
+// own compiles to a vector load, whose round trip would delay the task's
+// first data loads.
+template <typename TaskT>
+__device__ __forceinline__ void load_buf_ids(const TaskT* __restrict__ tk, int* src_buf, int* dst_buf) {
+  static_assert(__builtin_offsetof(TaskT, src_buf) % 4 == 0 &&
+                    __builtin_offsetof(TaskT, dst_buf) == __builtin_offsetof(TaskT, src_buf) + 2,
+                "adjacent 16-bit buffer ids");
+  const uint32_t w = __builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t*>(&tk->src_buf));
+  *src_buf = static_cast<int16_t>(w & 0xffffu);
+  *dst_buf = static_cast<int16_t>(w >> 16);
+}
+
+// A task's divisions by its dimensions (extent, multiply-high magic and
+// shift per dimension), read once as wave-uniform values (scalar registers):
+// the eight 1-byte shift counts as one 8-byte word, since a byte array read
+// at every use compiles to a vector byte load per lane.  The task record is
+// the same for every thread that calls this (a workgroup's or a wave's).
+template <typename TaskT>
+__device__ __forceinline__ void load_divisors(const TaskT* __restrict__ tk, int32_t* dim, uint32_t* mag,
+                                              uint32_t* shr) {
+  static_assert(__builtin_offsetof(TaskT, shr) % 8 == 0, "8-byte aligned shift counts");
+  const uint64_t shr8 = *reinterpret_cast<const uint64_t*>(tk->shr);
+#pragma unroll
+  for (int d = 0; d < kMaxDims; ++d) {
+    dim[d] = __builtin_amdgcn_readfirstlane(tk->dim[d]);
+    mag[d] = __builtin_amdgcn_readfirstlane(tk->mag[d]);
+    shr[d] = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(shr8 >> (8 * d)) & 0xffu);
+  }
+}
+
 // One task, processed by `nthr` threads starting at thread `t0` of the
 // workgroup (the whole workgroup for a large task, one wave for small ones).
 // SPLIT: tasks with lo != 0 write bf16 hi and lo planes instead of T.
@@ -70,9 +102,19 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
   const int count = tk->count;
   const uint32_t start = static_cast<uint32_t>(tk->start);
   const T sign = static_cast<T>(tk->sign);
-  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  const bool has_src = tk->src_buf >= 0;
-  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, has_src ? tk->src_buf : tk->dst_buf) + tk->src;
+  int32_t dim[kMaxDims], ss[kMaxDims], ds[kMaxDims];
+  uint32_t mag[kMaxDims], shr[kMaxDims];
+  load_divisors(tk, dim, mag, shr);
+#pragma unroll
+  for (int d = 0; d < kMaxDims; ++d) {
+    ss[d] = __builtin_amdgcn_readfirstlane(tk->ss[d]);
+    ds[d] = __builtin_amdgcn_readfirstlane(tk->ds[d]);
+  }
+  int sbuf, dbuf;
+  load_buf_ids(tk, &sbuf, &dbuf);
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, dbuf) + tk->dst;
+  const bool has_src = sbuf >= 0;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, has_src ? sbuf : dbuf) + tk->src;
   for (int e0 = 0; e0 < count; e0 += nthr * kBatch) {
     int32_t so[kBatch], dof[kBatch];
     T v[kBatch];
@@ -87,11 +129,11 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
       for (int d = 0; d < kMaxDims; ++d) {
         if (d < n) {
           // lin < 2^31: division by dim[d] as a multiply-high (host-side magic)
-          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
-          const uint32_t i = lin - q * static_cast<uint32_t>(tk->dim[d]);
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
+          const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
           lin = q;
-          a += static_cast<int32_t>(i) * tk->ss[d];
-          b += static_cast<int32_t>(i) * tk->ds[d];
+          a += static_cast<int32_t>(i) * ss[d];
+          b += static_cast<int32_t>(i) * ds[d];
         }
       }
       so[u] = a;
@@ -116,7 +158,7 @@ __device__ __forceinline__ void permute_task(const PermTask* __restrict__ tk, co
     }
     if (SPLIT && tk->lo != 0) {
       // the operand permute of a split-BF16x3 plan (alpha 1, beta 0)
-      TK_GLOBAL __bf16* hi = (TK_GLOBAL __bf16*)buf_ptr<void>(P, tk->dst_buf) + tk->dst;
+      TK_GLOBAL __bf16* hi = (TK_GLOBAL __bf16*)buf_ptr<void>(P, dbuf) + tk->dst;
 #pragma unroll
       for (int u = 0; u < kBatch; ++u) {
         const int e = e0 + u * nthr + lt;
@@ -203,8 +245,13 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
                                            const Ptrs& P, double alpha, double beta, int lt, int nthr) {
   const int n = tk->n, count = tk->count, c0 = tk->c0, c1 = tk->c1;
   const uint32_t start = static_cast<uint32_t>(tk->start);
-  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, tk->src_buf);
+  int sbuf, dbuf;
+  load_buf_ids(tk, &sbuf, &dbuf);
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, dbuf) + tk->dst;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, sbuf);
+  int32_t dim[kMaxDims];
+  uint32_t mag[kMaxDims], shr[kMaxDims];
+  load_divisors(tk, dim, mag, shr);
   for (int e = lt; e < count; e += nthr) {
     uint32_t lin = start + static_cast<uint32_t>(e);
     int32_t idx[kMaxDims];
@@ -213,8 +260,8 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
     for (int d = 0; d < kMaxDims; ++d) {
       idx[d] = 0;
       if (d < n) {
-        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
-        const uint32_t i = lin - q * static_cast<uint32_t>(tk->dim[d]);
+        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
+        const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
         lin = q;
         idx[d] = static_cast<int32_t>(i);
         dof += static_cast<int64_t>(i) * tk->ds[d];
@@ -264,13 +311,18 @@ __device__ __forceinline__ void gather_task(const TraceTask* __restrict__ tk, co
                                             const Ptrs& P, double alpha, double beta, int lt, int nthr) {
   const int n = tk->n, count = tk->count, c0 = tk->c0, c1 = tk->c1;
   const uint32_t start = static_cast<uint32_t>(tk->start);
-  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, tk->dst_buf) + tk->dst;
-  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, tk->src_buf);
+  int sbuf, dbuf;
+  load_buf_ids(tk, &sbuf, &dbuf);
+  TK_GLOBAL T* __restrict__ dst = buf_ptr<T>(P, dbuf) + tk->dst;
+  const TK_GLOBAL T* __restrict__ src = buf_ptr<const T>(P, sbuf);
   int32_t ss[kMaxDims] = {0, 0, 0, 0, 0, 0, 0, 0};  // the shared source strides (none without terms)
   if (c1 > c0) {
 #pragma unroll
     for (int d = 0; d < kMaxDims; ++d) ss[d] = cs[c0].ss[d];
   }
+  int32_t dim[kMaxDims];
+  uint32_t mag[kMaxDims], shr[kMaxDims];
+  load_divisors(tk, dim, mag, shr);
   for (int e0 = lt; e0 < count; e0 += kGatherUnroll * nthr) {
     int64_t dof[kGatherUnroll], rel[kGatherUnroll];
     double acc[kGatherUnroll];
@@ -284,8 +336,8 @@ __device__ __forceinline__ void gather_task(const TraceTask* __restrict__ tk, co
 #pragma unroll
       for (int d = 0; d < kMaxDims; ++d) {
         if (d < n) {
-          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * tk->mag[d]) >> tk->shr[d]);
-          const int64_t i = static_cast<int64_t>(lin - q * static_cast<uint32_t>(tk->dim[d]));
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
+          const int64_t i = static_cast<int64_t>(lin - q * static_cast<uint32_t>(dim[d]));
           lin = q;
           dof[u] += i * tk->ds[d];
           rel[u] += i * ss[d];
