@@ -1156,10 +1156,10 @@ std::vector<std::pair<int, int>> trace_exchanged_pairs(const Structure& A, const
   return r;
 }
 
-// output elements per trace task: small, so that a trace with few large
-// output blocks still spreads over every CU (each element gathers several
-// diagonal entries, so the kernel is latency- rather than bandwidth-bound)
-constexpr int64_t kTraceChunk = 512;
+// output elements per trace task: one pass of a 256-thread workgroup at 4
+// elements per thread, and small, so that a trace with few large output
+// blocks still spreads over every CU
+constexpr int64_t kTraceChunk = 1024;
 
 struct TracePlan {
   std::shared_ptr<Structure> A, C;

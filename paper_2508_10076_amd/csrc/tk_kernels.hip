@@ -236,13 +236,21 @@ __global__ __launch_bounds__(kThreads) void permute_tile_kernel(const TileTask* 
   }
 }
 
-// Partial trace: thread per output element; the element's index in the
-// block is split over the output dimensions once, then each contribution
-// adds coef * (sum along its traced diagonal), and the element is written
-// once (alpha times the trace plus beta times the old value).
+// Partial trace: each thread takes kTraceUnroll output elements at once;
+// their indices in the block are split over the output dimensions once, then
+// each contribution adds coef * (sum along its traced diagonal) -- the
+// diagonal walk is the same for every element of a task, so each of its
+// steps issues the loads of all the thread's elements before adding them
+// (a walk per element would wait one memory latency per diagonal entry) --
+// and each element is written once (alpha times the trace plus beta times
+// the old value).  Lanes past the task's end repeat its last element (loads
+// stay in bounds) and skip the store.
+constexpr int kTraceUnroll = 4;
+
 template <typename T>
 __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, const TraceContrib* __restrict__ cs,
                                            const Ptrs& P, double alpha, double beta, int lt, int nthr) {
+  constexpr int U = kTraceUnroll;
   const int n = tk->n, count = tk->count, c0 = tk->c0, c1 = tk->c1;
   const uint32_t start = static_cast<uint32_t>(tk->start);
   int sbuf, dbuf;
@@ -252,37 +260,53 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
   int32_t dim[kMaxDims];
   uint32_t mag[kMaxDims], shr[kMaxDims];
   load_divisors(tk, dim, mag, shr);
-  for (int e = lt; e < count; e += nthr) {
-    uint32_t lin = start + static_cast<uint32_t>(e);
-    int32_t idx[kMaxDims];
-    int64_t dof = 0;
+  for (int e0 = lt; e0 < count; e0 += U * nthr) {
+    int32_t idx[U][kMaxDims];
+    int64_t dof[U];
 #pragma unroll
-    for (int d = 0; d < kMaxDims; ++d) {
-      idx[d] = 0;
-      if (d < n) {
-        const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
-        const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
-        lin = q;
-        idx[d] = static_cast<int32_t>(i);
-        dof += static_cast<int64_t>(i) * tk->ds[d];
+    for (int u = 0; u < U; ++u) {
+      uint32_t lin = start + static_cast<uint32_t>(min(e0 + u * nthr, count - 1));
+      dof[u] = 0;
+#pragma unroll
+      for (int d = 0; d < kMaxDims; ++d) {
+        idx[u][d] = 0;
+        if (d < n) {
+          const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(lin) * mag[d]) >> shr[d]);
+          const uint32_t i = lin - q * static_cast<uint32_t>(dim[d]);
+          lin = q;
+          idx[u][d] = static_cast<int32_t>(i);
+          dof[u] += static_cast<int64_t>(i) * tk->ds[d];
+        }
       }
     }
-    double acc = 0.0;
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = 0.0;
     for (int c = c0; c < c1; ++c) {
       const TraceContrib* cb = cs + c;
-      int64_t base = cb->src;
+      int64_t base[U];
 #pragma unroll
-      for (int d = 0; d < kMaxDims; ++d)
-        if (d < n) base += static_cast<int64_t>(idx[d]) * cb->ss[d];
+      for (int u = 0; u < U; ++u) {
+        base[u] = cb->src;
+#pragma unroll
+        for (int d = 0; d < kMaxDims; ++d)
+          if (d < n) base[u] += static_cast<int64_t>(idx[u][d]) * cb->ss[d];
+      }
       const int nd = cb->nd;
       int32_t t[kMaxTracePairs] = {0, 0, 0, 0};
-      double sum = 0.0;
+      double sum[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sum[u] = 0.0;
       for (;;) {  // every diagonal index of the traced pairs, first pair fastest
-        int64_t o = base;
+        int64_t o = 0;
 #pragma unroll
         for (int j = 0; j < kMaxTracePairs; ++j)
           if (j < nd) o += static_cast<int64_t>(t[j]) * cb->dstr[j];
-        sum += static_cast<double>(src[o]);
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = static_cast<double>(src[base[u] + o]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) sum[u] += v[u];
         int j = 0;
         for (; j < nd; ++j) {
           if (++t[j] < cb->dd[j]) break;
@@ -290,11 +314,16 @@ __device__ __forceinline__ void trace_task(const TraceTask* __restrict__ tk, con
         }
         if (j == nd) break;
       }
-      acc += cb->coef * sum;
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[u] += cb->coef * sum[u];
     }
-    double v = alpha * acc;
-    if (beta != 0.0) v += beta * static_cast<double>(dst[dof]);
-    dst[dof] = static_cast<T>(v);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * nthr >= count) break;
+      double v = alpha * acc[u];
+      if (beta != 0.0) v += beta * static_cast<double>(dst[dof[u]]);
+      dst[dof[u]] = static_cast<T>(v);
+    }
   }
 }
 
