@@ -2416,8 +2416,9 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
             }
           continue;
         }
+        const int64_t task_rows = int64_t(tk::kThreads) * tk::smallk_rows_per_thread(static_cast<int>(K));
         for (int32_t i = 0; i < rg.n(); ++i)
-          for (int64_t r0 = 0; r0 < rg.size[i]; r0 += tk::kThreads)
+          for (int64_t r0 = 0; r0 < rg.size[i]; r0 += task_rows)
             for (int64_t n0 = 0, j = 0; n0 < N; n0 += kSkCols) {
               while (cg.off[j] + cg.size[j] <= n0) ++j;
               tk::SmallKTask t{};
@@ -2425,7 +2426,7 @@ std::unique_ptr<tk_plan> build_contract_plan(tk_context* ctx, const tk_tensor* A
               t.b = Bt.soff[sb];
               t.lda = d.M;
               t.ldb = d.K;
-              t.rows = static_cast<int32_t>(std::min<int64_t>(tk::kThreads, rg.size[i] - r0));
+              t.rows = static_cast<int32_t>(std::min<int64_t>(task_rows, rg.size[i] - r0));
               t.r0 = static_cast<int32_t>(r0);
               t.rchan = rbase + i;
               t.cchan = cbase + static_cast<int32_t>(j);

@@ -147,6 +147,10 @@ struct SkChan {
 // crosses channels in order).  Output element (row, column) goes to
 // pairs[pair + (column channel - cchan)]: base + sum of leg index x stride,
 // times the pair's sign.
+// Rows of A~ per thread of the row-stationary small-K kernel: several when K
+// is small, so that each thread has more loads in flight.
+constexpr int smallk_rows_per_thread(int K) { return K <= 2 ? 4 : K <= 4 ? 2 : 1; }
+
 struct SmallKTask {
   int64_t a;  // A~ element of the task's first row, column 0
   int64_t b;  // B~ element of row 0, column 0 of the sector

@@ -1451,9 +1451,11 @@ __device__ __forceinline__ double smallk_dot(const double* a, const double* b) {
 }
 
 // Sector GEMMs with K = KK <= 8 fixed at compile time: HBM-bound, no MFMA.
-// One workgroup per task (up to 256 rows of one row channel), one thread per
-// row: the row's KK values of A~ are loaded once (consecutive rows are
-// consecutive in A~, so the loads are coalesced), then the task's columns are
+// One workgroup per task (up to kThreads x smallk_rows_per_thread(KK) rows of
+// one row channel); thread t owns rows t, t + kThreads, ...: the KK values of
+// A~ of all its rows are loaded before any is used (consecutive rows are
+// consecutive in A~, so the loads are coalesced; several rows per thread
+// keep more loads in flight when KK is small), then the task's columns are
 // walked in order; B~ values, channel tables and pair descriptors are the
 // same for every lane (scalar loads), and each output is written from
 // registers (consecutive rows of a channel land at a stride of the output's
@@ -1466,36 +1468,51 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
                                                           const SkChan* __restrict__ chans,
                                                           const PairDesc* __restrict__ pairs, Ptrs P, double alpha,
                                                           double beta) {
+  constexpr int RT = smallk_rows_per_thread(KK);
   const SmallKTask tk = const_ptr(tasks)[blockIdx.x];
   const TK_CONST SkChan* ch = const_ptr(chans);
   const TK_CONST PairDesc* pr = const_ptr(pairs);
-  const int t = threadIdx.x;
-  const bool ok = t < tk.rows;
-  const int rr = ok ? t : tk.rows - 1;
-  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk.a_buf) + tk.a + rr;
+  const TK_GLOBAL T* __restrict__ A = buf_ptr<const T>(P, tk.a_buf) + tk.a;
   const TK_CONST T* Bc = const_ptr((const T*)(buf_ptr<const T>(P, tk.b_buf) + tk.b));
   TK_GLOBAL T* __restrict__ D = buf_ptr<T>(P, tk.dst_buf);
-  double a[KK];
+  bool ok[RT];
+  double a[RT][KK];
 #pragma unroll
-  for (int k = 0; k < KK; ++k) a[k] = static_cast<double>(A[static_cast<int64_t>(k) * tk.lda]);
-  // leg indices of this row inside its channel (colex, first leg fastest)
-  int ri[4] = {0, 0, 0, 0};
+  for (int q = 0; q < RT; ++q) {
+    const int row = threadIdx.x + q * kThreads;
+    ok[q] = row < tk.rows;
+    const int rr = ok[q] ? row : tk.rows - 1;
+#pragma unroll
+    for (int k = 0; k < KK; ++k) a[q][k] = static_cast<double>(A[rr + static_cast<int64_t>(k) * tk.lda]);
+  }
+  // leg indices of each row inside its channel (colex, first leg fastest)
+  int ri[RT][4];
   {
     const SkChan rc = ch[tk.rchan];
-    int rem = tk.r0 + rr;
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
-      if (l < tk.nrleg) {
-        ri[l] = rem % rc.dim[l];
-        rem /= rc.dim[l];
+    for (int q = 0; q < RT; ++q) {
+      const int row = threadIdx.x + q * kThreads;
+      int rem = tk.r0 + (ok[q] ? row : tk.rows - 1);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        ri[q][l] = 0;
+        if (l < tk.nrleg) {
+          ri[q][l] = rem % rc.dim[l];
+          rem /= rc.dim[l];
+        }
       }
+    }
   }
   int j = tk.cchan, pi = tk.pair;
   SkChan cc = ch[j];
   PairDesc pd = pr[pi];
-  int64_t rowpart = 0;
+  int64_t rowpart[RT];
 #pragma unroll
-  for (int l = 0; l < 4; ++l) rowpart += static_cast<int64_t>(ri[l]) * pd.S[l];
+  for (int q = 0; q < RT; ++q) {
+    rowpart[q] = 0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) rowpart[q] += static_cast<int64_t>(ri[q][l]) * pd.S[l];
+  }
   // column leg indices of the current column (colex counter, first leg
   // fastest), started at column c0 of channel cchan
   int ci[4] = {0, 0, 0, 0};
@@ -1516,12 +1533,14 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
       c = 0;
       cc = ch[j];
       pd = pr[pi];
-      rowpart = 0;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        rowpart += static_cast<int64_t>(ri[l]) * pd.S[l];
-        ci[l] = 0;
+      for (int q = 0; q < RT; ++q) {
+        rowpart[q] = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) rowpart[q] += static_cast<int64_t>(ri[q][l]) * pd.S[l];
       }
+#pragma unroll
+      for (int l = 0; l < 4; ++l) ci[l] = 0;
     }
     int64_t colpart = 0;
 #pragma unroll
@@ -1530,11 +1549,15 @@ __global__ __launch_bounds__(kThreads) void smallk_kernel(const SmallKTask* __re
     const int64_t bo = static_cast<int64_t>(tk.bcol + n) * tk.ldb;
 #pragma unroll
     for (int k = 0; k < KK; ++k) b[k] = static_cast<double>(Bc[bo + k]);
-    double v = alpha * static_cast<double>(pd.sign) * smallk_dot<MODE, KK>(a, b);
-    const int64_t x = pd.base + rowpart + colpart;
-    if (ok) {
-      if (beta != 0.0) v += beta * static_cast<double>(D[x]);
-      D[x] = static_cast<T>(v);
+    const double scale = alpha * static_cast<double>(pd.sign);
+#pragma unroll
+    for (int q = 0; q < RT; ++q) {
+      double v = scale * smallk_dot<MODE, KK>(a[q], b);
+      const int64_t x = pd.base + rowpart[q] + colpart;
+      if (ok[q]) {
+        if (beta != 0.0) v += beta * static_cast<double>(D[x]);
+        D[x] = static_cast<T>(v);
+      }
     }
     ++c;
 #pragma unroll
