@@ -187,7 +187,7 @@ struct GemmArgs {
   const LegMap* row_map;
   const LegMap* col_map;
   const PairDesc* pairs;
-  double* partials;          // split-K partial tiles (tile_m * tile_n each)
+  double* partials;          // split-K partial tiles (tile_m * tile_n each; fp32 values for fp32 accumulators)
   Ptrs ptrs;
   double alpha, beta;
 };

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "tk_internal.h"
 
@@ -1111,7 +1112,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
       const GemmDesc d = descs[tile.gemm];
       if (tile.nsplit > 1) {
         // partial tile of one K split: stored lane-major for the reduce kernel
-        double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
+        // stored in the accumulator's own type (fp32 accumulators: fp32
+        // partials, half the bytes; the reduce widens them exactly)
+        CT* mine = reinterpret_cast<CT*>(args.partials) + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -1119,7 +1122,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
 #pragma unroll
             for (int v = 0; v < 4; ++v)
               if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + GS * g + VS * v < d.N)
-                mine[((mi * TN + ni) * 4 + v) * NT + tid] = static_cast<double>(acc[mi][ni][v]);
+                mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
       } else {
         store_tile_t<TS, AT, TM, TN, VS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
                                          tile.n0 + wn + GS * g, acc);
@@ -1162,9 +1165,11 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const
     const int r = tile.m0 + wm + 16 * mi + (lane & 15);
     const int c = tile.n0 + wn + 16 * ni + (LAYOUT == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
     if (r >= d.M || c >= d.N) continue;
+    // partials in the accumulators' type: fp64 (LAYOUT 0) or fp32 (LAYOUT 2)
+    using PT = typename std::conditional<LAYOUT == 0, double, float>::type;
     double sum = 0.0;
-    const double* p = args.partials + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
-    for (int j = 0; j < tile.nsplit; ++j) sum += p[static_cast<int64_t>(j) * (BM * BN)];
+    const PT* p = reinterpret_cast<const PT*>(args.partials) + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
+    for (int j = 0; j < tile.nsplit; ++j) sum += static_cast<double>(p[static_cast<int64_t>(j) * (BM * BN)]);
     store_elem<TS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), r, c, sum);
   }
 }
@@ -1388,7 +1393,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs
       const GemmTile tile = tiles[ct];
       const GemmDesc d = descs[tile.gemm];
       if (tile.nsplit > 1) {
-        double* mine = args.partials + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
+        // fp32 partials (the accumulators' type; the reduce widens them exactly)
+        float* mine = reinterpret_cast<float*>(args.partials) + static_cast<int64_t>(tile.slot0 + tile.split) * (BM * BN);
 #pragma unroll
         for (int mi = 0; mi < TM; ++mi)
 #pragma unroll
@@ -1396,7 +1402,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs
 #pragma unroll
             for (int v = 0; v < 4; ++v)
               if (tile.m0 + wm + 16 * mi + l16 < d.M && tile.n0 + wn + 16 * ni + 4 * g + v < d.N)
-                mine[((mi * TN + ni) * 4 + v) * NT + tid] = static_cast<double>(acc[mi][ni][v]);
+                mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
       } else {
         store_tile_t<TS, f4_t, TM, TN, 1>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
                                           tile.n0 + wn + 4 * g, acc);
