@@ -800,13 +800,20 @@ __device__ __forceinline__ float buffer_load<float>(__amdgpu_buffer_rsrc_t r, ui
 
 // Epilogue of a tile held transposed: value v of acc[mi][ni] is
 // C[r0 + 16 mi][c0 + 16 ni + VS v] (r0, c0 already include the lane's row
-// and column).  Scatter outputs (mode 1) look up the row map once per row
-// and the column map once per column; the map and pair tables are read
-// through restrict pointers so their loads may move ahead of the stores.
+// and column); the wave's sub-tile spans rows rb .. rb + 16 TM - 1 and
+// columns cb .. cb + 16 TN - 1 (wave-uniform, before clipping to M x N).
+// Scatter outputs (mode 1): rows (columns) of a sector are numbered channel
+// by channel, so when the first and last valid row of the sub-tile share a
+// channel every row does, and likewise for columns.  Then one channel pair
+// covers the sub-tile: its placement is read once, through scalar loads, and
+// an element's offset is a row part (once per row) plus a column part (once
+// per column).  A sub-tile across channel boundaries looks up the pair of
+// every element.
 template <typename TS, typename AT, int TM, int TN, int VS>
 __device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL TS* __restrict__ C,
-                                             int r0, int c0, const AT (&acc)[TM][TN]) {
+                                             int r0, int c0, int rb, int cb, const AT (&acc)[TM][TN]) {
   const double alpha = args.alpha, beta = args.beta;
+  if (rb >= d.M || cb >= d.N) return;  // the whole sub-tile lies outside the sector
   if (d.mode == 0) {
 #pragma unroll
     for (int ni = 0; ni < TN; ++ni)
@@ -832,6 +839,44 @@ __device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDes
   LegMap rm[TM];
 #pragma unroll
   for (int mi = 0; mi < TM; ++mi) rm[mi] = rmap[min(r0 + 16 * mi, d.M - 1)];
+  const int rl = min(rb + 16 * TM, d.M) - 1, cl = min(cb + 16 * TN, d.N) - 1;
+  const TK_CONST LegMap* rmu = const_ptr(rmap);
+  const TK_CONST LegMap* cmu = const_ptr(cmap);
+  const int rc = rmu[rb].chan, cc = cmu[cb].chan;
+  if (rc == rmu[rl].chan && cc == cmu[cl].chan) {
+    const TK_CONST PairDesc* pu = const_ptr(pairs) + static_cast<int64_t>(rc) * d.ncc + cc;
+    const double scale = alpha * pu->sign;
+    int32_t S[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) S[l] = pu->S[l];
+    int64_t R[TM];
+#pragma unroll
+    for (int mi = 0; mi < TM; ++mi) {
+      R[mi] = pu->base;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) R[mi] += static_cast<int64_t>(rm[mi].idx[l]) * S[l];
+    }
+#pragma unroll
+    for (int ni = 0; ni < TN; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = c0 + 16 * ni + VS * v;
+        if (c >= d.N) continue;
+        const LegMap cm = cmap[c];
+        int64_t col = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) col += static_cast<int64_t>(cm.idx[l]) * S[4 + l];
+#pragma unroll
+        for (int mi = 0; mi < TM; ++mi) {
+          if (r0 + 16 * mi >= d.M) continue;
+          const int64_t x = R[mi] + col;
+          double val = scale * static_cast<double>(acc[mi][ni][v]);
+          if (beta != 0.0) val += beta * static_cast<double>(C[x]);
+          C[x] = static_cast<TS>(val);
+        }
+      }
+    return;
+  }
 #pragma unroll
   for (int ni = 0; ni < TN; ++ni)
 #pragma unroll
@@ -1125,7 +1170,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
                 mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
       } else {
         store_tile_t<TS, AT, TM, TN, VS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
-                                         tile.n0 + wn + GS * g, acc);
+                                         tile.n0 + wn + GS * g, uni(tile.m0 + wm), uni(tile.n0 + wn), acc);
       }
       // nothing left in flight (see the same wait in gemm_split3_kernel)
       __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -1405,7 +1450,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, 2) void gemm_split3_kernel(GemmArgs
                 mine[((mi * TN + ni) * 4 + v) * NT + tid] = acc[mi][ni][v];
       } else {
         store_tile_t<TS, f4_t, TM, TN, 1>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + l16,
-                                          tile.n0 + wn + 4 * g, acc);
+                                          tile.n0 + wn + 4 * g, __builtin_amdgcn_readfirstlane(tile.m0 + wm),
+                                          __builtin_amdgcn_readfirstlane(tile.n0 + wn), acc);
       }
       // The epilogue's table loads are done by now (the stage loads issued
       // before them are too: the counter is in order), but some of their
