@@ -830,25 +830,40 @@ __device__ __forceinline__ void store_tile_t(const GemmArgs& args, const GemmDes
 #pragma unroll
       for (int l = 0; l < 4; ++l) R[mi] += static_cast<int64_t>(rm[mi].idx[l]) * S[l];
     }
+    // The leg indices of the lane's columns (four packed 16-bit fields) are
+    // loaded a group of HG column bands at a time, before that group's
+    // stores: a load issued after a store waits for the store too (one
+    // in-order counter).  All bands at once where the registers allow.
+    constexpr int HG = TM * TN <= 4 ? TN : 1;
 #pragma unroll
-    for (int ni = 0; ni < TN; ++ni)
+    for (int n0 = 0; n0 < TN; n0 += HG) {
+      uint64_t cidx[HG][4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = c0 + 16 * ni + VS * v;
-        if (c >= d.N) continue;
-        const LegMap cm = cmap[c];
-        int64_t col = 0;
+      for (int h = 0; h < HG; ++h)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) col += static_cast<int64_t>(cm.idx[l]) * S[4 + l];
+        for (int v = 0; v < 4; ++v)
+          cidx[h][v] = *reinterpret_cast<const uint64_t*>(cmap[min(c0 + 16 * (n0 + h) + VS * v, d.N - 1)].idx);
 #pragma unroll
-        for (int mi = 0; mi < TM; ++mi) {
-          if (r0 + 16 * mi >= d.M) continue;
-          const int64_t x = R[mi] + col;
-          double val = scale * static_cast<double>(acc[mi][ni][v]);
-          if (beta != 0.0) val += beta * static_cast<double>(C[x]);
-          C[x] = static_cast<TS>(val);
+      for (int h = 0; h < HG; ++h)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ni = n0 + h;
+          const int c = c0 + 16 * ni + VS * v;
+          if (c >= d.N) continue;
+          int64_t col = 0;
+#pragma unroll
+          for (int l = 0; l < 4; ++l)
+            col += static_cast<int64_t>(static_cast<uint32_t>(cidx[h][v] >> (16 * l)) & 0xffffu) * S[4 + l];
+#pragma unroll
+          for (int mi = 0; mi < TM; ++mi) {
+            if (r0 + 16 * mi >= d.M) continue;
+            const int64_t x = R[mi] + col;
+            double val = scale * static_cast<double>(acc[mi][ni][v]);
+            if (beta != 0.0) val += beta * static_cast<double>(C[x]);
+            C[x] = static_cast<TS>(val);
+          }
         }
-      }
+    }
     return;
   }
 #pragma unroll
