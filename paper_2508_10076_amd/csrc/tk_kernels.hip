@@ -737,6 +737,32 @@ __global__ __launch_bounds__(kThreads) void zero_ranges_kernel(const ZeroRange* 
 // grouped sector GEMM, fp64 MFMA
 // ---------------------------------------------------------------------------
 
+// Epilogue store of one accumulated element of C~ (row r, column s of the
+// sector GEMM d): in place (mode 0) or scattered into C (mode 1).
+template <typename TC>
+__device__ __forceinline__ void store_elem(const GemmArgs& args, const GemmDesc& d, TK_GLOBAL TC* Cbase, int r,
+                                           int s, double acc) {
+  if (r >= d.M || s >= d.N) return;
+  int64_t idx;
+  double scale = args.alpha;
+  if (d.mode == 0) {
+    idx = d.c + static_cast<int64_t>(s) * d.ldc + r;
+  } else {
+    const LegMap rm = args.row_map[d.row_map + r];
+    const LegMap cm = args.col_map[d.col_map + s];
+    const PairDesc& pd = args.pairs[d.pair_base + static_cast<int64_t>(rm.chan) * d.ncc + cm.chan];
+    idx = pd.base;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      idx += static_cast<int64_t>(rm.idx[l]) * pd.S[l] + static_cast<int64_t>(cm.idx[l]) * pd.S[4 + l];
+    }
+    scale *= pd.sign;
+  }
+  double v = scale * acc;
+  if (args.beta != 0.0) v += args.beta * static_cast<double>(Cbase[idx]);
+  Cbase[idx] = static_cast<TC>(v);
+}
+
 // MFMA of one 16x16x4 step for the arithmetic type: accumulator type, the
 // call (first operand = B, so the result is the transposed tile), and where
 // value v of lane l sits: column GS (l/16) + VS v of the transposed tile.
@@ -1171,51 +1197,41 @@ __global__ __launch_bounds__(64 * WGM * WGN, (kF64WavesPerEu<BM, BN, BK_>)) void
 
 // Sum of the K-split partial tiles of the split groups, in split order (a
 // fixed order: the result does not depend on which unit finished first),
-// then the same epilogue as an unsplit tile.  Element q * NT + tid of a
-// partial tile is the accumulator value number q of GEMM thread tid.
+// then the same epilogue as an unsplit tile.  A flat stream over (group,
+// element) pairs: element e of a partial tile is the accumulator value the
+// GEMM thread e % NT held as its value number e / NT.
 // LAYOUT 0: fp64 arithmetic, transposed accumulators (row lane % 16,
 // column lane/16 + 4v); 2: fp32 accumulation (fp32 or split-BF16x3 MFMAs),
 // transposed (row lane % 16, column 4 (lane/16) + v).
 template <typename TS, int BM, int BN, int WGM, int WGN, int LAYOUT>
-__global__ __launch_bounds__(64 * WGM * WGN) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups) {
-  // one workgroup per split group, shaped like the GEMM's: thread tid sums
-  // the values it held in the GEMM over the splits (each partial tile is
-  // read coalesced, value by value) and runs the same epilogue
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GemmArgs args, const GemmTile* groups, int64_t total) {
   using TT = F64Tile<BM, BN, WGM, WGN>;
-  constexpr int NT = TT::NT, TM = TT::TM, TN = TT::TN;
-  constexpr int VS = LAYOUT == 0 ? 4 : 1, GS = LAYOUT == 0 ? 1 : 4;
-  using PT = typename std::conditional<LAYOUT == 0, double, float>::type;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const GemmTile tile = const_ptr(groups)[blockIdx.x];
-  const GemmDesc d = const_ptr(args.descs)[tile.gemm];
-  int wm, wn;
-  wave_origin<TT>(tid >> 6, &wm, &wn);
-  d4_t acc[TM][TN];
-#pragma unroll
-  for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < TN; ++ni) acc[mi][ni] = d4_t{0, 0, 0, 0};
-  const PT* p = reinterpret_cast<const PT*>(args.partials) + static_cast<int64_t>(tile.slot0) * (BM * BN) + tid;
-  for (int j = 0; j < tile.nsplit; ++j) {
-    // all values of one split first, then the sums (a fixed order per element)
-    PT part[TM][TN][4];
-#pragma unroll
-    for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) part[mi][ni][v] = p[((mi * TN + ni) * 4 + v) * NT];
-#pragma unroll
-    for (int mi = 0; mi < TM; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < TN; ++ni)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[mi][ni][v] += static_cast<double>(part[mi][ni][v]);
-    p += BM * BN;
+  constexpr int NT = TT::NT, TN = TT::TN;
+  static_assert((BM * BN) % 256 == 0, "a workgroup's elements must lie in one group");
+  for (int64_t x = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; x < total;
+       x += static_cast<int64_t>(gridDim.x) * 256) {
+    // a workgroup's 256 consecutive elements lie in one group (BM * BN is a
+    // multiple of 256), so the group and its tables are uniform: scalar loads
+    const int grp = __builtin_amdgcn_readfirstlane(static_cast<int>(x / (BM * BN)));
+    const int e = static_cast<int>(x % (BM * BN));
+    const int tid = e % NT, val = e / NT;
+    const int v = val & 3, t = val >> 2;
+    const int mi = t / TN, ni = t % TN;
+    const int lane = tid & 63, wave = tid >> 6;
+    const GemmTile tile = const_ptr(groups)[grp];
+    const GemmDesc d = const_ptr(args.descs)[tile.gemm];
+    int wm, wn;
+    wave_origin<TT>(wave, &wm, &wn);
+    const int r = tile.m0 + wm + 16 * mi + (lane & 15);
+    const int c = tile.n0 + wn + 16 * ni + (LAYOUT == 0 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+    if (r >= d.M || c >= d.N) continue;
+    // partials in the accumulators' type: fp64 (LAYOUT 0) or fp32 (LAYOUT 2)
+    using PT = typename std::conditional<LAYOUT == 0, double, float>::type;
+    double sum = 0.0;
+    const PT* p = reinterpret_cast<const PT*>(args.partials) + static_cast<int64_t>(tile.slot0) * (BM * BN) + e;
+    for (int j = 0; j < tile.nsplit; ++j) sum += static_cast<double>(p[static_cast<int64_t>(j) * (BM * BN)]);
+    store_elem<TS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), r, c, sum);
   }
-  store_tile_t<TS, d4_t, TM, TN, VS>(args, d, buf_ptr<TS>(args.ptrs, d.c_buf), tile.m0 + wm + (lane & 15),
-                                     tile.n0 + wn + GS * (lane >> 4), __builtin_amdgcn_readfirstlane(tile.m0 + wm),
-                                     __builtin_amdgcn_readfirstlane(tile.n0 + wn), acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -2173,10 +2189,12 @@ hipError_t launch_splitk_reduce(int dtype, int precision, int tile_m, int tile_n
                                 const GemmTile* groups, int ngroups, hipStream_t stream) {
   if (ngroups <= 0) return hipSuccess;
   if (!gemm_tile_supported(dtype, precision, tile_m, tile_n, tile_k)) return hipErrorInvalidValue;
+  const int64_t total = static_cast<int64_t>(ngroups) * tile_m * tile_n;
+  const unsigned nblk = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 65536));
   const int kind = compute_kind(dtype, precision);
-#define TK_RED_LAUNCH(TS_, L_, BM_, BN_, WM_, WN_)                                                                 \
-  hipLaunchKernelGGL((splitk_reduce_kernel<TS_, BM_, BN_, WM_, WN_, L_>), dim3(ngroups), dim3(64 * WM_ * WN_), 0, \
-                     stream, args, groups)
+#define TK_RED_LAUNCH(TS_, L_, BM_, BN_, WM_, WN_)                                                               \
+  hipLaunchKernelGGL((splitk_reduce_kernel<TS_, BM_, BN_, WM_, WN_, L_>), dim3(nblk), dim3(256), 0, stream, args, \
+                     groups, total)
 #define TK_RED_CASE(BM_, BN_, BK_, WM_, WN_)                                                   \
   if (tile_m == BM_ && tile_n == BN_ && tile_k == BK_) {                                       \
     if (dtype == 0 && kind == 0) {                                                             \
