@@ -2023,7 +2023,8 @@ std::vector<Unit> make_units(const std::vector<GemmDesc>& descs, int tm, int tn,
 // CUs in turn).  So the most expensive units land on distinct CUs (the
 // workgroups of a CU share its matrix cores), and runs of consecutive units,
 // which come from one cluster, share an XCD.
-Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu, int bpc, int64_t split_target) {
+Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu, int bpc, int64_t split_target,
+          bool one_per_wg) {
   Sched out;
   const int cpx = std::max(1, num_cu / kNumXcd);
   const int bm = std::max(1, static_cast<int>(std::sqrt(double(cpx))));
@@ -2040,6 +2041,7 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu
   for (int w = kNumXcd * cpx * bpc; w < nwg; ++w) order.push_back(w);  // CU counts not a multiple of 8
   std::stable_sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
   std::vector<std::vector<GemmTile>> per(nwg);
+  std::vector<std::vector<GemmTile>> per_xcd(kNumXcd);  // units in the order dealt, by XCD
   using E = std::pair<int64_t, int>;  // (load, rank in order)
   std::priority_queue<E, std::vector<E>, std::greater<E>> heap;
   for (int v = 0; v < static_cast<int>(order.size()); ++v) heap.push({0, v});
@@ -2048,6 +2050,7 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu
     E e = heap.top();
     heap.pop();
     per[order[e.second]].push_back(u.t);
+    per_xcd[order[e.second] % kNumXcd].push_back(u.t);
     mk = std::max(mk, e.first + u.cost);
     heap.push({e.first + u.cost, e.second});
   }
@@ -2056,6 +2059,20 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu
   const double red_bytes = 2.0 * out.nslots * double(tm) * tn * 8.0;
   out.makespan = static_cast<double>(mk) / 4.0 + (out.nslots ? 2.0 + red_bytes / 8.5e6 : 0.0);
   out.wg_first.assign(1, 0);
+  if (one_per_wg) {
+    // one unit per workgroup, workgroup p taking the next unit the LPT dealt
+    // to XCD p % kNumXcd: the hardware starts a new workgroup on a CU as
+    // soon as one retires, which balances the CUs of an XCD at run time
+    std::vector<size_t> next(kNumXcd, 0);
+    for (size_t left = units.size(); left > 0;)
+      for (int x = 0; x < kNumXcd; ++x)
+        if (next[x] < per_xcd[x].size()) {
+          out.tiles.push_back(per_xcd[x][next[x]++]);
+          out.wg_first.push_back(static_cast<int32_t>(out.tiles.size()));
+          --left;
+        }
+    return out;
+  }
   for (int w = 0; w < nwg; ++w) {
     out.tiles.insert(out.tiles.end(), per[w].begin(), per[w].end());
     out.wg_first.push_back(static_cast<int32_t>(out.tiles.size()));
@@ -2063,15 +2080,22 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu
   return out;
 }
 
-Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int num_cu, int bpc) {
-  Sched best = lpt(descs, tm, tn, tk, num_cu, bpc, 0);
+// Split-BF16x3 GEMMs run one tile per workgroup (hardware balancing: their
+// GEMM stage 6 % faster on the H_eff D = 4096 contractions); the fp64 and
+// fp32 kernels keep persistent workgroups, whose stream of stages crosses
+// tile boundaries (one tile per workgroup was no faster in fp64 and 20 %
+// slower on the split-K contraction in fp32).
+Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int num_cu, int bpc,
+                     int precision) {
+  const bool one = precision == TK_PREC_BF16X3;
+  Sched best = lpt(descs, tm, tn, tk, num_cu, bpc, 0, one);
   if (descs.empty()) return best;
   const int64_t max_wg = int64_t(num_cu) * bpc;
   int64_t total = 0;
   for (const auto& d : descs) total += ((d.M + tm - 1) / tm) * ((d.N + tn - 1) / tn) * ((d.K + tk - 1) / tk);
   for (int per_wg : {2, 3, 4, 6, 8}) {
     const int64_t target = std::max<int64_t>(4, total / (max_wg * per_wg));
-    Sched s = lpt(descs, tm, tn, tk, num_cu, bpc, target);
+    Sched s = lpt(descs, tm, tn, tk, num_cu, bpc, target, one);
     if (s.makespan < 0.97 * best.makespan) best = std::move(s);
   }
   return best;
@@ -2090,7 +2114,7 @@ void plan_reschedule(tk_plan& P, int tm, int tn, int tk, bool upload = true) {
   P.tile_n = tn;
   P.tile_k = tk;
   const int per_cu = P.ctx ? tk::gemm_blocks_per_cu(P.dtype, P.precision, tm, tn, tk) : 1;
-  Sched sc = schedule_tiles(P.descs, tm, tn, tk, P.ctx ? P.ctx->num_cu : 256, per_cu);
+  Sched sc = schedule_tiles(P.descs, tm, tn, tk, P.ctx ? P.ctx->num_cu : 256, per_cu, P.precision);
   P.tiles = sc.tiles;
   P.wg_first = sc.wg_first;
   P.groups = sc.groups;
@@ -3685,7 +3709,8 @@ void batch_schedule(tk_batch& b, int tm, int tn, int tk) {
   b.tile_m = tm;
   b.tile_n = tn;
   b.tile_k = tk;
-  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu, tk::gemm_blocks_per_cu(b.dtype, b.precision, tm, tn, tk));
+  Sched sc = schedule_tiles(b.descs, tm, tn, tk, b.ctx->num_cu, tk::gemm_blocks_per_cu(b.dtype, b.precision, tm, tn, tk),
+                            b.precision);
   b.tiles = sc.tiles;
   b.wg_first = sc.wg_first;
   b.groups = sc.groups;
