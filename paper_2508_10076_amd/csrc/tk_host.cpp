@@ -2080,11 +2080,12 @@ Sched lpt(const std::vector<GemmDesc>& descs, int tm, int tn, int BK, int num_cu
   return out;
 }
 
-// Split-BF16x3 GEMMs run one tile per workgroup (hardware balancing: their
-// GEMM stage 6 % faster on the H_eff D = 4096 contractions); the fp64 and
-// fp32 kernels keep persistent workgroups, whose stream of stages crosses
-// tile boundaries (one tile per workgroup was no faster in fp64 and 20 %
-// slower on the split-K contraction in fp32).
+// Split-BF16x3 GEMMs run one tile per workgroup: the hardware balancing
+// gains that kernel more than the prefetch across tile boundaries of a
+// persistent workgroup (its GEMM stage 5-6 % faster on the H_eff D = 4096
+// contractions).  The fp64 and fp32 kernels keep persistent workgroups (one
+// tile per workgroup was no faster in fp64 and 20 % slower on the split-K
+// contraction in fp32).
 Sched schedule_tiles(const std::vector<GemmDesc>& descs, int tm, int tn, int tk, int num_cu, int bpc,
                      int precision) {
   const bool one = precision == TK_PREC_BF16X3;
