@@ -188,6 +188,33 @@ def test_heff_plan_flops_match_expected_sizes():
     assert 4.0e8 < total < 4.8e8
 
 
+def test_split3_schedule_is_one_tile_per_workgroup():
+    """The grouped GEMM of a split-BF16x3 plan runs one tile per workgroup;
+    the fp64 plan of the same contraction, on the same tile shape, has the
+    same tiles and split-K groups dealt to persistent workgroups (at most one
+    per CU when planned without a device: 256)."""
+    cfg = synth.config2()
+    t = {k: lib_tensor(v) for k, v in cfg["tensors"].items()}
+    seen = 0
+    for out, a, b, call in cfg["calls"]:
+        args = (t[a], call["pA"], call["qA"], t[b], call["pB"], call["qB"], call["pAB"], call["qAB"])
+        Cn = tk.tensor_create_contracted(None, *args)
+        plans = {p: tk.Plan(None, *args, Cn, precision=p) for p in ("native", "bf16x3")}
+        for P in plans.values():
+            P.set_tile(64, 64, 32)
+        cn, cb = plans["native"].counts(), plans["bf16x3"].counts()
+        for k in ("tiles", "split_groups", "split_slots", "makespan_stages"):
+            assert cn[k] == cb[k], k
+        if cn["tiles"]:
+            seen += 1
+            assert cb["gemm_wgs"] == cb["tiles"]
+            assert 0 < cn["gemm_wgs"] <= min(cn["tiles"], 256)
+        for P in plans.values():
+            P.close()
+        t[out] = Cn
+    assert seen >= 2
+
+
 @pytest.mark.parametrize("sym", ["Z1", "Z2", "FZ2", "U1", "U1xFZ2"])
 def test_traced_spaces_match_oracle(sym):
     """tk_tensor_create_traced gives the spaces of the dense trace oracle
